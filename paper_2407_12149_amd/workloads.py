@@ -1,0 +1,176 @@
+"""Seeded synthetic inputs shared by the HIP path, the tests and the benchmark.
+
+This module only draws inputs (coefficient fields, sensor layouts, data,
+quantity-of-interest weights); it holds none of the sampler's arithmetic.
+
+Workloads follow the paper's experimental set-up (Sec. 5.1): unit square or
+cube, homogeneous Dirichlet data, interior-node unknowns, point observations
+averaged over small patches with diagonal noise covariance, and a linear
+quantity of interest averaged over a central region.
+"""
+import numpy as np
+
+# --------------------------------------------------------------------------
+# grid helpers
+# --------------------------------------------------------------------------
+
+
+def sites(n, dim):
+    return n ** dim
+
+
+def level_ns(n, levels):
+    out = [n]
+    for _ in range(levels - 1):
+        out.append((out[-1] - 1) // 2)
+    return out[::-1]  # coarsest first
+
+
+def face_midpoints(n, dim, k):
+    """Coordinates of the faces normal to axis k, in the layout of the face
+    arrays: axis k has n+1 entries (face between nodes f and f+1 sits at
+    (f + 1/2) h), the other axes n entries (node i at i h), x fastest."""
+    h = 1.0 / (n + 1)
+    axes = []
+    for j in range(dim):
+        if j == k:
+            axes.append((np.arange(n + 1) + 0.5) * h)
+        else:
+            axes.append(np.arange(1, n + 1) * h)
+    # meshgrid with x fastest: build in reversed axis order, C-order
+    grids = np.meshgrid(*axes[::-1], indexing="ij")
+    return [g for g in grids[::-1]]  # list x, y, (z), each shape (..., x)
+
+
+def face_array(n, dim, log_a):
+    """Concatenate a(x) = exp(log_a(x)) at the faces of every axis."""
+    parts = []
+    for k in range(dim):
+        xs = face_midpoints(n, dim, k)
+        parts.append(np.exp(log_a(*xs)).reshape(-1))
+    return np.concatenate(parts)
+
+
+# --------------------------------------------------------------------------
+# coefficient fields
+# --------------------------------------------------------------------------
+
+
+def fourier_log_field(dim, nmodes=64, amplitude=1.0, max_wave=4, seed=1):
+    """log a = amplitude sqrt(2/K) sum_k cos(2 pi w_k.x + phi_k), w_k uniform in
+    {-W..W}^d minus 0, phi_k uniform in [0, 2 pi): pointwise std = amplitude."""
+    rng = np.random.default_rng(seed)
+    waves = []
+    while len(waves) < nmodes:
+        w = rng.integers(-max_wave, max_wave + 1, size=dim)
+        if np.any(w != 0):
+            waves.append(w)
+    waves = np.array(waves, dtype=np.float64)
+    phases = rng.uniform(0.0, 2.0 * np.pi, size=nmodes)
+    c = amplitude * np.sqrt(2.0 / nmodes)
+
+    def log_a(*xs):
+        out = np.zeros_like(xs[0])
+        for w, ph in zip(waves, phases):
+            arg = ph + 2.0 * np.pi * sum(w[j] * xs[j] for j in range(dim))
+            out += np.cos(arg)
+        return c * out
+
+    return log_a
+
+
+def gaussian_log_field(dim, corr_len, variance, seed, nfeatures=1024):
+    """Random-Fourier-feature Gaussian field with squared-exponential
+    covariance variance * exp(-|r|^2 / (2 corr_len^2)):
+    log a = sqrt(2 variance / K) sum_k cos(omega_k.x + phi_k), omega ~ N(0, I/corr_len^2)."""
+    rng = np.random.default_rng(seed)
+    omega = rng.normal(0.0, 1.0 / corr_len, size=(nfeatures, dim))
+    phases = rng.uniform(0.0, 2.0 * np.pi, size=nfeatures)
+    c = np.sqrt(2.0 * variance / nfeatures)
+
+    def log_a(*xs):
+        out = np.zeros_like(xs[0])
+        for chunk in range(0, nfeatures, 64):
+            for w, ph in zip(omega[chunk:chunk + 64], phases[chunk:chunk + 64]):
+                out += np.cos(ph + sum(w[j] * xs[j] for j in range(dim)))
+        return c * out
+
+    return log_a
+
+
+# --------------------------------------------------------------------------
+# observations, data and quantity of interest
+# --------------------------------------------------------------------------
+
+
+def patch_sensors(n, dim, m, seed):
+    """m sensors, each the mean over the 3^dim nodes centred at a node drawn
+    uniformly without replacement among nodes at least 2 from the boundary.
+    Returns CSR over observations (ptr[m+1], fine site index, weight)."""
+    rng = np.random.default_rng(seed)
+    inner = n - 2  # centres i_k in 2..n-1
+    if inner < 1:
+        raise ValueError("grid too small for 3-point patches")
+    total = inner ** dim
+    if m > total:
+        raise ValueError("more sensors than admissible centres")
+    flat = rng.choice(total, size=m, replace=False)
+    ptr = np.zeros(m + 1, dtype=np.int64)
+    idx, val = [], []
+    w = 1.0 / 3 ** dim
+    for j, f in enumerate(flat):
+        c = []
+        for _ in range(dim):
+            c.append(2 + f % inner)
+            f //= inner
+        for t in range(3 ** dim):
+            rem, lin, mult = t, 0, 1
+            for k in range(dim):
+                off = rem % 3 - 1
+                rem //= 3
+                lin += (c[k] + off - 1) * mult
+                mult *= n
+            idx.append(lin)
+            val.append(w)
+        ptr[j + 1] = len(idx)
+    return ptr, np.array(idx, dtype=np.int32), np.array(val, dtype=np.float64)
+
+
+def observed_values(m, seed, low=1.0, high=4.0):
+    """Fixed observed values in [1, 4], as in the paper's posterior set-up."""
+    return np.random.default_rng(seed).uniform(low, high, size=m)
+
+
+def subcube_qoi(n, dim, lo=0.25, hi=0.75):
+    """F_i = 1/count on nodes with every coordinate in [lo, hi] (inclusive)."""
+    h = 1.0 / (n + 1)
+    x = np.arange(1, n + 1) * h
+    inside = (x >= lo - 1e-12) & (x <= hi + 1e-12)
+    mask = inside
+    for _ in range(dim - 1):
+        mask = np.multiply.outer(inside, mask)
+    F = mask.astype(np.float64).reshape(-1)
+    return F / F.sum()
+
+
+# --------------------------------------------------------------------------
+# the benchmark configurations
+# --------------------------------------------------------------------------
+
+
+def config(name):
+    """Problem description for a named workload (input recipe)."""
+    if name == "prior63":
+        n, dim = 63, 2
+        return dict(name=name, dim=dim, n=n, levels=4, kappa2=100.0, face_coef=None,
+                    obs=None, y=None, nchains=1, nsamples=2000, seed=0,
+                    F=subcube_qoi(n, dim))
+    if name == "posterior1023":
+        n, dim, m = 1023, 2, 64
+        face = face_array(n, dim, fourier_log_field(dim, nmodes=64, amplitude=1.0, seed=1))
+        ptr, idx, val = patch_sensors(n, dim, m, seed=2)
+        gamma = np.full(m, 0.01 ** 2)
+        return dict(name=name, dim=dim, n=n, levels=7, kappa2=100.0, face_coef=face,
+                    obs=(ptr, idx, val, gamma), y=observed_values(m, seed=3), nchains=8,
+                    nsamples=10000, seed=0, F=subcube_qoi(n, dim))
+    raise KeyError(name)

@@ -1,0 +1,291 @@
+"""Pins of the oracle's random smoother and MGMC update against exact
+identities and closed forms of the paper.
+
+* Smoother: deterministic part equals theta + Mt^{-1}(f - At theta) with
+  Mt = D + L + B Gamma^{-1} B^T (eq. M_lowrank_gibbs), and its noise has the
+  covariance that leaves N(At^{-1} f, At^{-1}) invariant:
+  J J^T = At^{-1} - S At^{-1} S^T, S = I - Mt^{-1} At (Sec. 3.3 eq.
+  low_rank_smoother_covariance; Appendix proposition on smoother noise).
+* One MGMC update is theta' = X theta + Y f + W with Y = (I - X) At^{-1} and
+  Cov(W) = At^{-1} - X At^{-1} X^T (Lemma MG-iteration-rep).
+* The symmetric V-cycle is At-self-adjoint, the noise-free chain is the
+  multigrid solver with a grid-independent rate (Lemma MGidentity-mean-cov,
+  Thm. equivalence, Prop. V-cycle-bound).
+* Chain statistics match the closed-form posterior mean and variance (eqs.
+  post-mean, post-cov) and the IACT closed form (eq. tau_int).
+"""
+import numpy as np
+import pytest
+from scipy import linalg
+
+import oracle
+from oracle import NOISE_IMPULSE, NOISE_ZERO
+from paper_2407_12149_amd import diagnostics, workloads
+
+
+def make(dim, n, levels, kappa2=10.0, beta=0, gamma=1e-3, seed=11, variable=True):
+    face = None
+    if variable:
+        rng = np.random.default_rng(seed)
+        per = (n + 1) * n ** (dim - 1)
+        face = np.exp(0.5 * rng.normal(size=dim * per))
+    o = oracle.Oracle(dim, n, levels, kappa2, face_coef=face, seed=seed)
+    if beta:
+        ptr, idx, val = workloads.patch_sensors(n, dim, beta, seed=seed + 1)
+        o.set_obs(ptr, idx, val, np.full(beta, gamma))
+    return o
+
+
+def colour_order_matrix(o, level):
+    """Permutation listing sites in forward sweep order (colours 0,3,1,2 in 2D,
+    0,3,5,6,1,2,4,7 in 3D; lexicographic within a colour)."""
+    col = o.dense(level, 7).astype(int)
+    order = [0, 3, 1, 2] if o.dim == 2 else [0, 3, 5, 6, 1, 2, 4, 7]
+    return np.concatenate([np.flatnonzero(col == c) for c in order])
+
+
+def smoother_matrix(o, level, direction):
+    """Mt = D + L (+ B Gamma^-1 B^T) with L the strictly lower part of A_l in
+    sweep order (forward) or its transpose (backward)."""
+    A = o.dense(level, 0)
+    perm = colour_order_matrix(o, level)
+    rank = np.empty_like(perm)
+    rank[perm] = np.arange(perm.size)
+    lower = rank[:, None] > rank[None, :]
+    if direction == 1:
+        lower = lower.T
+    M = np.diag(np.diag(A)) + np.where(lower, A, 0.0)
+    if o.beta:
+        M = M + (o.dense(level, 6) - A)
+    return M
+
+
+def maps_of(o, fn, N):
+    """Linear maps of a random update: X (state -> state, noise 0) and J
+    (noise -> state, state 0), built with zero and impulse noise."""
+    o.set_noise(NOISE_ZERO)
+    X = np.column_stack([fn(np.eye(N)[i]) for i in range(N)])
+    o.set_noise(NOISE_ZERO)
+    fn(np.zeros(N))
+    K = o.noise_drawn()
+    cols = []
+    for k in range(K):
+        o.set_noise(NOISE_IMPULSE, k)
+        cols.append(fn(np.zeros(N)))
+    o.set_noise(0)
+    return X, np.column_stack(cols)
+
+
+@pytest.mark.parametrize("dim,n,levels,beta", [(2, 7, 2, 0), (2, 15, 3, 3), (3, 7, 2, 2)])
+@pytest.mark.parametrize("direction", [0, 1])
+def test_smoother_splitting_and_noise(dim, n, levels, beta, direction):
+    o = make(dim, n, levels, beta=beta)
+    L = levels - 1
+    N = o.level_sites(L)
+    At = o.dense(L, 6)
+    Mt = smoother_matrix(o, L, direction)
+    X, J = maps_of(o, lambda t: o.smooth(L, direction, t), N)
+    S = np.eye(N) - np.linalg.solve(Mt, At)
+    assert np.allclose(X, S, atol=1e-12 * np.abs(S).max())
+    # deterministic part with a right-hand side: theta + Mt^{-1}(f - At theta)
+    rng = np.random.default_rng(5)
+    th, f = rng.normal(size=N), rng.normal(size=N)
+    o.set_noise(NOISE_ZERO)
+    got = o.smooth(L, direction, th, f)
+    want = th + np.linalg.solve(Mt, f - At @ th)
+    assert np.allclose(got, want, atol=1e-11 * np.abs(want).max())
+    # noise covariance: Mt^{-1}(Mt + Mt^T - At)Mt^{-T} = At^{-1} - S At^{-1} S^T
+    Ainv = np.linalg.inv(At)
+    cov = J @ J.T
+    assert np.abs(cov - (Ainv - S @ Ainv @ S.T)).max() <= 1e-11 * np.abs(Ainv).max()
+    D = np.diag(np.diag(o.dense(L, 0)))
+    noise_cov = D + (At - o.dense(L, 0))
+    assert np.allclose(Mt + Mt.T - At, noise_cov, atol=1e-12 * np.abs(At).max())
+    Minv = np.linalg.inv(Mt)
+    assert np.abs(cov - Minv @ noise_cov @ Minv.T).max() <= 1e-11 * np.abs(Ainv).max()
+
+
+def test_forward_and_backward_splittings_are_transposes():
+    o = make(2, 15, 3, beta=2)
+    M0 = smoother_matrix(o, 2, 0)
+    M1 = smoother_matrix(o, 2, 1)
+    assert np.allclose(M0.T, M1)
+
+
+CYCLE_CASES = [
+    (2, 7, 2, 0), (2, 15, 3, 0), (3, 7, 2, 0),
+    (2, 7, 2, 2), (2, 15, 3, 4), (3, 7, 2, 3),
+    (2, 15, 1, 0), (2, 7, 1, 2),
+]
+
+
+@pytest.mark.parametrize("dim,n,levels,beta", CYCLE_CASES)
+def test_cycle_covariance_identity(dim, n, levels, beta):
+    """Cov(W) = J J^T = At^{-1} - X At^{-1} X^T for one MGMC update, to round-off
+    (Lemma MG-iteration-rep, eq. noise-cov-id)."""
+    o = make(dim, n, levels, beta=beta)
+    o.set_rhs(None)
+    N = o.N
+    At = o.dense(levels - 1, 6)
+    Ainv = np.linalg.inv(At)
+    X, J = maps_of(o, lambda t: o.cycle(t), N)
+    err = np.abs(J @ J.T - (Ainv - X @ Ainv @ X.T)).max() / np.abs(Ainv).max()
+    assert err <= 1e-12
+    if levels == 1:  # exact Cholesky sampler: X = 0, Cov(W) = At^{-1}
+        assert np.abs(X).max() == 0.0
+    # symmetric V-cycle: X is At-self-adjoint, contraction below 1
+    assert np.allclose(At @ X, X.T @ At, atol=1e-11 * np.abs(At).max())
+    ev = linalg.eigvals(X)
+    assert np.abs(ev).max() < 0.5
+
+
+def test_cycle_mean_map():
+    """With zero noise theta' = X theta + (I - X) At^{-1} f (eq. def-Y-ell)."""
+    o = make(2, 15, 3, beta=3)
+    N = o.N
+    At = o.dense(2, 6)
+    o.set_rhs(None)
+    X, _ = maps_of(o, lambda t: o.cycle(t), N)
+    rng = np.random.default_rng(2)
+    f, th = rng.normal(size=N), rng.normal(size=N)
+    o.set_rhs(f)
+    o.set_noise(NOISE_ZERO)
+    got = o.cycle(th)
+    want = X @ th + (np.eye(N) - X) @ np.linalg.solve(At, f)
+    assert np.allclose(got, want, atol=1e-11 * np.abs(want).max())
+
+
+def test_any_full_rank_prolongation_keeps_the_target():
+    """Invariance holds for any full-rank P with Galerkin coarse operators
+    (Thm. on invariance, Sec. 3.1): user weights give an exact identity too."""
+    n, dim = 7, 2
+    w = np.zeros((9, 9))
+    for t in range(9):
+        dx, dy = t % 3 - 1, t // 3 - 1
+        w[:, t] = (0.5 if dx else 1.0) * (0.5 if dy else 1.0)
+    plain = oracle.Oracle(dim, n, 2, 10.0)
+    same = oracle.Oracle(dim, n, 2, 10.0, prolong_w=w)
+    assert np.array_equal(plain.dense(0, 0), same.dense(0, 0))
+    other = oracle.Oracle(dim, n, 2, 10.0, prolong_w=w * np.linspace(0.7, 1.3, 9)[None, :])
+    other.set_rhs(None)
+    Ainv = np.linalg.inv(other.dense(1, 6))
+    X, J = maps_of(other, lambda t: other.cycle(t), other.N)
+    assert np.abs(J @ J.T - (Ainv - X @ Ainv @ X.T)).max() <= 1e-12 * np.abs(Ainv).max()
+
+
+def test_planted_restriction_scale_is_detected():
+    """A textbook full-weighting restriction R = 2^-d P^T, planted in the
+    oracle, keeps the noise-free solver convergent but breaks the covariance
+    identity: the identity test is what pins R = P^T (Sec. 3.1)."""
+    o = make(2, 15, 3)
+    o.set_rhs(None)
+    Ainv = np.linalg.inv(o.dense(2, 6))
+    o.set_restriction_scale(0.25)
+    X, J = maps_of(o, lambda t: o.cycle(t), o.N)
+    assert np.abs(linalg.eigvals(X)).max() < 0.9
+    err = np.abs(J @ J.T - (Ainv - X @ Ainv @ X.T)).max() / np.abs(Ainv).max()
+    assert err > 1e-2
+
+
+def contraction_rate(dim, n, levels, kappa2, iters=12):
+    """Asymptotic error contraction of the noise-free chain with f = 0, from
+    the last step of a power iteration on a random start."""
+    o = oracle.Oracle(dim, n, levels, kappa2)
+    o.set_rhs(None)
+    o.set_noise(NOISE_ZERO)
+    rng = np.random.default_rng(0)
+    th = rng.normal(size=o.N)
+    ratios = []
+    for _ in range(iters):
+        nxt = o.cycle(th)
+        ratios.append(np.linalg.norm(nxt) / np.linalg.norm(th))
+        th = nxt / np.linalg.norm(nxt)
+    return ratios[-1]
+
+
+def test_noise_free_chain_is_multigrid_with_grid_independent_rate():
+    """Thm. equivalence / Prop. V-cycle-bound: the rate is bounded away from 1
+    uniformly in n.  The paper prints no value; measured: 2D 5-point 0.23-0.24
+    for n = 31..255, 3D 7-point 0.40 for n = 15..31."""
+    rates2 = [contraction_rate(2, n, int(np.log2(n + 1)) - 1, 100.0) for n in (31, 63, 127, 255)]
+    rates3 = [contraction_rate(3, n, int(np.log2(n + 1)) - 1, 1.0, iters=8) for n in (15, 31)]
+    assert max(rates2) < 0.3
+    assert max(rates3) < 0.45
+    for rates in (rates2, rates3):
+        assert max(rates) / min(rates) <= 1.1
+
+
+def test_noise_free_chain_converges_to_posterior_mean():
+    """With z = 0 the chain is E[theta^(m)] and converges to At^{-1} f_L with
+    f_L = B Gamma^{-1} y; the closed form is eq. post-mean."""
+    o = make(2, 15, 3, beta=4, gamma=1e-2)
+    y = workloads.observed_values(4, seed=1)
+    o.set_posterior_rhs(y)
+    o.set_noise(NOISE_ZERO)
+    th = np.zeros(o.N)
+    for m in range(40):
+        th = o.cycle(th, m=m)
+    A = o.dense(2, 0)
+    B = o.dense(2, 2)
+    Gam = np.diag(np.full(4, 1e-2))
+    Ainv_B = np.linalg.solve(A, B)
+    mu = Ainv_B @ np.linalg.solve(Gam + B.T @ Ainv_B, y)
+    assert np.allclose(th, mu, atol=1e-12 * np.abs(mu).max())
+
+
+def test_zero_observations_equal_prior_bitwise():
+    a = make(2, 15, 3)
+    b = make(2, 15, 3)
+    b.set_obs(np.zeros(1, dtype=np.int64), np.zeros(0, dtype=np.int32), np.zeros(0), np.zeros(0))
+    t0 = np.zeros(a.N)
+    ta, _, _ = a.chain(t0, 0, 5, chain=3)
+    tb, _, _ = b.chain(t0, 0, 5, chain=3)
+    assert np.array_equal(ta, tb)
+
+
+def test_chain_is_counter_based():
+    """A sample depends only on (seed, chain, m): chunked runs equal one run."""
+    o = make(2, 15, 3, beta=2)
+    t0 = np.zeros(o.N)
+    full, _, _ = o.chain(t0, 0, 6, chain=2)
+    half, _, _ = o.chain(t0, 0, 3, chain=2)
+    rest, _, _ = o.chain(half, 3, 3, chain=2)
+    assert np.array_equal(full, rest)
+    other, _, _ = o.chain(t0, 0, 6, chain=1)
+    assert not np.array_equal(full, other)
+
+
+def test_chain_statistics_match_closed_forms():
+    """z-tests of the QoI mean and variance against eqs. post-mean/post-cov,
+    with IACT-corrected standard errors, and the Wolff IACT estimate against
+    the closed form tau = 1 + 2 sum_s F^T X^s At^{-1} F / F^T At^{-1} F (eq. tau_int)."""
+    beta, gamma = 3, 1e-2
+    o = make(2, 15, 3, kappa2=4.0, beta=beta, gamma=gamma)
+    y = workloads.observed_values(beta, seed=8)
+    o.set_posterior_rhs(y)
+    N = o.N
+    A, B = o.dense(2, 0), o.dense(2, 2)
+    At = o.dense(2, 6)
+    Atinv = np.linalg.inv(At)
+    mu = np.linalg.solve(A, B) @ np.linalg.solve(np.diag(np.full(beta, gamma)) + B.T @ np.linalg.solve(A, B), y)
+    F = workloads.subcube_qoi(15, 2)
+    qmean, qvar = F @ mu, F @ Atinv @ F
+    nsamp = 20000
+    _, q, _ = o.chain(np.zeros(N), 0, nsamp, chain=0, F=F)
+    q = q[200:]
+    tau, dtau, _ = diagnostics.iact_wolff(q)
+    se_mean = np.sqrt(qvar * tau / q.size)
+    assert abs(q.mean() - qmean) / se_mean < 4.0
+    se_var = qvar * np.sqrt(2.0 * tau / q.size)
+    assert abs(q.var() - qvar) / se_var < 4.0
+    # closed-form IACT
+    o.set_rhs(None)
+    X, _ = maps_of(o, lambda t: o.cycle(t), N)
+    v = Atinv @ F
+    num, s = 0.0, v.copy()
+    for _ in range(200):
+        s = X @ s
+        num += F @ s
+    tau_inf = 1.0 + 2.0 * num / (F @ v)
+    assert abs(tau - tau_inf) <= 3.0 * dtau + 0.02
+    assert 1.0 <= tau_inf < 3.0
