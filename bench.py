@@ -1,0 +1,177 @@
+#!/usr/bin/env python3
+"""Benchmark: effective samples per second of the MGMC posterior sampler on
+one MI355X.
+
+Workload ``posterior1023``: 2D unit square, 1023 x 1023 interior nodes,
+A = h^2 (kappa^2 I - div(a grad)) with kappa = 10 and log a a 64-mode random
+Fourier field, 64 observations (3 x 3 patch means, Gamma = 1e-4 I, data in
+[1, 4]), 7-level V(1,1) cycles, 8 chains, FP64.  One step is one MGMC update
+of all 8 chains (sweeps, low-rank corrections, transfers, coarsest sample and
+the QoI reduction).  ESS/s = steps x chains / (tau x seconds) with tau the
+Wolff IACT of the QoI series of the timed steps.
+
+Prints one JSON line.  --gpus N with N > 1 is refused: this build runs on one
+GPU (chains would shard across GPUs without communication).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def sweep_bytes(n, dim, nchains, esz, faces_per_site):
+    """Algorithmic HBM bytes of one finest-level smoother sweep (all colours):
+    every chain state read and written once, the shared right-hand side read
+    once, and the operator (dim face coefficients + diagonal per site) read
+    once for all chains."""
+    N = n ** dim
+    return N * nchains * 2 * esz + N * esz + N * (faces_per_site + 1) * esz
+
+
+def cpu_baseline(cfg, seconds_target, tau):
+    """Time the CPU oracle on a bounded sample of the same workload: all 8
+    chains, one host thread per chain, as many updates as fit the target."""
+    import concurrent.futures as cf
+
+    import oracle
+
+    ptr, idx, val, gamma = cfg["obs"]
+    o = oracle.Oracle(2, cfg["n"], cfg["levels"], cfg["kappa2"], face_coef=cfg["face_coef"], seed=cfg["seed"])
+    o.set_obs(ptr, idx, val, gamma)
+    o.set_posterior_rhs(cfg["y"])
+    nch = cfg["nchains"]
+    N = cfg["n"] ** 2
+    # probe one update to size the sample
+    t0 = time.perf_counter()
+    o.chain(np.zeros(N), 0, 1, chain=0)
+    per = time.perf_counter() - t0
+    nsamp = max(2, int(seconds_target / max(per, 1e-6)))
+    threads = min(nch, os.cpu_count() or 1, 16)
+
+    def run(c):
+        return o.chain(np.zeros(N), 0, nsamp, chain=c)
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(run, range(nch)))
+    wall = time.perf_counter() - t0
+    return {
+        "value": nsamp * nch / (tau * wall),
+        "unit": "effective samples/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{nch} chains x {nsamp} updates of the same 1023^2 posterior workload "
+                  f"({wall:.1f} s wall), ESS with the GPU chains' IACT {tau:.3f}",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--profile-steps", type=int, default=100)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; chains shard across GPUs "
+                          "without communication but no multi-GPU path is built"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_2407_12149_amd import diagnostics, mgmc, workloads
+
+    torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", 0)))
+    log("[bench] generating workload posterior1023")
+    cfg = workloads.config("posterior1023")
+    n, dim, nch = cfg["n"], cfg["dim"], cfg["nchains"]
+    prob = dict(dim=dim, n=n, levels=cfg["levels"], kappa2=cfg["kappa2"], face_coef=cfg["face_coef"],
+                nchains=nch, seed=cfg["seed"], precision="fp64")
+    log("[bench] set-up")
+    t0 = time.perf_counter()
+    s = mgmc.Sampler(prob, obs=cfg["obs"])
+    setup_s = time.perf_counter() - t0
+    F = torch.tensor(cfg["F"], device="cuda")
+    y = cfg["y"]
+
+    log(f"[bench] warmup {args.warmup}")
+    s.set_graph(bool(args.graph))
+    s.posterior_sample(y, 0, args.warmup, F=F)
+    torch.cuda.synchronize()
+
+    log(f"[bench] timed {args.steps} steps")
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(s.stream)
+    q = s.posterior_sample(y, args.warmup, args.steps, F=F)
+    stop.record(s.stream)
+    torch.cuda.synchronize()
+    seconds = start.elapsed_time(stop) / 1e3
+    qs = q.cpu().numpy()
+    taus = [diagnostics.iact_wolff(qs[:, c])[0] for c in range(nch)]
+    tau = float(np.mean(taus))
+    value = args.steps * nch / (tau * seconds)
+
+    # kernel time of the finest-level sweeps, bracketed by HIP events on the
+    # sampler's stream during a further run of the same workload
+    log(f"[bench] kernel timing {args.profile_steps} steps")
+    s.set_graph(False)
+    s.set_profiling(True)
+    m1 = args.warmup + args.steps
+    s.posterior_sample(y, m1, args.profile_steps, F=F)
+    kms, launches = s.profile_read()
+    s.set_profiling(False)
+    per_launch_s = kms / 1e3 / max(launches, 1)
+    launches_per_sweep = launches / (2.0 * args.profile_steps)
+    bytes_sweep = sweep_bytes(n, dim, nch, 8, dim)
+    bytes_launch = bytes_sweep / launches_per_sweep
+    achieved = bytes_launch / per_launch_s / 1e9
+
+    result = {
+        "metric": "effective samples/s (plain MGMC posterior, FP64)",
+        "value": value,
+        "unit": "effective samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": seconds * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "posterior1023", "grid": "1023x1023", "levels": cfg["levels"],
+                   "chains": nch, "sensors": 64, "cycle": "V(1,1)", "graph": bool(args.graph)},
+        "iact": tau,
+        "setup_s": setup_s,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "kernel": "finest-level smoother sweep", "launches_per_sweep": launches_per_sweep,
+                     "avg_launch_us": per_launch_s * 1e6, "bytes_per_launch": bytes_launch},
+    }
+    s.close()
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline")
+        result["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds, tau)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

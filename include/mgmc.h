@@ -1,0 +1,154 @@
+/*
+ * mgmc.h -- C ABI of the MI355X Multigrid Monte Carlo sampler.
+ *
+ * The library draws a Markov chain theta^(0), theta^(1), ... whose law
+ * converges to the Gaussian N(At^{-1} f, At^{-1}) with precision
+ *   At = A + B Gamma^{-1} B^T
+ * (Kazashi, Mueller, Scheichl, arXiv 2407.12149: target of Sec. 5.1 eq.
+ * target_distribution, posterior covariance eq. post-cov).  Each update is one
+ * MGMC V-cycle theta^(m+1) = MGMC_L(At, f_L, theta^(m)) (Alg. 1, gamma = 1)
+ * with colour-ordered random Gauss-Seidel smoothing, the Woodbury low-rank
+ * correction of Alg. 3 (omega = 1) on every level when observations are
+ * given, Galerkin coarse operators (eq. galerkin_triple_product), transfers
+ * R = P^T (Sec. 3.1) and an exact Cholesky sample on the coarsest level
+ * (Sec. 3.4).
+ *
+ * A is the finite-difference operator of Sec. 5.1.1 in divergence form,
+ *   (A u)_i = s [kappa^2 u_i + h^-2 sum_k a_{i+e_k/2}(u_i - u_{i+e_k})
+ *                                     + a_{i-e_k/2}(u_i - u_{i-e_k})],
+ * on the n^dim interior nodes of the unit square/cube with u = 0 on the
+ * boundary, h = 1/(n+1), s the operator scale (default h^dim).
+ *
+ * Conventions shared by every call:
+ *   * Site vectors are lexicographic over interior nodes, x fastest:
+ *     index (i_1-1) + n (i_2-1) + n^2 (i_3-1), 1 <= i_k <= n.
+ *   * Chain states are stored chain-major: theta[c * N + i], N = n^dim.
+ *   * Noise is counter-based (Philox4x32-10 with Box-Muller, per site, per
+ *     sweep, per sample index m), so sample m of chain c depends only on
+ *     (seed, chain_offset + c, m, problem): runs can be split at any m.
+ *   * Every call after mgmc_setup is asynchronous on the HIP stream given at
+ *     setup; device pointers must stay valid until that stream reaches the
+ *     work.  mgmc_setup synchronises that stream before returning.
+ *   * Errors are reported by return code; mgmc_last_error() gives a
+ *     thread-local message for the last failing call of this thread.  On
+ *     MGMC_EINVAL nothing has been written.
+ *   * One context per host thread; contexts are independent.
+ */
+#ifndef MGMC_H
+#define MGMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mgmc_ctx mgmc_ctx; /* opaque, owned by the library */
+
+typedef enum {
+  MGMC_OK = 0,
+  MGMC_EINVAL = 1,      /* invalid argument (shape, NULL pointer, sign) */
+  MGMC_ENOMEM = 2,      /* host or device allocation failed */
+  MGMC_EDEVICE = 3,     /* a HIP call failed; message carries the HIP error */
+  MGMC_ENOTSPD = 4,     /* the coarsest matrix At_0 has no Cholesky factor */
+  MGMC_EUNSUPPORTED = 5,
+  MGMC_ESTATE = 6       /* call not valid in the context's state */
+} mgmc_status;
+
+typedef enum {
+  MGMC_FP64 = 0, /* sweeps, noise and state in FP64 */
+  MGMC_FP32 = 1  /* sweeps, noise and state in FP32; coarsest sample and
+                    low-rank terms in FP64 */
+} mgmc_precision;
+
+typedef struct {
+  int32_t dim;             /* 2 or 3 */
+  int32_t n;               /* interior nodes per dimension, n = 2^k - 1 */
+  int32_t levels;          /* 1 <= levels <= k; n_{l-1} = (n_l - 1)/2 */
+  int32_t nu1, nu2;        /* pre/post sweeps per level, >= 1, nu1 + nu2 <= 16 */
+  double kappa2;           /* kappa^2 of the shifted operator */
+  double scale;            /* operator scale s; <= 0 selects h^dim */
+  const double* face_coef; /* host; NULL means a = 1, else dim concatenated face
+                              arrays, array k with n+1 entries along axis k and
+                              n along the others, x fastest: entry f along
+                              axis k is a at the face between nodes f and f+1 */
+  const double* prolong_w; /* host; NULL means multilinear interpolation, else
+                              3^dim weights per coarse node J of the finest
+                              transfer (weight of fine node 2J + delta, delta in
+                              {-1,0,1}^dim, x fastest), coarse nodes
+                              lexicographic; coarser transfers stay multilinear */
+  int32_t precision;       /* mgmc_precision */
+  int32_t nchains;         /* >= 1 chains sharing the operator */
+  int64_t chain_offset;    /* chain c draws the noise of chain id chain_offset + c */
+  uint64_t seed;           /* the low 32 bits key the noise */
+} mgmc_problem;
+
+typedef struct {
+  int32_t beta;            /* number of observations, >= 1 */
+  const int64_t* ptr;      /* host, beta + 1 offsets into idx/val (CSR over observations) */
+  const int32_t* idx;      /* host, fine site index of each weight */
+  const double* val;       /* host, weights: column j of B_L (Sec. 2.3 eq. B_ell_definition) */
+  const double* gamma;     /* host, beta noise variances sigma_j^2 > 0 (Gamma diagonal) */
+} mgmc_obs;
+
+/* Build the hierarchy on the device: fine operator, Galerkin coarse operators
+ * A_{l-1} = P^T A_l P and B_{l-1} = P^T B_l (eq. A_ell_1_B_ell_1), the
+ * low-rank smoother matrices C = M^{-1} B, S = Gamma + B^T C, G = C S^{-1} for
+ * forward and backward sweeps on every level l >= 1 (Alg. 3), and the
+ * coarsest Cholesky factor of At_0.  obs = NULL gives the prior (B = 0).
+ * hip_stream: a hipStream_t (NULL = default stream) used by every later call.
+ * Host arrays are copied; the caller may free them on return.
+ * Errors: EINVAL (shape, levels, nu, NULL arrays, gamma <= 0, site index out
+ * of range), ENOTSPD, ENOMEM, EDEVICE. */
+mgmc_status mgmc_setup(const mgmc_problem* problem, const mgmc_obs* obs, void* hip_stream,
+                       mgmc_ctx** out);
+
+/* Run updates m0 .. m0+nsamples-1 of every chain for the target with
+ * right-hand side f_L = rhs (Alg. 1 with f_L given; rhs = NULL means f = 0,
+ * the prior N(0, At^{-1})).
+ *   theta: device, [nchains][N] in the context precision, in/out.
+ *   rhs:   device FP64 [N] or NULL.
+ *   F:     device FP64 [N] weights of the linear quantity of interest
+ *          q = F^T theta (Sec. 4 eq. F_matrix), or NULL.
+ *   qoi:   device FP64 [nsamples][nchains]: q after each update, or NULL
+ *          (both F and qoi, or neither).
+ * Errors: EINVAL (NULL theta/ctx, nsamples < 0, m0 < 0, F without qoi). */
+mgmc_status mgmc_sample(mgmc_ctx* ctx, int64_t m0, int64_t nsamples, void* theta,
+                        const double* rhs, const double* F, double* qoi);
+
+/* As mgmc_sample for the Bayesian posterior: f_L = B_L Gamma^{-1} y
+ * (Sec. 2.3 eq. f_ell_definition), recomputed when y changes.
+ *   y: host FP64 [beta] observed values.
+ * Errors: ESTATE if the context was set up without observations; otherwise
+ * as mgmc_sample. */
+mgmc_status mgmc_posterior_sample(mgmc_ctx* ctx, const double* y, int64_t m0, int64_t nsamples,
+                                  void* theta, const double* F, double* qoi);
+
+/* Number of levels and sites N_l = n_l^dim of level l (0 = coarsest);
+ * -1 for an invalid level. */
+int32_t mgmc_levels(const mgmc_ctx* ctx);
+int64_t mgmc_level_sites(const mgmc_ctx* ctx, int32_t level);
+
+/* Capture one update into a HIP graph and replay it per sample (1) or launch
+ * kernels one by one (0, default).  Results are identical either way. */
+mgmc_status mgmc_set_graph(mgmc_ctx* ctx, int32_t enabled);
+
+/* Kernel timing of the finest-level smoother sweeps (the hot loop of the
+ * update): when enabled, every launch of a finest-level sweep kernel is
+ * bracketed by a pair of HIP events on the context stream, in the
+ * one-by-one launch mode only.  mgmc_profile_read synchronises the stream
+ * and returns the summed kernel time in milliseconds and the number of
+ * launches timed since profiling was enabled. */
+mgmc_status mgmc_set_profiling(mgmc_ctx* ctx, int32_t enabled);
+mgmc_status mgmc_profile_read(mgmc_ctx* ctx, double* total_ms, int64_t* launches);
+
+/* Synchronise the context's stream and release everything it owns. */
+mgmc_status mgmc_destroy(mgmc_ctx* ctx);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* mgmc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

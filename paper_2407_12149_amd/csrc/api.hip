@@ -1,0 +1,593 @@
+// C ABI of the MGMC sampler: context set-up, device upload and the V-cycle
+// driver (Alg. 1 with gamma = 1, nu1 forward / nu2 backward smoothing steps).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hierarchy.h"
+#include "mgmc.h"
+#include "mgmc_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+mgmc_status fail(mgmc_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define MGMC_HIP(expr)                                                                  \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(MGMC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+inline int64_t host_pidx(const mgmc::Geom& g, const int* i, int dim) {
+  return int64_t(i[0] + 3) + int64_t(g.px) * (int64_t(i[1]) + int64_t(g.py) * (dim == 3 ? i[2] : 0));
+}
+
+inline int64_t padded_of(const mgmc::Geom& g, int dim, int64_t lin) {
+  int i[3] = {0, 0, 0};
+  for (int k = 0; k < dim; ++k) {
+    i[k] = 1 + int(lin % g.n);
+    lin /= g.n;
+  }
+  return host_pidx(g, i, dim);
+}
+
+}  // namespace
+
+struct mgmc_ctx {
+  mgmc_problem prob{};
+  hipStream_t stream = nullptr;
+  mgmc::Launch L;
+  int levels = 0, S = 9, beta = 0, qnb = 0;
+  size_t esz = 8;
+  std::vector<mgmc::DevLevel> lv;
+  double* KT = nullptr;
+  double* UinvT = nullptr;
+  double* gisq = nullptr;
+  double* ginv = nullptr;
+  double* xi = nullptr;
+  double* u = nullptr;
+  double* v = nullptr;
+  int64_t* mcur = nullptr;
+  double* qpart = nullptr;
+  void* fL = nullptr;  // padded finest right-hand side, shared by the chains
+  mgmc::HostHierarchy H;
+  std::vector<double> last_y;
+  bool posterior_ready = false;
+  bool use_graph = false;
+  std::vector<void*> allocs;
+  // profiling: a ring of event pairs around finest-level sweep launches
+  bool profiling = false;
+  bool capturing = false;
+  std::vector<hipEvent_t> ev_start, ev_stop;
+  std::vector<char> ev_pending;
+  size_t ev_next = 0;
+  double prof_ms = 0.0;
+  int64_t prof_launches = 0;
+
+  template <class T>
+  mgmc_status alloc(T*& p, size_t count) {
+    void* raw = nullptr;
+    const size_t bytes = count ? count * sizeof(T) : sizeof(T);
+    hipError_t e = hipMalloc(&raw, bytes);
+    if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? MGMC_ENOMEM : MGMC_EDEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
+    allocs.push_back(raw);
+    p = static_cast<T*>(raw);
+    MGMC_HIP(hipMemset(raw, 0, bytes));
+    return MGMC_OK;
+  }
+  mgmc_status alloc_bytes(void*& p, size_t bytes) {
+    char* c = nullptr;
+    mgmc_status s = alloc(c, bytes);
+    p = c;
+    return s;
+  }
+  template <class T>
+  mgmc_status upload(T*& p, const std::vector<T>& h) {
+    mgmc_status s = alloc(p, h.size());
+    if (s != MGMC_OK) return s;
+    if (!h.empty()) MGMC_HIP(hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    return MGMC_OK;
+  }
+  // Upload a double host vector converted to the context precision.
+  mgmc_status upload_real(void*& p, const std::vector<double>& h) {
+    if (L.fp32) {
+      std::vector<float> f(h.begin(), h.end());
+      float* d = nullptr;
+      mgmc_status s = upload(d, f);
+      p = d;
+      return s;
+    }
+    double* d = nullptr;
+    mgmc_status s = upload(d, h);
+    p = d;
+    return s;
+  }
+};
+
+namespace {
+
+mgmc_status validate(const mgmc_problem* p, const mgmc_obs* obs) {
+  if (!p) return fail(MGMC_EINVAL, "problem is NULL");
+  if (p->dim != 2 && p->dim != 3) return fail(MGMC_EINVAL, "dim must be 2 or 3");
+  if (p->n < 1 || ((p->n + 1) & p->n) != 0) return fail(MGMC_EINVAL, "n must be 2^k - 1");
+  int k = 0;
+  while ((1 << k) < p->n + 1) ++k;
+  if (p->levels < 1 || p->levels > k) return fail(MGMC_EINVAL, "levels must be in [1, log2(n+1)]");
+  if (p->nu1 < 1 || p->nu2 < 1 || p->nu1 + p->nu2 > 16) return fail(MGMC_EINVAL, "nu1, nu2 must be >= 1 with nu1 + nu2 <= 16");
+  if (p->nchains < 1 || p->nchains > 65535) return fail(MGMC_EINVAL, "nchains must be in [1, 65535]");
+  if (p->precision != MGMC_FP64 && p->precision != MGMC_FP32) return fail(MGMC_EINVAL, "unknown precision");
+  if (!(p->kappa2 == p->kappa2) || !(p->scale == p->scale)) return fail(MGMC_EINVAL, "kappa2/scale is NaN");
+  if (p->chain_offset < 0 || p->chain_offset + p->nchains > (int64_t(1) << 32)) return fail(MGMC_EINVAL, "chain ids must fit 32 bits");
+  const int n0 = ((p->n + 1) >> (p->levels - 1)) - 1;
+  int64_t N0 = 1, N = 1;
+  for (int d = 0; d < p->dim; ++d) {
+    N0 *= n0;
+    N *= p->n;
+  }
+  if (N0 > 4096) return fail(MGMC_EINVAL, "coarsest level has more than 4096 sites; use more levels");
+  if (N > (int64_t(1) << 31) - 1) return fail(MGMC_EINVAL, "grid too large");
+  if (p->face_coef) {
+    int64_t per = p->n + 1;
+    for (int d = 1; d < p->dim; ++d) per *= p->n;
+    for (int64_t e = 0; e < per * p->dim; ++e)
+      if (!(p->face_coef[e] > 0.0) || !std::isfinite(p->face_coef[e])) return fail(MGMC_EINVAL, "face coefficients must be positive and finite");
+  }
+  if (p->prolong_w) {
+    if (p->levels < 2) return fail(MGMC_EINVAL, "prolong_w needs at least two levels");
+    const int nc = (p->n - 1) / 2;
+    int64_t cnt = p->dim == 2 ? 9 : 27;
+    for (int d = 0; d < p->dim; ++d) cnt *= nc;
+    for (int64_t e = 0; e < cnt; ++e)
+      if (!std::isfinite(p->prolong_w[e]))
+        return fail(MGMC_EINVAL, "prolongation weights must be finite");
+  }
+  if (obs) {
+    if (obs->beta < 1 || obs->beta > 4096) return fail(MGMC_EINVAL, "beta must be in [1, 4096]");
+    if (!obs->ptr || !obs->idx || !obs->val || !obs->gamma) return fail(MGMC_EINVAL, "observation arrays must not be NULL");
+    if (obs->ptr[0] != 0) return fail(MGMC_EINVAL, "obs ptr[0] must be 0");
+    for (int j = 0; j < obs->beta; ++j) {
+      if (obs->ptr[j + 1] < obs->ptr[j]) return fail(MGMC_EINVAL, "obs ptr must be non-decreasing");
+      if (!(obs->gamma[j] > 0.0) || !std::isfinite(obs->gamma[j])) return fail(MGMC_EINVAL, "gamma must be positive and finite");
+      for (int64_t e = obs->ptr[j]; e < obs->ptr[j + 1]; ++e) {
+        if (obs->idx[e] < 0 || obs->idx[e] >= N) return fail(MGMC_EINVAL, "observation site out of range");
+        if (!std::isfinite(obs->val[e])) return fail(MGMC_EINVAL, "observation weight is NaN");
+      }
+    }
+  }
+  return MGMC_OK;
+}
+
+mgmc_status upload_level(mgmc_ctx* c, int l) {
+  const mgmc::HostHierarchy& H = c->H;
+  const mgmc::HostLevel& h = H.lv[l];
+  mgmc::DevLevel& d = c->lv[l];
+  const int dim = H.dim, S = H.S, nch = c->prob.nchains;
+  d.g = mgmc::make_geom(dim, h.n);
+  d.N = h.N;
+  d.cross = (l == H.L);
+  const int64_t Np = d.g.Np;
+  std::vector<int64_t> pad(h.N);
+  for (int64_t i = 0; i < h.N; ++i) pad[i] = padded_of(d.g, dim, i);
+  {
+    std::vector<double> coef(size_t(S) * Np, 0.0), invd(Np, 0.0), isqd(Np, 0.0);
+    const int centre = (S - 1) / 2;
+    for (int t = 0; t < S; ++t)
+      for (int64_t i = 0; i < h.N; ++i) coef[size_t(t) * Np + pad[i]] = h.st[size_t(t) * h.N + i];
+    for (int64_t i = 0; i < h.N; ++i) {
+      const double a = h.st[size_t(centre) * h.N + i];
+      invd[pad[i]] = 1.0 / a;
+      isqd[pad[i]] = 1.0 / std::sqrt(a);
+    }
+    mgmc_status s;
+    if ((s = c->upload_real(d.coef, coef)) != MGMC_OK) return s;
+    if ((s = c->upload_real(d.invd, invd)) != MGMC_OK) return s;
+    if ((s = c->upload_real(d.isqd, isqd)) != MGMC_OK) return s;
+  }
+  if (!h.wP.empty()) {
+    const mgmc::HostLevel& hc = H.lv[l - 1];
+    const mgmc::Geom gc = mgmc::make_geom(dim, hc.n);
+    std::vector<double> w(size_t(S) * gc.Np, 0.0);
+    for (int64_t J = 0; J < hc.N; ++J) {
+      const int64_t pj = padded_of(gc, dim, J);
+      for (int t = 0; t < S; ++t) w[size_t(t) * gc.Np + pj] = h.wP[size_t(J) * S + t];
+    }
+    mgmc_status s = c->upload(d.wP, w);
+    if (s != MGMC_OK) return s;
+  }
+  mgmc_status s = c->alloc_bytes(d.theta, size_t(nch) * Np * c->esz);
+  if (s != MGMC_OK) return s;
+  if (l < H.L) {
+    s = c->alloc_bytes(d.f, size_t(nch) * Np * c->esz);
+    if (s != MGMC_OK) return s;
+  }
+  if (H.beta > 0) {
+    const int beta = H.beta;
+    std::vector<int64_t> bptr(beta + 1, 0);
+    std::vector<int32_t> bidx;
+    std::vector<double> bval;
+    std::vector<std::vector<std::pair<int32_t, double>>> rows(h.N);
+    for (int j = 0; j < beta; ++j) {
+      for (const auto& [site, w] : h.Bcol[j]) {
+        bidx.push_back(int32_t(pad[site]));
+        bval.push_back(w);
+        rows[site].push_back({j, w});
+      }
+      bptr[j + 1] = int64_t(bidx.size());
+    }
+    if ((s = c->upload(d.bptr, bptr)) != MGMC_OK) return s;
+    if ((s = c->upload(d.bidx, bidx)) != MGMC_OK) return s;
+    if ((s = c->upload(d.bval, bval)) != MGMC_OK) return s;
+    std::vector<int32_t> brow, brcol;
+    std::vector<int64_t> brptr(1, 0);
+    std::vector<double> brval;
+    for (int64_t i = 0; i < h.N; ++i) {
+      if (rows[i].empty()) continue;
+      brow.push_back(int32_t(pad[i]));
+      for (const auto& [j, w] : rows[i]) {
+        brcol.push_back(j);
+        brval.push_back(w);
+      }
+      brptr.push_back(int64_t(brcol.size()));
+    }
+    d.nbrows = int32_t(brow.size());
+    if ((s = c->upload(d.brow, brow)) != MGMC_OK) return s;
+    if ((s = c->upload(d.brptr, brptr)) != MGMC_OK) return s;
+    if ((s = c->upload(d.brcol, brcol)) != MGMC_OK) return s;
+    if ((s = c->upload(d.brval, brval)) != MGMC_OK) return s;
+    if (l >= 1) {
+      for (int dir = 0; dir < 2; ++dir) {
+        const int64_t ns = int64_t(h.supp[dir].size());
+        d.nsupp[dir] = int32_t(ns);
+        std::vector<int32_t> supp(ns);
+        std::vector<double> CT(size_t(beta) * ns), GT(size_t(beta) * ns);
+        for (int64_t r = 0; r < ns; ++r) {
+          supp[r] = int32_t(pad[h.supp[dir][r]]);
+          for (int j = 0; j < beta; ++j) {
+            CT[size_t(j) * ns + r] = h.C[dir][size_t(r) * beta + j];
+            GT[size_t(j) * ns + r] = h.G[dir][size_t(r) * beta + j];
+          }
+        }
+        if ((s = c->upload(d.supp[dir], supp)) != MGMC_OK) return s;
+        if ((s = c->upload(d.CT[dir], CT)) != MGMC_OK) return s;
+        if ((s = c->upload(d.GT[dir], GT)) != MGMC_OK) return s;
+        if ((s = c->upload(d.SmG[dir], h.SmG[dir])) != MGMC_OK) return s;
+      }
+    }
+  }
+  return MGMC_OK;
+}
+
+// Collect the elapsed time of ring slot k (blocks until its stop event fired).
+mgmc_status drain_slot(mgmc_ctx* c, size_t k) {
+  if (!c->ev_pending[k]) return MGMC_OK;
+  MGMC_HIP(hipEventSynchronize(c->ev_stop[k]));
+  float ms = 0.f;
+  MGMC_HIP(hipEventElapsedTime(&ms, c->ev_start[k], c->ev_stop[k]));
+  c->prof_ms += ms;
+  c->prof_launches += 1;
+  c->ev_pending[k] = 0;
+  return MGMC_OK;
+}
+
+// Launch `body` bracketed by events when profiling the finest level.
+template <class F>
+mgmc_status timed(mgmc_ctx* c, bool finest, F&& body) {
+  const bool on = c->profiling && finest && !c->capturing;
+  size_t k = 0;
+  if (on) {
+    k = c->ev_next;
+    c->ev_next = (c->ev_next + 1) % c->ev_start.size();
+    mgmc_status s = drain_slot(c, k);
+    if (s != MGMC_OK) return s;
+    MGMC_HIP(hipEventRecord(c->ev_start[k], c->stream));
+  }
+  hipError_t e = body();
+  if (e != hipSuccess) return fail(MGMC_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+  if (on) {
+    MGMC_HIP(hipEventRecord(c->ev_stop[k], c->stream));
+    c->ev_pending[k] = 1;
+  }
+  return MGMC_OK;
+}
+
+#define MGMC_LAUNCH(expr)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) return fail(MGMC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// One MGMC update of every chain (Alg. 1), enqueued on the context stream.
+mgmc_status enqueue_cycle(mgmc_ctx* c, const void* fL, const double* F, double* qoi, int64_t m0) {
+  const mgmc::Launch& L = c->L;
+  const int top = c->levels - 1, nq = 1 << c->prob.dim, beta = c->beta;
+  const int nch = c->prob.nchains;
+  if (top == 0) {
+    MGMC_LAUNCH(mgmc::launch_coarsest(L, c->lv[0], fL, 0, c->lv[0].theta, c->KT, c->UinvT));
+  } else {
+    for (int l = top; l >= 1; --l) {
+      mgmc::DevLevel& lv = c->lv[l];
+      const void* f = (l == top) ? fL : lv.f;
+      const int64_t fcs = (l == top) ? 0 : lv.g.Np;
+      if (l < top) MGMC_LAUNCH(mgmc::launch_fill_zero(L, lv.theta, int64_t(nch) * lv.g.Np));
+      for (int j = 0; j < c->prob.nu1; ++j) {
+        const uint32_t word = mgmc::noise_word(l, j);
+        for (int q = 0; q < nq; ++q) {
+          mgmc_status st = timed(c, l == top, [&] {
+            return mgmc::launch_sweep_colour(L, lv, f, fcs, word, mgmc::forward_colour(c->prob.dim, q));
+          });
+          if (st != MGMC_OK) return st;
+        }
+        if (beta) MGMC_LAUNCH(mgmc::launch_lowrank(L, lv, 0, word, beta, c->gisq, c->xi, c->u));
+      }
+      MGMC_LAUNCH(mgmc::launch_restrict(L, lv, c->lv[l - 1], f, fcs));
+      if (beta) {
+        MGMC_LAUNCH(mgmc::launch_gather_v(L, lv, beta, c->ginv, c->v));
+        MGMC_LAUNCH(mgmc::launch_coarse_rhs_lowrank(L, c->lv[l - 1], c->v, beta));
+      }
+    }
+    MGMC_LAUNCH(mgmc::launch_coarsest(L, c->lv[0], c->lv[0].f, c->lv[0].g.Np, c->lv[0].theta, c->KT, c->UinvT));
+    for (int l = 1; l <= top; ++l) {
+      mgmc::DevLevel& lv = c->lv[l];
+      const void* f = (l == top) ? fL : lv.f;
+      const int64_t fcs = (l == top) ? 0 : lv.g.Np;
+      MGMC_LAUNCH(mgmc::launch_prolong(L, lv, c->lv[l - 1]));
+      for (int j = 0; j < c->prob.nu2; ++j) {
+        const uint32_t word = mgmc::noise_word(l, c->prob.nu1 + j);
+        for (int q = nq - 1; q >= 0; --q) {
+          mgmc_status st = timed(c, l == top, [&] {
+            return mgmc::launch_sweep_colour(L, lv, f, fcs, word, mgmc::forward_colour(c->prob.dim, q));
+          });
+          if (st != MGMC_OK) return st;
+        }
+        if (beta) MGMC_LAUNCH(mgmc::launch_lowrank(L, lv, 1, word, beta, c->gisq, c->xi, c->u));
+      }
+    }
+  }
+  if (qoi) MGMC_LAUNCH(mgmc::launch_qoi(L, c->lv[top], c->lv[top].theta, F, c->qpart, c->qnb, qoi, m0));
+  MGMC_LAUNCH(mgmc::launch_advance_m(c->stream, c->mcur));
+  return MGMC_OK;
+}
+
+mgmc_status run_samples(mgmc_ctx* c, const void* fL, int64_t m0, int64_t nsamples, void* theta,
+                        const double* F, double* qoi) {
+  const int top = c->levels - 1;
+  MGMC_LAUNCH(mgmc::launch_unpack(c->L, c->lv[top], theta, c->lv[top].theta));
+  MGMC_LAUNCH(mgmc::launch_set_m(c->stream, c->mcur, m0));
+  if (c->use_graph && c->stream != nullptr && nsamples > 1) {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    MGMC_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    c->capturing = true;
+    mgmc_status s = enqueue_cycle(c, fL, F, qoi, m0);
+    c->capturing = false;
+    hipError_t e = hipStreamEndCapture(c->stream, &graph);
+    if (s != MGMC_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return s;
+    }
+    if (e != hipSuccess) return fail(MGMC_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return fail(MGMC_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    for (int64_t k = 0; k < nsamples && e == hipSuccess; ++k) e = hipGraphLaunch(exec, c->stream);
+    // the launches are enqueued; destroying the executable graph is deferred by the runtime
+    hipError_t e2 = hipStreamSynchronize(c->stream);
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(MGMC_EDEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+    if (e2 != hipSuccess) return fail(MGMC_EDEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e2));
+  } else {
+    for (int64_t k = 0; k < nsamples; ++k) {
+      mgmc_status s = enqueue_cycle(c, fL, F, qoi, m0);
+      if (s != MGMC_OK) return s;
+    }
+  }
+  MGMC_LAUNCH(mgmc::launch_pack(c->L, c->lv[top], c->lv[top].theta, theta));
+  return MGMC_OK;
+}
+
+mgmc_status check_run_args(mgmc_ctx* c, int64_t m0, int64_t nsamples, void* theta, const double* F,
+                           double* qoi) {
+  if (!c) return fail(MGMC_EINVAL, "context is NULL");
+  if (!theta) return fail(MGMC_EINVAL, "theta is NULL");
+  if (nsamples < 0 || m0 < 0) return fail(MGMC_EINVAL, "m0 and nsamples must be >= 0");
+  if (m0 + nsamples > (int64_t(1) << 32)) return fail(MGMC_EINVAL, "sample index exceeds 32 bits");
+  if ((F == nullptr) != (qoi == nullptr)) return fail(MGMC_EINVAL, "F and qoi must be given together");
+  return MGMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mgmc_status mgmc_setup(const mgmc_problem* problem, const mgmc_obs* obs, void* hip_stream,
+                       mgmc_ctx** out) {
+  g_err.clear();
+  if (!out) return fail(MGMC_EINVAL, "out is NULL");
+  *out = nullptr;
+  mgmc_status s = validate(problem, obs);
+  if (s != MGMC_OK) return s;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(MGMC_EDEVICE, "no HIP device available");
+  mgmc_ctx* c = new (std::nothrow) mgmc_ctx();
+  if (!c) return fail(MGMC_ENOMEM, "host allocation failed");
+  c->prob = *problem;
+  c->prob.face_coef = nullptr;
+  c->prob.prolong_w = nullptr;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->levels = problem->levels;
+  c->S = problem->dim == 2 ? 9 : 27;
+  c->esz = problem->precision == MGMC_FP32 ? 4 : 8;
+  c->L.stream = c->stream;
+  c->L.dim = problem->dim;
+  c->L.fp32 = problem->precision == MGMC_FP32;
+  c->L.nchains = problem->nchains;
+  c->L.seed = uint32_t(problem->seed);
+  c->L.chain0 = uint32_t(problem->chain_offset);
+  std::string err;
+  s = mgmc::build_hierarchy(*problem, obs, c->H, err);
+  if (s != MGMC_OK) {
+    delete c;
+    return fail(s, err);
+  }
+  c->beta = c->H.beta;
+  c->lv.assign(c->levels, mgmc::DevLevel{});
+  auto cleanup = [&](mgmc_status st) {
+    mgmc_destroy(c);
+    return st;
+  };
+  for (int l = 0; l < c->levels; ++l)
+    if ((s = upload_level(c, l)) != MGMC_OK) return cleanup(s);
+  if ((s = c->upload(c->KT, c->H.KT)) != MGMC_OK) return cleanup(s);
+  if ((s = c->upload(c->UinvT, c->H.UinvT)) != MGMC_OK) return cleanup(s);
+  if ((s = c->alloc(c->mcur, 1)) != MGMC_OK) return cleanup(s);
+  const int top = c->levels - 1;
+  c->qnb = int(std::min<int64_t>(256, (c->lv[top].N + 4095) / 4096));
+  if (c->qnb < 1) c->qnb = 1;
+  if ((s = c->alloc(c->qpart, size_t(c->qnb) * problem->nchains)) != MGMC_OK) return cleanup(s);
+  if ((s = c->alloc_bytes(c->fL, size_t(c->lv[top].g.Np) * c->esz)) != MGMC_OK) return cleanup(s);
+  if (c->beta > 0) {
+    std::vector<double> gisq(c->beta), ginv(c->beta);
+    for (int j = 0; j < c->beta; ++j) {
+      gisq[j] = 1.0 / std::sqrt(c->H.gamma[j]);
+      ginv[j] = 1.0 / c->H.gamma[j];
+    }
+    if ((s = c->upload(c->gisq, gisq)) != MGMC_OK) return cleanup(s);
+    if ((s = c->upload(c->ginv, ginv)) != MGMC_OK) return cleanup(s);
+    const size_t bc = size_t(c->beta) * problem->nchains;
+    if ((s = c->alloc(c->xi, bc)) != MGMC_OK) return cleanup(s);
+    if ((s = c->alloc(c->u, bc)) != MGMC_OK) return cleanup(s);
+    if ((s = c->alloc(c->v, bc)) != MGMC_OK) return cleanup(s);
+  }
+  // keep only what later calls need on the host: the observation columns
+  for (int l = 0; l < c->levels; ++l) {
+    mgmc::HostLevel& h = c->H.lv[l];
+    std::vector<double>().swap(h.st);
+    for (int d = 0; d < 2; ++d) {
+      std::vector<double>().swap(h.C[d]);
+      std::vector<double>().swap(h.G[d]);
+    }
+    if (l < top) std::vector<std::vector<std::pair<int64_t, double>>>().swap(h.Bcol);
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+    return cleanup(fail(MGMC_EDEVICE, "synchronisation after set-up failed"));
+  *out = c;
+  return MGMC_OK;
+}
+
+mgmc_status mgmc_sample(mgmc_ctx* c, int64_t m0, int64_t nsamples, void* theta, const double* rhs,
+                        const double* F, double* qoi) {
+  g_err.clear();
+  mgmc_status s = check_run_args(c, m0, nsamples, theta, F, qoi);
+  if (s != MGMC_OK) return s;
+  const void* fL = nullptr;
+  if (rhs) {
+    MGMC_LAUNCH(mgmc::launch_unpack_rhs(c->L, c->lv[c->levels - 1], rhs, c->fL));
+    fL = c->fL;
+  }
+  c->posterior_ready = false;
+  return run_samples(c, fL, m0, nsamples, theta, F, qoi);
+}
+
+mgmc_status mgmc_posterior_sample(mgmc_ctx* c, const double* y, int64_t m0, int64_t nsamples,
+                                  void* theta, const double* F, double* qoi) {
+  g_err.clear();
+  mgmc_status s = check_run_args(c, m0, nsamples, theta, F, qoi);
+  if (s != MGMC_OK) return s;
+  if (c->beta == 0) return fail(MGMC_ESTATE, "context was set up without observations");
+  if (!y) return fail(MGMC_EINVAL, "y is NULL");
+  for (int j = 0; j < c->beta; ++j)
+    if (!std::isfinite(y[j])) return fail(MGMC_EINVAL, "y must be finite");
+  const bool same = c->posterior_ready && std::equal(c->last_y.begin(), c->last_y.end(), y);
+  if (!same) {
+    const int top = c->levels - 1;
+    std::vector<double> f = mgmc::posterior_rhs(c->H, y);
+    const mgmc::Geom& g = c->lv[top].g;
+    std::vector<double> padded(g.Np, 0.0);
+    for (int64_t i = 0; i < c->lv[top].N; ++i) padded[padded_of(g, c->prob.dim, i)] = f[i];
+    MGMC_HIP(hipStreamSynchronize(c->stream));
+    if (c->L.fp32) {
+      std::vector<float> pf(padded.begin(), padded.end());
+      MGMC_HIP(hipMemcpy(c->fL, pf.data(), pf.size() * sizeof(float), hipMemcpyHostToDevice));
+    } else {
+      MGMC_HIP(hipMemcpy(c->fL, padded.data(), padded.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    c->last_y.assign(y, y + c->beta);
+    c->posterior_ready = true;
+  }
+  return run_samples(c, c->fL, m0, nsamples, theta, F, qoi);
+}
+
+int32_t mgmc_levels(const mgmc_ctx* c) { return c ? c->levels : -1; }
+
+int64_t mgmc_level_sites(const mgmc_ctx* c, int32_t level) {
+  if (!c || level < 0 || level >= c->levels) return -1;
+  return c->lv[level].N;
+}
+
+mgmc_status mgmc_set_graph(mgmc_ctx* c, int32_t enabled) {
+  if (!c) return fail(MGMC_EINVAL, "context is NULL");
+  c->use_graph = enabled != 0;
+  return MGMC_OK;
+}
+
+mgmc_status mgmc_set_profiling(mgmc_ctx* c, int32_t enabled) {
+  if (!c) return fail(MGMC_EINVAL, "context is NULL");
+  if (enabled && c->ev_start.empty()) {
+    const size_t ring = 512;
+    c->ev_start.resize(ring);
+    c->ev_stop.resize(ring);
+    c->ev_pending.assign(ring, 0);
+    for (size_t k = 0; k < ring; ++k) {
+      MGMC_HIP(hipEventCreate(&c->ev_start[k]));
+      MGMC_HIP(hipEventCreate(&c->ev_stop[k]));
+    }
+  }
+  if (enabled) {
+    for (size_t k = 0; k < c->ev_pending.size(); ++k) c->ev_pending[k] = 0;
+    c->prof_ms = 0.0;
+    c->prof_launches = 0;
+  }
+  c->profiling = enabled != 0;
+  return MGMC_OK;
+}
+
+mgmc_status mgmc_profile_read(mgmc_ctx* c, double* total_ms, int64_t* launches) {
+  if (!c || !total_ms || !launches) return fail(MGMC_EINVAL, "NULL argument");
+  MGMC_HIP(hipStreamSynchronize(c->stream));
+  for (size_t k = 0; k < c->ev_pending.size(); ++k) {
+    mgmc_status s = drain_slot(c, k);
+    if (s != MGMC_OK) return s;
+  }
+  *total_ms = c->prof_ms;
+  *launches = c->prof_launches;
+  return MGMC_OK;
+}
+
+mgmc_status mgmc_destroy(mgmc_ctx* c) {
+  if (!c) return MGMC_OK;
+  mgmc_status s = MGMC_OK;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) s = fail(MGMC_EDEVICE, "stream synchronisation failed in destroy");
+  for (size_t k = 0; k < c->ev_start.size(); ++k) {
+    (void)hipEventDestroy(c->ev_start[k]);
+    (void)hipEventDestroy(c->ev_stop[k]);
+  }
+  for (void* p : c->allocs) (void)hipFree(p);
+  delete c;
+  return s;
+}
+
+const char* mgmc_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

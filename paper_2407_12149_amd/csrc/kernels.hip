@@ -1,0 +1,587 @@
+// HIP kernels of one MGMC update (gfx950).
+//
+//  * k_sweep: one colour pass of the random Gauss-Seidel smoother (Alg. 2/3
+//    with M = D + L in colour order, omega = 1): for every site i of the colour
+//    theta_i <- (f_i - sum_{j != i} A_ij theta_j) / A_ii + z_i / sqrt(A_ii),
+//    z_i from Philox.  One thread owns one Philox block, i.e. the two sites of
+//    the colour at x-distance 2 that share it.
+//  * k_restrict: f_{l-1}(J) = sum_delta w_J(delta) (f - A theta)(2J + delta),
+//    the restricted residual with R = P^T (Alg. 1, restriction step).
+//  * k_prolong: theta_i += sum_J P_iJ psi_J (Alg. 1, prolongation step).
+//  * k_coarsest: theta_0 = K f_0 + U^{-1} z, an exact draw from
+//    N(At_0^{-1} f_0, At_0^{-1}) (Sec. 3.4).
+//  * k_lowrank_*: the low-rank correction of Alg. 3 (see launch_lowrank).
+//  * k_qoi_*: q = F^T theta per chain, fixed-order reductions.
+#include "device_rng.h"
+#include "mgmc_internal.h"
+
+namespace mgmc {
+
+Geom make_geom(int dim, int n) {
+  Geom g;
+  g.n = n;
+  g.px = ((n + 5) + 3) / 4 * 4;
+  g.py = n + 2;
+  g.Np = int64_t(g.px) * g.py * (dim == 3 ? (n + 2) : 1);
+  return g;
+}
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ int64_t pidx(const Geom& g, int i1, int i2, int i3) {
+  return int64_t(i1 + 3) + int64_t(g.px) * (int64_t(i2) + int64_t(g.py) * i3);
+}
+
+__device__ __forceinline__ int64_t poff(const Geom& g, int dx, int dy, int dz) {
+  return int64_t(dx) + int64_t(g.px) * (int64_t(dy) + int64_t(g.py) * dz);
+}
+
+template <int DIM>
+__device__ __forceinline__ void unflatten(int64_t lin, int n, int& i1, int& i2, int& i3) {
+  i1 = 1 + int(lin % n);
+  lin /= n;
+  if (DIM == 3) {
+    i2 = 1 + int(lin % n);
+    i3 = 1 + int(lin / n);
+  } else {
+    i2 = 1 + int(lin);
+    i3 = 0;
+  }
+}
+
+__device__ __forceinline__ double multilinear(int dx, int dy, int dz) {
+  double w = 1.0;
+  if (dx) w *= 0.5;
+  if (dy) w *= 0.5;
+  if (dz) w *= 0.5;
+  return w;
+}
+
+// One Gauss-Seidel site update (neighbours in ascending index order).
+template <typename T, int DIM, bool CROSS>
+__device__ __forceinline__ void gs_update(const T* __restrict__ coef, const T* __restrict__ invd,
+                                          const T* __restrict__ isqd, T* __restrict__ th,
+                                          const T* __restrict__ f, const Geom& g, int64_t i, T z) {
+  constexpr int S = DIM == 2 ? 9 : 27;
+  T s = f ? f[i] : T(0);
+#pragma unroll
+  for (int t = 0; t < S; ++t) {
+    const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = DIM == 3 ? t / 9 - 1 : 0;
+    const int nz = (dx != 0) + (dy != 0) + (dz != 0);
+    if (nz == 0 || (CROSS && nz != 1)) continue;
+    s -= coef[int64_t(t) * g.Np + i] * th[i + poff(g, dx, dy, dz)];
+  }
+  th[i] = s * invd[i] + z * isqd[i];
+}
+
+template <typename T, int DIM, bool CROSS>
+__global__ __launch_bounds__(kBlock) void k_sweep(const T* __restrict__ coef,
+                                                  const T* __restrict__ invd,
+                                                  const T* __restrict__ isqd, T* __restrict__ theta,
+                                                  const T* __restrict__ f, int64_t fcs, Geom g,
+                                                  int colour, uint32_t word,
+                                                  const int64_t* __restrict__ mcur, uint32_t seed,
+                                                  uint32_t chain0) {
+  const int p1 = colour & 1, p2 = (colour >> 1) & 1, p3 = (colour >> 2) & 1;
+  const int n = g.n;
+  const int m1 = p1 ? (n + 1) / 2 : (n - 1) / 2;
+  const int m2 = p2 ? (n + 1) / 2 : (n - 1) / 2;
+  const int m3 = DIM == 3 ? (p3 ? (n + 1) / 2 : (n - 1) / 2) : 1;
+  const int qx = (m1 + 1) / 2;
+  const int64_t total = int64_t(qx) * m2 * m3;
+  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gid >= total) return;
+  const int c = blockIdx.y;
+  const int q = int(gid % qx);
+  const int64_t rest = gid / qx;
+  const int s2 = int(rest % m2), s3 = int(rest / m2);
+  const int i1 = 4 * q + (p1 ? 1 : 2);
+  const int i2 = 2 * s2 + (p2 ? 1 : 2);
+  const int i3 = DIM == 3 ? 2 * s3 + (p3 ? 1 : 2) : 0;
+  const uint32_t pair = uint32_t(q) + uint32_t(qx) * (uint32_t(s2) + uint32_t(m2) * uint32_t(s3));
+  const Block4 blk = philox10(pair, word | uint32_t(colour), uint32_t(*mcur), 0u, seed, chain0 + c);
+  T z0, z1;
+  Gauss<T>::pair(blk, z0, z1);
+  T* th = theta + int64_t(c) * g.Np;
+  const T* fc = f ? f + int64_t(c) * fcs : nullptr;
+  const int64_t ia = pidx(g, i1, i2, i3);
+  gs_update<T, DIM, CROSS>(coef, invd, isqd, th, fc, g, ia, z0);
+  if (2 * q + 1 < m1) gs_update<T, DIM, CROSS>(coef, invd, isqd, th, fc, g, ia + 2, z1);
+}
+
+template <typename T, int DIM, bool CROSS, bool USERP>
+__global__ __launch_bounds__(kBlock) void k_restrict(const T* __restrict__ coef,
+                                                     const T* __restrict__ theta,
+                                                     const T* __restrict__ f, int64_t fcs, Geom gf,
+                                                     T* __restrict__ fcoarse, Geom gc,
+                                                     const double* __restrict__ wP) {
+  constexpr int S = DIM == 2 ? 9 : 27;
+  const int nc = gc.n;
+  const int64_t total = int64_t(nc) * nc * (DIM == 3 ? nc : 1);
+  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gid >= total) return;
+  const int c = blockIdx.y;
+  int J1, J2, J3;
+  unflatten<DIM>(gid, nc, J1, J2, J3);
+  const T* th = theta + int64_t(c) * gf.Np;
+  const T* fc = f ? f + int64_t(c) * fcs : nullptr;
+  const int64_t iJ = pidx(gc, J1, J2, J3);
+  T acc = T(0);
+#pragma unroll
+  for (int t1 = 0; t1 < S; ++t1) {
+    const int ex = t1 % 3 - 1, ey = (t1 / 3) % 3 - 1, ez = DIM == 3 ? t1 / 9 - 1 : 0;
+    const int64_t ii = pidx(gf, 2 * J1 + ex, 2 * J2 + ey, DIM == 3 ? 2 * J3 + ez : 0);
+    T r = fc ? fc[ii] : T(0);
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+      const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = DIM == 3 ? t / 9 - 1 : 0;
+      const int nz = (dx != 0) + (dy != 0) + (dz != 0);
+      if (CROSS && nz > 1) continue;
+      r -= coef[int64_t(t) * gf.Np + ii] * th[ii + poff(gf, dx, dy, dz)];
+    }
+    const T w = USERP ? T(wP[int64_t(t1) * gc.Np + iJ]) : T(multilinear(ex, ey, ez));
+    acc += w * r;
+  }
+  fcoarse[int64_t(c) * gc.Np + iJ] = acc;
+}
+
+template <typename T, int DIM, bool USERP>
+__global__ __launch_bounds__(kBlock) void k_prolong(T* __restrict__ theta, Geom gf,
+                                                    const T* __restrict__ psi, Geom gc,
+                                                    const double* __restrict__ wP) {
+  const int nf = gf.n;
+  const int64_t total = int64_t(nf) * nf * (DIM == 3 ? nf : 1);
+  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gid >= total) return;
+  const int c = blockIdx.y;
+  int i[3];
+  unflatten<DIM>(gid, nf, i[0], i[1], i[2]);
+  // coarse nodes covering i along each axis, ascending: (J, delta) with i = 2J + delta
+  int J[3][2], D[3][2], cnt[3];
+  for (int k = 0; k < 3; ++k) {
+    if (k >= DIM) {
+      J[k][0] = 0; D[k][0] = 0; cnt[k] = 1;
+    } else if ((i[k] & 1) == 0) {
+      J[k][0] = i[k] / 2; D[k][0] = 0; cnt[k] = 1;
+    } else {
+      J[k][0] = (i[k] - 1) / 2; D[k][0] = 1;
+      J[k][1] = (i[k] + 1) / 2; D[k][1] = -1;
+      cnt[k] = 2;
+    }
+  }
+  const T* ps = psi + int64_t(c) * gc.Np;
+  T s = T(0);
+  for (int a3 = 0; a3 < cnt[2]; ++a3)
+    for (int a2 = 0; a2 < cnt[1]; ++a2)
+      for (int a1 = 0; a1 < cnt[0]; ++a1) {
+        const int64_t jc = pidx(gc, J[0][a1], J[1][a2], J[2][a3]);
+        T w;
+        if (USERP) {
+          const int t = (D[0][a1] + 1) + 3 * (D[1][a2] + 1) + 9 * (D[2][a3] + 1);
+          w = T(wP[int64_t(t) * gc.Np + jc]);
+        } else {
+          w = T(multilinear(D[0][a1], D[1][a2], D[2][a3]));
+        }
+        s += w * ps[jc];
+      }
+  theta[int64_t(c) * gf.Np + pidx(gf, i[0], i[1], i[2])] += s;
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_coarsest(const double* __restrict__ KT,
+                                                     const double* __restrict__ UinvT,
+                                                     const T* __restrict__ f0, int64_t fcs,
+                                                     T* __restrict__ theta0, Geom g, int N0,
+                                                     const int64_t* __restrict__ mcur,
+                                                     uint32_t seed, uint32_t chain0) {
+  extern __shared__ double sh[];
+  double* fv = sh;
+  double* zv = sh + N0;
+  const int c = blockIdx.x;
+  const uint32_t m = uint32_t(*mcur);
+  for (int k = threadIdx.x; k < N0; k += blockDim.x) {
+    int i1, i2, i3;
+    unflatten<DIM>(k, g.n, i1, i2, i3);
+    fv[k] = f0 ? double(f0[int64_t(c) * fcs + pidx(g, i1, i2, i3)]) : 0.0;
+  }
+  for (int p = threadIdx.x; 2 * p < N0; p += blockDim.x) {
+    const Block4 blk = philox10(uint32_t(p), 0u, m, 2u, seed, chain0 + c);
+    double z0, z1;
+    Gauss<double>::pair(blk, z0, z1);
+    zv[2 * p] = z0;
+    if (2 * p + 1 < N0) zv[2 * p + 1] = z1;
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < N0; r += blockDim.x) {
+    double s = 0.0;
+    for (int k = 0; k < N0; ++k) s += KT[int64_t(k) * N0 + r] * fv[k];
+    for (int k = r; k < N0; ++k) s += UinvT[int64_t(k) * N0 + r] * zv[k];
+    int i1, i2, i3;
+    unflatten<DIM>(r, g.n, i1, i2, i3);
+    theta0[int64_t(c) * g.Np + pidx(g, i1, i2, i3)] = T(s);
+  }
+}
+
+// Low-rank smoother, step 1 per chain: xi = Gamma^{-1/2} zeta, w = B^T theta,
+// u = w + (S - Gamma) xi.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_lowrank_prep(const T* __restrict__ theta, int64_t Np,
+                                                         int beta, const double* __restrict__ gisq,
+                                                         const int64_t* __restrict__ bptr,
+                                                         const int32_t* __restrict__ bidx,
+                                                         const double* __restrict__ bval,
+                                                         const double* __restrict__ SmG,
+                                                         double* __restrict__ xi_out,
+                                                         double* __restrict__ u_out, uint32_t word,
+                                                         const int64_t* __restrict__ mcur,
+                                                         uint32_t seed, uint32_t chain0) {
+  extern __shared__ double sh[];
+  double* xi = sh;
+  double* w = sh + beta;
+  const int c = blockIdx.x;
+  const T* th = theta + int64_t(c) * Np;
+  const uint32_t m = uint32_t(*mcur);
+  for (int j = threadIdx.x; j < beta; j += blockDim.x) {
+    const Block4 blk = philox10(uint32_t(j >> 1), word, m, 1u, seed, chain0 + c);
+    double z0, z1;
+    Gauss<double>::pair(blk, z0, z1);
+    xi[j] = ((j & 1) ? z1 : z0) * gisq[j];
+    double acc = 0.0;
+    for (int64_t e = bptr[j]; e < bptr[j + 1]; ++e) acc += bval[e] * double(th[bidx[e]]);
+    w[j] = acc;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < beta; j += blockDim.x) {
+    double acc = w[j];
+    for (int k = 0; k < beta; ++k) acc += SmG[int64_t(j) * beta + k] * xi[k];
+    xi_out[int64_t(c) * beta + j] = xi[j];
+    u_out[int64_t(c) * beta + j] = acc;
+  }
+}
+
+// Step 2 on the support rows: theta_r += sum_j C_rj xi_j - sum_j G_rj u_j.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_lowrank_apply(T* __restrict__ theta, int64_t Np,
+                                                          int beta, int nsupp,
+                                                          const int32_t* __restrict__ supp,
+                                                          const double* __restrict__ CT,
+                                                          const double* __restrict__ GT,
+                                                          const double* __restrict__ xi,
+                                                          const double* __restrict__ u) {
+  extern __shared__ double sh[];
+  double* xs = sh;
+  double* us = sh + beta;
+  const int c = blockIdx.y;
+  for (int j = threadIdx.x; j < beta; j += blockDim.x) {
+    xs[j] = xi[int64_t(c) * beta + j];
+    us[j] = u[int64_t(c) * beta + j];
+  }
+  __syncthreads();
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nsupp) return;
+  double a = 0.0, b = 0.0;
+  for (int j = 0; j < beta; ++j) {
+    a += CT[int64_t(j) * nsupp + r] * xs[j];
+    b += GT[int64_t(j) * nsupp + r] * us[j];
+  }
+  T* th = theta + int64_t(c) * Np;
+  const int64_t at = supp[r];
+  th[at] = T(double(th[at]) + a - b);
+}
+
+// v = Gamma^{-1} B^T theta after the pre-smoother (feeds the coarse rhs).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gather_v(const T* __restrict__ theta, int64_t Np,
+                                                     int beta, const int64_t* __restrict__ bptr,
+                                                     const int32_t* __restrict__ bidx,
+                                                     const double* __restrict__ bval,
+                                                     const double* __restrict__ ginv,
+                                                     double* __restrict__ v) {
+  const int c = blockIdx.x;
+  const T* th = theta + int64_t(c) * Np;
+  for (int j = threadIdx.x; j < beta; j += blockDim.x) {
+    double acc = 0.0;
+    for (int64_t e = bptr[j]; e < bptr[j + 1]; ++e) acc += bval[e] * double(th[bidx[e]]);
+    v[int64_t(c) * beta + j] = acc * ginv[j];
+  }
+}
+
+// f_{l-1} -= B_{l-1} v on the rows of B_{l-1}: the low-rank part of the
+// restricted residual, P^T B_l v = B_{l-1} v.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_coarse_rhs_lr(T* __restrict__ fc, int64_t Np,
+                                                          const double* __restrict__ v, int beta,
+                                                          int nrows, const int32_t* __restrict__ brow,
+                                                          const int64_t* __restrict__ brptr,
+                                                          const int32_t* __restrict__ brcol,
+                                                          const double* __restrict__ brval) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  const int c = blockIdx.y;
+  double s = 0.0;
+  for (int64_t e = brptr[r]; e < brptr[r + 1]; ++e) s += brval[e] * v[int64_t(c) * beta + brcol[e]];
+  T* f = fc + int64_t(c) * Np;
+  f[brow[r]] = T(double(f[brow[r]]) - s);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill_zero(T* __restrict__ p, int64_t count) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = T(0);
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (int(threadIdx.x) < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_qoi_partial(const T* __restrict__ theta, Geom g,
+                                                        int64_t N, const double* __restrict__ F,
+                                                        double* __restrict__ partial, int nb) {
+  __shared__ double sh[kBlock];
+  const int c = blockIdx.y, b = blockIdx.x;
+  const int64_t chunk = (N + nb - 1) / nb;
+  const int64_t lo = int64_t(b) * chunk, hi = lo + chunk < N ? lo + chunk : N;
+  const T* th = theta + int64_t(c) * g.Np;
+  double acc = 0.0;
+  for (int64_t lin = lo + threadIdx.x; lin < hi; lin += blockDim.x) {
+    int i1, i2, i3;
+    unflatten<DIM>(lin, g.n, i1, i2, i3);
+    acc += F[lin] * double(th[pidx(g, i1, i2, i3)]);
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[int64_t(c) * nb + b] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_qoi_final(const double* __restrict__ partial, int nb,
+                                                      double* __restrict__ qoi,
+                                                      const int64_t* __restrict__ mcur, int64_t m0,
+                                                      int nchains) {
+  __shared__ double sh[kBlock];
+  const int c = blockIdx.x;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += partial[int64_t(c) * nb + b];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) qoi[(*mcur - m0) * nchains + c] = s;
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_unpack(const T* __restrict__ user, T* __restrict__ th,
+                                                   Geom g, int64_t N) {
+  const int64_t lin = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (lin >= N) return;
+  const int c = blockIdx.y;
+  int i1, i2, i3;
+  unflatten<DIM>(lin, g.n, i1, i2, i3);
+  th[int64_t(c) * g.Np + pidx(g, i1, i2, i3)] = user[int64_t(c) * N + lin];
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_pack(const T* __restrict__ th, T* __restrict__ user,
+                                                 Geom g, int64_t N) {
+  const int64_t lin = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (lin >= N) return;
+  const int c = blockIdx.y;
+  int i1, i2, i3;
+  unflatten<DIM>(lin, g.n, i1, i2, i3);
+  user[int64_t(c) * N + lin] = th[int64_t(c) * g.Np + pidx(g, i1, i2, i3)];
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_unpack_rhs(const double* __restrict__ user,
+                                                       T* __restrict__ f, Geom g, int64_t N) {
+  const int64_t lin = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (lin >= N) return;
+  int i1, i2, i3;
+  unflatten<DIM>(lin, g.n, i1, i2, i3);
+  f[pidx(g, i1, i2, i3)] = T(user[lin]);
+}
+
+__global__ void k_set_m(int64_t* mcur, int64_t value) { *mcur = value; }
+__global__ void k_advance_m(int64_t* mcur) { *mcur += 1; }
+
+inline unsigned blocks_for(int64_t count) { return unsigned((count + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+#define MGMC_DISPATCH(L, ...)  \
+  do {                          \
+    if ((L).fp32) {             \
+      using T = float;          \
+      if ((L).dim == 2) {       \
+        constexpr int DIM = 2;  \
+        __VA_ARGS__;            \
+      } else {                  \
+        constexpr int DIM = 3;  \
+        __VA_ARGS__;            \
+      }                         \
+    } else {                    \
+      using T = double;         \
+      if ((L).dim == 2) {       \
+        constexpr int DIM = 2;  \
+        __VA_ARGS__;            \
+      } else {                  \
+        constexpr int DIM = 3;  \
+        __VA_ARGS__;            \
+      }                         \
+    }                           \
+  } while (0)
+
+hipError_t launch_sweep_colour(const Launch& L, const DevLevel& lv, const void* f, int64_t fcs,
+                               uint32_t word, int colour) {
+  const int n = lv.g.n;
+  auto ext = [n](int p) { return p ? (n + 1) / 2 : (n - 1) / 2; };
+  const int m1 = ext(colour & 1), m2 = ext((colour >> 1) & 1);
+  const int m3 = L.dim == 3 ? ext((colour >> 2) & 1) : 1;
+  const int64_t total = int64_t((m1 + 1) / 2) * m2 * m3;
+  if (total == 0) return hipSuccess;
+  dim3 grid(blocks_for(total), L.nchains);
+  MGMC_DISPATCH(L, {
+    if (lv.cross)
+      k_sweep<T, DIM, true><<<grid, kBlock, 0, L.stream>>>(
+          (const T*)lv.coef, (const T*)lv.invd, (const T*)lv.isqd, (T*)lv.theta, (const T*)f, fcs,
+          lv.g, colour, word, L.mcur, L.seed, L.chain0);
+    else
+      k_sweep<T, DIM, false><<<grid, kBlock, 0, L.stream>>>(
+          (const T*)lv.coef, (const T*)lv.invd, (const T*)lv.isqd, (T*)lv.theta, (const T*)f, fcs,
+          lv.g, colour, word, L.mcur, L.seed, L.chain0);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_restrict(const Launch& L, const DevLevel& fine, const DevLevel& coarse,
+                           const void* f, int64_t fcs) {
+  dim3 grid(blocks_for(coarse.N), L.nchains);
+  MGMC_DISPATCH(L, {
+    const T* cf = (const T*)fine.coef;
+    const T* th = (const T*)fine.theta;
+    T* out = (T*)coarse.f;
+    if (fine.wP) {
+      if (fine.cross)
+        k_restrict<T, DIM, true, true><<<grid, kBlock, 0, L.stream>>>(cf, th, (const T*)f, fcs, fine.g, out, coarse.g, fine.wP);
+      else
+        k_restrict<T, DIM, false, true><<<grid, kBlock, 0, L.stream>>>(cf, th, (const T*)f, fcs, fine.g, out, coarse.g, fine.wP);
+    } else {
+      if (fine.cross)
+        k_restrict<T, DIM, true, false><<<grid, kBlock, 0, L.stream>>>(cf, th, (const T*)f, fcs, fine.g, out, coarse.g, nullptr);
+      else
+        k_restrict<T, DIM, false, false><<<grid, kBlock, 0, L.stream>>>(cf, th, (const T*)f, fcs, fine.g, out, coarse.g, nullptr);
+    }
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_prolong(const Launch& L, const DevLevel& fine, const DevLevel& coarse) {
+  dim3 grid(blocks_for(fine.N), L.nchains);
+  MGMC_DISPATCH(L, {
+    if (fine.wP)
+      k_prolong<T, DIM, true><<<grid, kBlock, 0, L.stream>>>((T*)fine.theta, fine.g, (const T*)coarse.theta, coarse.g, fine.wP);
+    else
+      k_prolong<T, DIM, false><<<grid, kBlock, 0, L.stream>>>((T*)fine.theta, fine.g, (const T*)coarse.theta, coarse.g, nullptr);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_coarsest(const Launch& L, const DevLevel& lv0, const void* f0, int64_t fcs,
+                           void* theta0, const double* KT, const double* UinvT) {
+  const int N0 = int(lv0.N);
+  const size_t shmem = size_t(2) * N0 * sizeof(double);
+  MGMC_DISPATCH(L, {
+    k_coarsest<T, DIM><<<L.nchains, kBlock, shmem, L.stream>>>(KT, UinvT, (const T*)f0, fcs, (T*)theta0, lv0.g, N0, L.mcur, L.seed, L.chain0);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_lowrank(const Launch& L, const DevLevel& lv, int dir, uint32_t word, int beta,
+                          const double* gisq, double* xi, double* u) {
+  const size_t shmem = size_t(2) * beta * sizeof(double);
+  if (L.fp32) {
+    k_lowrank_prep<float><<<L.nchains, kBlock, shmem, L.stream>>>((const float*)lv.theta, lv.g.Np, beta, gisq, lv.bptr, lv.bidx, lv.bval, lv.SmG[dir], xi, u, word, L.mcur, L.seed, L.chain0);
+  } else {
+    k_lowrank_prep<double><<<L.nchains, kBlock, shmem, L.stream>>>((const double*)lv.theta, lv.g.Np, beta, gisq, lv.bptr, lv.bidx, lv.bval, lv.SmG[dir], xi, u, word, L.mcur, L.seed, L.chain0);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || lv.nsupp[dir] == 0) return e;
+  dim3 grid(blocks_for(lv.nsupp[dir]), L.nchains);
+  if (L.fp32)
+    k_lowrank_apply<float><<<grid, kBlock, shmem, L.stream>>>((float*)lv.theta, lv.g.Np, beta, lv.nsupp[dir], lv.supp[dir], lv.CT[dir], lv.GT[dir], xi, u);
+  else
+    k_lowrank_apply<double><<<grid, kBlock, shmem, L.stream>>>((double*)lv.theta, lv.g.Np, beta, lv.nsupp[dir], lv.supp[dir], lv.CT[dir], lv.GT[dir], xi, u);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_v(const Launch& L, const DevLevel& lv, int beta, const double* ginv,
+                           double* v) {
+  if (L.fp32)
+    k_gather_v<float><<<L.nchains, kBlock, 0, L.stream>>>((const float*)lv.theta, lv.g.Np, beta, lv.bptr, lv.bidx, lv.bval, ginv, v);
+  else
+    k_gather_v<double><<<L.nchains, kBlock, 0, L.stream>>>((const double*)lv.theta, lv.g.Np, beta, lv.bptr, lv.bidx, lv.bval, ginv, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse_rhs_lowrank(const Launch& L, const DevLevel& coarse, const double* v,
+                                     int beta) {
+  if (coarse.nbrows == 0) return hipSuccess;
+  dim3 grid(blocks_for(coarse.nbrows), L.nchains);
+  if (L.fp32)
+    k_coarse_rhs_lr<float><<<grid, kBlock, 0, L.stream>>>((float*)coarse.f, coarse.g.Np, v, beta, coarse.nbrows, coarse.brow, coarse.brptr, coarse.brcol, coarse.brval);
+  else
+    k_coarse_rhs_lr<double><<<grid, kBlock, 0, L.stream>>>((double*)coarse.f, coarse.g.Np, v, beta, coarse.nbrows, coarse.brow, coarse.brptr, coarse.brcol, coarse.brval);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(const Launch& L, void* p, int64_t count) {
+  if (count == 0) return hipSuccess;
+  if (L.fp32)
+    k_fill_zero<float><<<blocks_for(count), kBlock, 0, L.stream>>>((float*)p, count);
+  else
+    k_fill_zero<double><<<blocks_for(count), kBlock, 0, L.stream>>>((double*)p, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_qoi(const Launch& L, const DevLevel& fine, const void* theta, const double* F,
+                      double* partial, int nb, double* qoi, int64_t m0) {
+  dim3 grid(nb, L.nchains);
+  MGMC_DISPATCH(L, { k_qoi_partial<T, DIM><<<grid, kBlock, 0, L.stream>>>((const T*)theta, fine.g, fine.N, F, partial, nb); });
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_qoi_final<<<L.nchains, kBlock, 0, L.stream>>>(partial, nb, qoi, L.mcur, m0, L.nchains);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack(const Launch& L, const DevLevel& lv, const void* user, void* theta) {
+  dim3 grid(blocks_for(lv.N), L.nchains);
+  MGMC_DISPATCH(L, { k_unpack<T, DIM><<<grid, kBlock, 0, L.stream>>>((const T*)user, (T*)theta, lv.g, lv.N); });
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(const Launch& L, const DevLevel& lv, const void* theta, void* user) {
+  dim3 grid(blocks_for(lv.N), L.nchains);
+  MGMC_DISPATCH(L, { k_pack<T, DIM><<<grid, kBlock, 0, L.stream>>>((const T*)theta, (T*)user, lv.g, lv.N); });
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack_rhs(const Launch& L, const DevLevel& lv, const double* user, void* f) {
+  MGMC_DISPATCH(L, { k_unpack_rhs<T, DIM><<<blocks_for(lv.N), kBlock, 0, L.stream>>>(user, (T*)f, lv.g, lv.N); });
+  return hipGetLastError();
+}
+
+hipError_t launch_set_m(hipStream_t s, int64_t* mcur, int64_t value) {
+  k_set_m<<<1, 1, 0, s>>>(mcur, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance_m(hipStream_t s, int64_t* mcur) {
+  k_advance_m<<<1, 1, 0, s>>>(mcur);
+  return hipGetLastError();
+}
+
+}  // namespace mgmc

@@ -1,0 +1,87 @@
+// Device-side data of the MGMC library and the kernel launchers.
+//
+// Layout of every level vector (state theta, right-hand side f, stencil
+// arrays): padded lexicographic with a zero ghost ring, x fastest.  Node
+// (i1, i2, i3), 0 <= i_k <= n+1, sits at (i1 + 3) + px (i2 + py i3) with
+// px = round_up(n + 5, 4) and py = n + 2, so that interior node i1 = 4q + 1
+// starts a 32-byte aligned group of four.  Chains are stored one padded field
+// after another (chain-major).  Ghost entries are zero and never written.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mgmc {
+
+struct Geom {
+  int n = 0;       // interior nodes per dimension
+  int px = 0;      // x pitch
+  int py = 0;      // rows per plane (n + 2)
+  int64_t Np = 0;  // padded entries per field
+};
+
+Geom make_geom(int dim, int n);
+
+struct DevLevel {
+  Geom g;
+  int64_t N = 0;                 // n^dim interior sites
+  bool cross = false;            // stencil has only centre + axis entries
+  void* coef = nullptr;          // [S][Np] stencil entries, precision T
+  void* invd = nullptr;          // [Np] 1 / A_ii
+  void* isqd = nullptr;          // [Np] 1 / sqrt(A_ii)
+  double* wP = nullptr;          // [S][Np of level l-1] user prolongation into this level
+  void* theta = nullptr;         // [nchains][Np]
+  void* f = nullptr;             // [nchains][Np] (levels below the finest)
+  // observations B_l: columns (for B^T theta) and rows (for coarse rhs)
+  int64_t* bptr = nullptr;       // [beta + 1]
+  int32_t* bidx = nullptr;       // padded site of each weight
+  double* bval = nullptr;
+  int32_t nbrows = 0;
+  int32_t* brow = nullptr;       // padded site of each row
+  int64_t* brptr = nullptr;      // [nbrows + 1]
+  int32_t* brcol = nullptr;      // observation index
+  double* brval = nullptr;
+  // low-rank smoother for forward (0) / backward (1) sweeps
+  int32_t nsupp[2] = {0, 0};
+  int32_t* supp[2] = {nullptr, nullptr};   // padded sites
+  double* CT[2] = {nullptr, nullptr};      // [beta][nsupp]
+  double* GT[2] = {nullptr, nullptr};      // [beta][nsupp]
+  double* SmG[2] = {nullptr, nullptr};     // [beta][beta], S - Gamma
+};
+
+struct Launch {
+  hipStream_t stream = nullptr;
+  int dim = 2;
+  int fp32 = 0;
+  int nchains = 1;
+  uint32_t seed = 0;
+  uint32_t chain0 = 0;
+  const int64_t* mcur = nullptr;  // device: current sample index
+};
+
+// Noise counter word 1: level << 8 | sweep << 4 | colour.
+inline uint32_t noise_word(int level, int sigma) { return (uint32_t(level) << 8) | (uint32_t(sigma) << 4); }
+
+hipError_t launch_sweep_colour(const Launch& L, const DevLevel& lv, const void* f, int64_t fcs,
+                               uint32_t word, int colour);
+hipError_t launch_restrict(const Launch& L, const DevLevel& fine, const DevLevel& coarse,
+                           const void* f, int64_t fcs);
+hipError_t launch_prolong(const Launch& L, const DevLevel& fine, const DevLevel& coarse);
+hipError_t launch_coarsest(const Launch& L, const DevLevel& lv0, const void* f0, int64_t fcs,
+                           void* theta0, const double* KT, const double* UinvT);
+hipError_t launch_lowrank(const Launch& L, const DevLevel& lv, int dir, uint32_t word, int beta,
+                          const double* gisq, double* xi, double* u);
+hipError_t launch_gather_v(const Launch& L, const DevLevel& lv, int beta, const double* ginv,
+                           double* v);
+hipError_t launch_coarse_rhs_lowrank(const Launch& L, const DevLevel& coarse, const double* v,
+                                     int beta);
+hipError_t launch_fill_zero(const Launch& L, void* p, int64_t count);
+hipError_t launch_qoi(const Launch& L, const DevLevel& fine, const void* theta, const double* F,
+                      double* partial, int nb, double* qoi, int64_t m0);
+hipError_t launch_unpack(const Launch& L, const DevLevel& lv, const void* user, void* theta);
+hipError_t launch_pack(const Launch& L, const DevLevel& lv, const void* theta, void* user);
+hipError_t launch_unpack_rhs(const Launch& L, const DevLevel& lv, const double* user, void* f);
+hipError_t launch_set_m(hipStream_t s, int64_t* mcur, int64_t value);
+hipError_t launch_advance_m(hipStream_t s, int64_t* mcur);
+
+}  // namespace mgmc

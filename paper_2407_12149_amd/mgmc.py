@@ -1,0 +1,247 @@
+"""Python binding of libmgmc.so (the MI355X MGMC sampler).
+
+Argument marshalling only: every step of the sampler runs in the HIP library.
+The functions carry the names of the C ABI in ``include/mgmc.h``; torch is
+used for device memory and streams.  If the library has not been built the
+import of this module fails loudly -- there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmgmc.so")
+
+MGMC_OK, MGMC_EINVAL, MGMC_ENOMEM, MGMC_EDEVICE, MGMC_ENOTSPD, MGMC_EUNSUPPORTED, MGMC_ESTATE = range(7)
+MGMC_FP64, MGMC_FP32 = 0, 1
+
+EXPORTED = [
+    "mgmc_setup", "mgmc_sample", "mgmc_posterior_sample", "mgmc_levels", "mgmc_level_sites",
+    "mgmc_set_graph", "mgmc_set_profiling", "mgmc_profile_read", "mgmc_destroy",
+    "mgmc_last_error",
+]
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class mgmc_problem(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32), ("n", ctypes.c_int32), ("levels", ctypes.c_int32),
+        ("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32), ("kappa2", ctypes.c_double),
+        ("scale", ctypes.c_double), ("face_coef", _dp), ("prolong_w", _dp),
+        ("precision", ctypes.c_int32), ("nchains", ctypes.c_int32),
+        ("chain_offset", ctypes.c_int64), ("seed", ctypes.c_uint64),
+    ]
+
+
+class mgmc_obs(ctypes.Structure):
+    _fields_ = [
+        ("beta", ctypes.c_int32), ("ptr", ctypes.POINTER(ctypes.c_int64)),
+        ("idx", ctypes.POINTER(ctypes.c_int32)), ("val", _dp), ("gamma", _dp),
+    ]
+
+
+class MGMCError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"mgmc status {status}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library():
+    """Load libmgmc.so; raise if it is missing (build it with __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: the HIP library must be built "
+                          "(python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    lib.mgmc_setup.restype = ctypes.c_int
+    lib.mgmc_setup.argtypes = [ctypes.POINTER(mgmc_problem), ctypes.POINTER(mgmc_obs), vp,
+                               ctypes.POINTER(vp)]
+    lib.mgmc_sample.restype = ctypes.c_int
+    lib.mgmc_sample.argtypes = [vp, ctypes.c_int64, ctypes.c_int64, vp, vp, vp, vp]
+    lib.mgmc_posterior_sample.restype = ctypes.c_int
+    lib.mgmc_posterior_sample.argtypes = [vp, _dp, ctypes.c_int64, ctypes.c_int64, vp, vp, vp]
+    lib.mgmc_levels.restype = ctypes.c_int32
+    lib.mgmc_levels.argtypes = [vp]
+    lib.mgmc_level_sites.restype = ctypes.c_int64
+    lib.mgmc_level_sites.argtypes = [vp, ctypes.c_int32]
+    lib.mgmc_set_graph.restype = ctypes.c_int
+    lib.mgmc_set_graph.argtypes = [vp, ctypes.c_int32]
+    lib.mgmc_set_profiling.restype = ctypes.c_int
+    lib.mgmc_set_profiling.argtypes = [vp, ctypes.c_int32]
+    lib.mgmc_profile_read.restype = ctypes.c_int
+    lib.mgmc_profile_read.argtypes = [vp, _dp, ctypes.POINTER(ctypes.c_int64)]
+    lib.mgmc_destroy.restype = ctypes.c_int
+    lib.mgmc_destroy.argtypes = [vp]
+    lib.mgmc_last_error.restype = ctypes.c_char_p
+    lib.mgmc_last_error.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != MGMC_OK:
+        raise MGMCError(status, load_library().mgmc_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def mgmc_setup(problem, obs=None, stream=None):
+    """problem: dict with dim, n, levels, kappa2 and optional scale, face_coef,
+    prolong_w, nu1, nu2, precision ('fp64'|'fp32'), nchains, chain_offset, seed.
+    obs: (ptr, idx, val, gamma) numpy arrays or None.  Returns an opaque handle."""
+    lib = load_library()
+    keep = []
+
+    def arr(a, dtype):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=dtype)
+        keep.append(a)
+        return a
+
+    face = arr(problem.get("face_coef"), np.float64)
+    pw = arr(problem.get("prolong_w"), np.float64)
+    prec = problem.get("precision", "fp64")
+    p = mgmc_problem(
+        dim=int(problem["dim"]), n=int(problem["n"]), levels=int(problem["levels"]),
+        nu1=int(problem.get("nu1", 1)), nu2=int(problem.get("nu2", 1)),
+        kappa2=float(problem["kappa2"]), scale=float(problem.get("scale", 0.0) or 0.0),
+        face_coef=None if face is None else face.ctypes.data_as(_dp),
+        prolong_w=None if pw is None else pw.ctypes.data_as(_dp),
+        precision=MGMC_FP32 if prec in ("fp32", MGMC_FP32) else MGMC_FP64,
+        nchains=int(problem.get("nchains", 1)), chain_offset=int(problem.get("chain_offset", 0)),
+        seed=int(problem.get("seed", 0)))
+    o = None
+    if obs is not None:
+        ptr, idx, val, gamma = obs
+        ptr, idx = arr(ptr, np.int64), arr(idx, np.int32)
+        val, gamma = arr(val, np.float64), arr(gamma, np.float64)
+        o = mgmc_obs(beta=len(ptr) - 1, ptr=ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                     idx=idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                     val=val.ctypes.data_as(_dp), gamma=gamma.ctypes.data_as(_dp))
+    handle = ctypes.c_void_p()
+    _check(lib.mgmc_setup(ctypes.byref(p), None if o is None else ctypes.byref(o),
+                          _stream_handle(stream), ctypes.byref(handle)))
+    return handle
+
+
+def mgmc_sample(ctx, m0, nsamples, theta, rhs=None, F=None, qoi=None):
+    _check(load_library().mgmc_sample(ctx, int(m0), int(nsamples), _ptr(theta), _ptr(rhs),
+                                      _ptr(F), _ptr(qoi)))
+
+
+def mgmc_posterior_sample(ctx, y, m0, nsamples, theta, F=None, qoi=None):
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    _check(load_library().mgmc_posterior_sample(ctx, y.ctypes.data_as(_dp), int(m0),
+                                                int(nsamples), _ptr(theta), _ptr(F), _ptr(qoi)))
+
+
+def mgmc_levels(ctx):
+    return int(load_library().mgmc_levels(ctx))
+
+
+def mgmc_level_sites(ctx, level):
+    return int(load_library().mgmc_level_sites(ctx, int(level)))
+
+
+def mgmc_set_graph(ctx, enabled):
+    _check(load_library().mgmc_set_graph(ctx, 1 if enabled else 0))
+
+
+def mgmc_set_profiling(ctx, enabled):
+    _check(load_library().mgmc_set_profiling(ctx, 1 if enabled else 0))
+
+
+def mgmc_profile_read(ctx):
+    """(summed kernel milliseconds, launches) of the finest-level sweeps."""
+    ms = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    _check(load_library().mgmc_profile_read(ctx, ctypes.byref(ms), ctypes.byref(cnt)))
+    return ms.value, cnt.value
+
+
+def mgmc_destroy(ctx):
+    _check(load_library().mgmc_destroy(ctx))
+
+
+def mgmc_last_error():
+    return load_library().mgmc_last_error().decode()
+
+
+class Sampler:
+    """Owner of one context plus the chain states (torch tensors on the GPU)."""
+
+    def __init__(self, problem, obs=None, stream=None, device="cuda"):
+        import torch
+        self.torch = torch
+        self.problem = dict(problem)
+        self.dtype = torch.float32 if problem.get("precision", "fp64") == "fp32" else torch.float64
+        self.nchains = int(problem.get("nchains", 1))
+        self.N = int(problem["n"]) ** int(problem["dim"])
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.ctx = mgmc_setup(problem, obs, self.stream)
+        self.device = device
+        self.theta = torch.zeros(self.nchains, self.N, dtype=self.dtype, device=device)
+
+    def _run(self, call, nsamples, F, want_qoi):
+        torch = self.torch
+        cur = torch.cuda.current_stream()
+        self.stream.wait_stream(cur)
+        qoi = None
+        with torch.cuda.stream(self.stream):
+            if F is not None and want_qoi:
+                qoi = torch.zeros(nsamples, self.nchains, dtype=torch.float64, device=self.device)
+            call(F if qoi is not None else None, qoi)
+        cur.wait_stream(self.stream)
+        return qoi
+
+    def sample(self, m0, nsamples, rhs=None, F=None, want_qoi=True):
+        """Updates m0..m0+nsamples-1 of every chain in place on self.theta;
+        returns the [nsamples, nchains] FP64 QoI series if F is given."""
+        return self._run(lambda Fp, q: mgmc_sample(self.ctx, m0, nsamples, self.theta, rhs, Fp, q),
+                         nsamples, F, want_qoi)
+
+    def posterior_sample(self, y, m0, nsamples, F=None, want_qoi=True):
+        return self._run(
+            lambda Fp, q: mgmc_posterior_sample(self.ctx, y, m0, nsamples, self.theta, Fp, q),
+            nsamples, F, want_qoi)
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def set_graph(self, enabled):
+        mgmc_set_graph(self.ctx, enabled)
+
+    def set_profiling(self, enabled):
+        mgmc_set_profiling(self.ctx, enabled)
+
+    def profile_read(self):
+        return mgmc_profile_read(self.ctx)
+
+    def close(self):
+        if self.ctx is not None:
+            mgmc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
