@@ -452,6 +452,7 @@ mgmc_status mgmc_setup(const mgmc_problem* problem, const mgmc_obs* obs, void* h
   if ((s = c->upload(c->KT, c->H.KT)) != MGMC_OK) return cleanup(s);
   if ((s = c->upload(c->UinvT, c->H.UinvT)) != MGMC_OK) return cleanup(s);
   if ((s = c->alloc(c->mcur, 1)) != MGMC_OK) return cleanup(s);
+  c->L.mcur = c->mcur;
   const int top = c->levels - 1;
   c->qnb = int(std::min<int64_t>(256, (c->lv[top].N + 4095) / 4096));
   if (c->qnb < 1) c->qnb = 1;

@@ -179,7 +179,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong(T* __restrict__ theta, Geom 
         const int64_t jc = pidx(gc, J[0][a1], J[1][a2], J[2][a3]);
         T w;
         if (USERP) {
-          const int t = (D[0][a1] + 1) + 3 * (D[1][a2] + 1) + 9 * (D[2][a3] + 1);
+          const int t = (D[0][a1] + 1) + 3 * (D[1][a2] + 1) + (DIM == 3 ? 9 * (D[2][a3] + 1) : 0);
           w = T(wP[int64_t(t) * gc.Np + jc]);
         } else {
           w = T(multilinear(D[0][a1], D[1][a2], D[2][a3]));
@@ -437,6 +437,7 @@ inline unsigned blocks_for(int64_t count) { return unsigned((count + kBlock - 1)
 
 hipError_t launch_sweep_colour(const Launch& L, const DevLevel& lv, const void* f, int64_t fcs,
                                uint32_t word, int colour) {
+  if (L.mcur == nullptr) return hipErrorInvalidValue;
   const int n = lv.g.n;
   auto ext = [n](int p) { return p ? (n + 1) / 2 : (n - 1) / 2; };
   const int m1 = ext(colour & 1), m2 = ext((colour >> 1) & 1);
@@ -492,6 +493,7 @@ hipError_t launch_prolong(const Launch& L, const DevLevel& fine, const DevLevel&
 
 hipError_t launch_coarsest(const Launch& L, const DevLevel& lv0, const void* f0, int64_t fcs,
                            void* theta0, const double* KT, const double* UinvT) {
+  if (L.mcur == nullptr) return hipErrorInvalidValue;
   const int N0 = int(lv0.N);
   const size_t shmem = size_t(2) * N0 * sizeof(double);
   MGMC_DISPATCH(L, {
@@ -502,6 +504,7 @@ hipError_t launch_coarsest(const Launch& L, const DevLevel& lv0, const void* f0,
 
 hipError_t launch_lowrank(const Launch& L, const DevLevel& lv, int dir, uint32_t word, int beta,
                           const double* gisq, double* xi, double* u) {
+  if (L.mcur == nullptr) return hipErrorInvalidValue;
   const size_t shmem = size_t(2) * beta * sizeof(double);
   if (L.fp32) {
     k_lowrank_prep<float><<<L.nchains, kBlock, shmem, L.stream>>>((const float*)lv.theta, lv.g.Np, beta, gisq, lv.bptr, lv.bidx, lv.bval, lv.SmG[dir], xi, u, word, L.mcur, L.seed, L.chain0);
@@ -549,6 +552,7 @@ hipError_t launch_fill_zero(const Launch& L, void* p, int64_t count) {
 
 hipError_t launch_qoi(const Launch& L, const DevLevel& fine, const void* theta, const double* F,
                       double* partial, int nb, double* qoi, int64_t m0) {
+  if (L.mcur == nullptr) return hipErrorInvalidValue;
   dim3 grid(nb, L.nchains);
   MGMC_DISPATCH(L, { k_qoi_partial<T, DIM><<<grid, kBlock, 0, L.stream>>>((const T*)theta, fine.g, fine.N, F, partial, nb); });
   hipError_t e = hipGetLastError();
