@@ -87,7 +87,19 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", type=int, default=1)
+    ap.add_argument("--copy-ref-mib", type=int, default=0,
+                    help="only run a device-to-device copy of this many MiB, 20 times "
+                         "(reference for the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_ref_mib:
+        import torch
+        src = torch.ones(args.copy_ref_mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(20):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_ref_bytes": src.numel() * 8, "repeats": 20}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; chains shard across GPUs "
                           "without communication but no multi-GPU path is built"}))

@@ -7,7 +7,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmgmc.so")
-SOURCES = ["csrc/api.hip", "csrc/kernels.hip", "csrc/hierarchy.cpp"]
+SOURCES = ["csrc/api.hip", "csrc/kernels.hip", "csrc/kernels_tiled.hip", "csrc/hierarchy.cpp"]
 
 
 def build(verbose: bool = False) -> str:

@@ -49,8 +49,8 @@ struct mgmc_ctx {
   int levels = 0, S = 9, beta = 0, qnb = 0;
   size_t esz = 8;
   std::vector<mgmc::DevLevel> lv;
-  double* KT = nullptr;
-  double* UinvT = nullptr;
+  double* K = nullptr;
+  double* Uinv = nullptr;
   double* gisq = nullptr;
   double* ginv = nullptr;
   double* xi = nullptr;
@@ -63,6 +63,9 @@ struct mgmc_ctx {
   std::vector<double> last_y;
   bool posterior_ready = false;
   bool use_graph = false;
+  bool tiled = true;    // one launch per 2D sweep; false: one launch per colour
+  int sweep_variant = 1;  // 0: LDS-staged tiles, 1: segment owners (256 threads), 2: (512)
+  int sweep_cpb = 0;      // chains per block of the 2D sweeps; 0 picks by size
   std::vector<void*> allocs;
   // profiling: a ring of event pairs around finest-level sweep launches
   bool profiling = false;
@@ -203,8 +206,12 @@ mgmc_status upload_level(mgmc_ctx* c, int l) {
     mgmc_status s = c->upload(d.wP, w);
     if (s != MGMC_OK) return s;
   }
-  mgmc_status s = c->alloc_bytes(d.theta, size_t(nch) * Np * c->esz);
+  mgmc_status s = c->alloc_bytes(d.buf[0], size_t(nch) * Np * c->esz);
   if (s != MGMC_OK) return s;
+  if (dim == 2 && l >= 1) {  // second buffer for the tiled (out-of-place) sweeps
+    s = c->alloc_bytes(d.buf[1], size_t(nch) * Np * c->esz);
+    if (s != MGMC_OK) return s;
+  }
   if (l < H.L) {
     s = c->alloc_bytes(d.f, size_t(nch) * Np * c->esz);
     if (s != MGMC_OK) return s;
@@ -305,54 +312,111 @@ mgmc_status timed(mgmc_ctx* c, bool finest, F&& body) {
     if (e_ != hipSuccess) return fail(MGMC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// One 2D sweep from theta_in into theta_out in the selected kernel form.
+hipError_t sweep2d(mgmc_ctx* c, const mgmc::DevLevel& lv, const void* in, void* out, int zero_in,
+                   const void* f, int64_t fcs, uint32_t word, int backward,
+                   const mgmc::DevLevel* coarse, const void* psi) {
+  if (c->sweep_variant == 0)
+    return mgmc::launch_sweep_tiled(c->L, lv, in, out, zero_in, f, fcs, word, backward, coarse, psi);
+  int cpb = c->sweep_cpb;
+  if (cpb <= 0) {
+    // enough blocks to fill the device, chains grouped so each block reuses
+    // its stencil registers; FP64 groups stay smaller (register pressure)
+    const int tys = lv.cross ? 12 : 8;
+    const int64_t tiles = int64_t((lv.g.n + 63) / 64) * ((lv.g.n + tys - 1) / tys);
+    const int nch = c->L.nchains, cap = c->L.fp32 ? 8 : 4;
+    int64_t want = int64_t(nch) * tiles / 1024;
+    cpb = int(std::max<int64_t>(1, std::min<int64_t>(cap, want)));
+    const int groups = (nch + cpb - 1) / cpb;
+    cpb = (nch + groups - 1) / groups;  // balance the chain groups
+  }
+  return mgmc::launch_sweep_seg(c->L, lv, in, out, zero_in, f, fcs, word, backward, coarse, psi,
+                                c->sweep_variant == 2 ? 1 : 0, cpb);
+}
+
 // One MGMC update of every chain (Alg. 1), enqueued on the context stream.
+// cur[l] names the buffer holding the state of level l; a tiled sweep reads
+// it and writes the other one.  The finest level ends every update in
+// buffer 0 (an odd number of sweeps there ends with an in-place sweep).
 mgmc_status enqueue_cycle(mgmc_ctx* c, const void* fL, const double* F, double* qoi, int64_t m0) {
   const mgmc::Launch& L = c->L;
   const int top = c->levels - 1, nq = 1 << c->prob.dim, beta = c->beta;
   const int nch = c->prob.nchains;
+  const bool tiled = c->tiled && c->prob.dim == 2;
+  const int nu1 = c->prob.nu1, nu2 = c->prob.nu2;
+  std::vector<int> cur(c->levels, 0);
+  auto state = [&](int l) { return c->lv[l].buf[cur[l]]; };
+  auto in_place_sweep = [&](int l, const void* f, int64_t fcs, uint32_t word, bool backward) -> mgmc_status {
+    mgmc::DevLevel& lv = c->lv[l];
+    for (int qq = 0; qq < nq; ++qq) {
+      const int q = backward ? nq - 1 - qq : qq;
+      mgmc_status st = timed(c, l == top, [&] {
+        return mgmc::launch_sweep_colour(L, lv, state(l), f, fcs, word, mgmc::forward_colour(c->prob.dim, q));
+      });
+      if (st != MGMC_OK) return st;
+    }
+    return MGMC_OK;
+  };
   if (top == 0) {
-    MGMC_LAUNCH(mgmc::launch_coarsest(L, c->lv[0], fL, 0, c->lv[0].theta, c->KT, c->UinvT));
+    MGMC_LAUNCH(mgmc::launch_coarsest(L, c->lv[0], fL, 0, state(0), c->K, c->Uinv));
   } else {
     for (int l = top; l >= 1; --l) {
       mgmc::DevLevel& lv = c->lv[l];
       const void* f = (l == top) ? fL : lv.f;
       const int64_t fcs = (l == top) ? 0 : lv.g.Np;
-      if (l < top) MGMC_LAUNCH(mgmc::launch_fill_zero(L, lv.theta, int64_t(nch) * lv.g.Np));
-      for (int j = 0; j < c->prob.nu1; ++j) {
+      const bool zero_start = l < top;  // psi^(0) = 0 on coarse levels
+      if (zero_start && !tiled) MGMC_LAUNCH(mgmc::launch_fill_zero(L, state(l), int64_t(nch) * lv.g.Np));
+      for (int j = 0; j < nu1; ++j) {
         const uint32_t word = mgmc::noise_word(l, j);
-        for (int q = 0; q < nq; ++q) {
+        if (tiled) {
+          const int zin = (zero_start && j == 0) ? 1 : 0;
           mgmc_status st = timed(c, l == top, [&] {
-            return mgmc::launch_sweep_colour(L, lv, f, fcs, word, mgmc::forward_colour(c->prob.dim, q));
+            return sweep2d(c, lv, state(l), lv.buf[1 - cur[l]], zin, f, fcs, word, 0, nullptr, nullptr);
           });
           if (st != MGMC_OK) return st;
+          cur[l] ^= 1;
+        } else {
+          mgmc_status st = in_place_sweep(l, f, fcs, word, false);
+          if (st != MGMC_OK) return st;
         }
-        if (beta) MGMC_LAUNCH(mgmc::launch_lowrank(L, lv, 0, word, beta, c->gisq, c->xi, c->u));
+        if (beta) MGMC_LAUNCH(mgmc::launch_lowrank(L, lv, state(l), 0, word, beta, c->gisq, c->xi, c->u));
       }
-      MGMC_LAUNCH(mgmc::launch_restrict(L, lv, c->lv[l - 1], f, fcs));
+      if (tiled)
+        MGMC_LAUNCH(mgmc::launch_restrict_tiled(L, lv, state(l), c->lv[l - 1], f, fcs));
+      else
+        MGMC_LAUNCH(mgmc::launch_restrict(L, lv, state(l), c->lv[l - 1], f, fcs));
       if (beta) {
-        MGMC_LAUNCH(mgmc::launch_gather_v(L, lv, beta, c->ginv, c->v));
+        MGMC_LAUNCH(mgmc::launch_gather_v(L, lv, state(l), beta, c->ginv, c->v));
         MGMC_LAUNCH(mgmc::launch_coarse_rhs_lowrank(L, c->lv[l - 1], c->v, beta));
       }
     }
-    MGMC_LAUNCH(mgmc::launch_coarsest(L, c->lv[0], c->lv[0].f, c->lv[0].g.Np, c->lv[0].theta, c->KT, c->UinvT));
+    MGMC_LAUNCH(mgmc::launch_coarsest(L, c->lv[0], c->lv[0].f, c->lv[0].g.Np, state(0), c->K, c->Uinv));
     for (int l = 1; l <= top; ++l) {
       mgmc::DevLevel& lv = c->lv[l];
       const void* f = (l == top) ? fL : lv.f;
       const int64_t fcs = (l == top) ? 0 : lv.g.Np;
-      MGMC_LAUNCH(mgmc::launch_prolong(L, lv, c->lv[l - 1]));
-      for (int j = 0; j < c->prob.nu2; ++j) {
-        const uint32_t word = mgmc::noise_word(l, c->prob.nu1 + j);
-        for (int q = nq - 1; q >= 0; --q) {
+      const void* psi = state(l - 1);
+      for (int j = 0; j < nu2; ++j) {
+        const uint32_t word = mgmc::noise_word(l, nu1 + j);
+        const bool last_in_place = l == top && ((nu1 + nu2) & 1) && j == nu2 - 1;
+        if (tiled && !last_in_place) {
+          const mgmc::DevLevel* coarse = (j == 0) ? &c->lv[l - 1] : nullptr;
           mgmc_status st = timed(c, l == top, [&] {
-            return mgmc::launch_sweep_colour(L, lv, f, fcs, word, mgmc::forward_colour(c->prob.dim, q));
+            return sweep2d(c, lv, state(l), lv.buf[1 - cur[l]], 0, f, fcs, word, 1, coarse, coarse ? psi : nullptr);
           });
           if (st != MGMC_OK) return st;
+          cur[l] ^= 1;
+        } else {
+          if (j == 0) MGMC_LAUNCH(mgmc::launch_prolong(L, lv, state(l), c->lv[l - 1], psi));
+          mgmc_status st = in_place_sweep(l, f, fcs, word, true);
+          if (st != MGMC_OK) return st;
         }
-        if (beta) MGMC_LAUNCH(mgmc::launch_lowrank(L, lv, 1, word, beta, c->gisq, c->xi, c->u));
+        if (beta) MGMC_LAUNCH(mgmc::launch_lowrank(L, lv, state(l), 1, word, beta, c->gisq, c->xi, c->u));
       }
     }
   }
-  if (qoi) MGMC_LAUNCH(mgmc::launch_qoi(L, c->lv[top], c->lv[top].theta, F, c->qpart, c->qnb, qoi, m0));
+  if (cur[top] != 0) return fail(MGMC_EDEVICE, "internal: finest state left in the second buffer");
+  if (qoi) MGMC_LAUNCH(mgmc::launch_qoi(L, c->lv[top], state(top), F, c->qpart, c->qnb, qoi, m0));
   MGMC_LAUNCH(mgmc::launch_advance_m(c->stream, c->mcur));
   return MGMC_OK;
 }
@@ -360,7 +424,7 @@ mgmc_status enqueue_cycle(mgmc_ctx* c, const void* fL, const double* F, double* 
 mgmc_status run_samples(mgmc_ctx* c, const void* fL, int64_t m0, int64_t nsamples, void* theta,
                         const double* F, double* qoi) {
   const int top = c->levels - 1;
-  MGMC_LAUNCH(mgmc::launch_unpack(c->L, c->lv[top], theta, c->lv[top].theta));
+  MGMC_LAUNCH(mgmc::launch_unpack(c->L, c->lv[top], theta, c->lv[top].buf[0]));
   MGMC_LAUNCH(mgmc::launch_set_m(c->stream, c->mcur, m0));
   if (c->use_graph && c->stream != nullptr && nsamples > 1) {
     hipGraph_t graph = nullptr;
@@ -393,7 +457,7 @@ mgmc_status run_samples(mgmc_ctx* c, const void* fL, int64_t m0, int64_t nsample
       if (s != MGMC_OK) return s;
     }
   }
-  MGMC_LAUNCH(mgmc::launch_pack(c->L, c->lv[top], c->lv[top].theta, theta));
+  MGMC_LAUNCH(mgmc::launch_pack(c->L, c->lv[top], c->lv[top].buf[0], theta));
   return MGMC_OK;
 }
 
@@ -449,8 +513,8 @@ mgmc_status mgmc_setup(const mgmc_problem* problem, const mgmc_obs* obs, void* h
   };
   for (int l = 0; l < c->levels; ++l)
     if ((s = upload_level(c, l)) != MGMC_OK) return cleanup(s);
-  if ((s = c->upload(c->KT, c->H.KT)) != MGMC_OK) return cleanup(s);
-  if ((s = c->upload(c->UinvT, c->H.UinvT)) != MGMC_OK) return cleanup(s);
+  if ((s = c->upload(c->K, c->H.K)) != MGMC_OK) return cleanup(s);
+  if ((s = c->upload(c->Uinv, c->H.Uinv)) != MGMC_OK) return cleanup(s);
   if ((s = c->alloc(c->mcur, 1)) != MGMC_OK) return cleanup(s);
   c->L.mcur = c->mcur;
   const int top = c->levels - 1;
@@ -541,6 +605,25 @@ mgmc_status mgmc_set_graph(mgmc_ctx* c, int32_t enabled) {
   if (!c) return fail(MGMC_EINVAL, "context is NULL");
   c->use_graph = enabled != 0;
   return MGMC_OK;
+}
+
+mgmc_status mgmc_set_option(mgmc_ctx* c, int32_t option, int64_t value) {
+  if (!c) return fail(MGMC_EINVAL, "context is NULL");
+  switch (option) {
+    case MGMC_OPT_TILED_SWEEPS:
+      c->tiled = value != 0;
+      return MGMC_OK;
+    case MGMC_OPT_SWEEP_VARIANT:
+      if (value < 0 || value > 2) return fail(MGMC_EINVAL, "sweep variant must be 0, 1 or 2");
+      c->sweep_variant = int(value);
+      return MGMC_OK;
+    case MGMC_OPT_CHAINS_PER_BLOCK:
+      if (value < 0 || value > 65535) return fail(MGMC_EINVAL, "chains per block out of range");
+      c->sweep_cpb = int(value);
+      return MGMC_OK;
+    default:
+      return fail(MGMC_EINVAL, "unknown option");
+  }
 }
 
 mgmc_status mgmc_set_profiling(mgmc_ctx* c, int32_t enabled) {

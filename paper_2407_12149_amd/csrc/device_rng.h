@@ -46,8 +46,9 @@ struct Gauss<double> {
     const double u1 = (double(w1 >> 11) + 0.5) * 0x1p-53;
     const double u2 = (double(w2 >> 11) + 0.5) * 0x1p-53;
     const double rad = sqrt(-2.0 * log(u1));
+    // (sin, cos)(2 pi u2) via the pi-scaled forms: exact argument reduction
     double sn, cs;
-    sincos(6.283185307179586476925 * u2, &sn, &cs);
+    sincospi(2.0 * u2, &sn, &cs);
     z0 = rad * cs;
     z1 = rad * sn;
   }

@@ -430,15 +430,14 @@ mgmc_status coarsest(HostHierarchy& H, std::string& err) {
     }
   }
   // K = Uinv Uinv^T = At_0^{-1}
-  H.KT.assign(size_t(N0) * N0, 0.0);
-  H.UinvT.assign(size_t(N0) * N0, 0.0);
+  H.K.assign(size_t(N0) * N0, 0.0);
   for (int64_t r = 0; r < N0; ++r)
     for (int64_t col = 0; col < N0; ++col) {
       double s = 0.0;
       for (int64_t k = std::max(r, col); k < N0; ++k) s += Ui[size_t(r) * N0 + k] * Ui[size_t(col) * N0 + k];
-      H.KT[size_t(col) * N0 + r] = s;
-      H.UinvT[size_t(col) * N0 + r] = Ui[size_t(r) * N0 + col];
+      H.K[size_t(r) * N0 + col] = s;
     }
+  H.Uinv = std::move(Ui);
   return MGMC_OK;
 }
 

@@ -38,8 +38,8 @@ struct HostHierarchy {
   int beta = 0;
   std::vector<double> gamma;
   // Coarsest exact sampler: theta_0 = K f_0 + U^{-1} z with At_0 = U^T U and
-  // K = At_0^{-1}; both stored transposed (column k contiguous).
-  std::vector<double> KT, UinvT;
+  // K = At_0^{-1}; both row-major.
+  std::vector<double> K, Uinv;
 };
 
 // Forward colour order (colour id c = sum_k (i_k mod 2) 2^k): even parity sum

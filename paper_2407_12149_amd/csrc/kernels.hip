@@ -12,6 +12,7 @@
 //    N(At_0^{-1} f_0, At_0^{-1}) (Sec. 3.4).
 //  * k_lowrank_*: the low-rank correction of Alg. 3 (see launch_lowrank).
 //  * k_qoi_*: q = F^T theta per chain, fixed-order reductions.
+#include "device_common.h"
 #include "device_rng.h"
 #include "mgmc_internal.h"
 
@@ -27,37 +28,6 @@ Geom make_geom(int dim, int n) {
 }
 
 namespace {
-
-constexpr int kBlock = 256;
-
-__device__ __forceinline__ int64_t pidx(const Geom& g, int i1, int i2, int i3) {
-  return int64_t(i1 + 3) + int64_t(g.px) * (int64_t(i2) + int64_t(g.py) * i3);
-}
-
-__device__ __forceinline__ int64_t poff(const Geom& g, int dx, int dy, int dz) {
-  return int64_t(dx) + int64_t(g.px) * (int64_t(dy) + int64_t(g.py) * dz);
-}
-
-template <int DIM>
-__device__ __forceinline__ void unflatten(int64_t lin, int n, int& i1, int& i2, int& i3) {
-  i1 = 1 + int(lin % n);
-  lin /= n;
-  if (DIM == 3) {
-    i2 = 1 + int(lin % n);
-    i3 = 1 + int(lin / n);
-  } else {
-    i2 = 1 + int(lin);
-    i3 = 0;
-  }
-}
-
-__device__ __forceinline__ double multilinear(int dx, int dy, int dz) {
-  double w = 1.0;
-  if (dx) w *= 0.5;
-  if (dy) w *= 0.5;
-  if (dz) w *= 0.5;
-  return w;
-}
 
 // One Gauss-Seidel site update (neighbours in ascending index order).
 template <typename T, int DIM, bool CROSS>
@@ -189,9 +159,17 @@ __global__ __launch_bounds__(kBlock) void k_prolong(T* __restrict__ theta, Geom 
   theta[int64_t(c) * gf.Np + pidx(gf, i[0], i[1], i[2])] += s;
 }
 
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// theta_0 = K f_0 + U^{-1} z: one wavefront per row, lanes split the row
+// (K and U^{-1} row-major, so a wavefront reads contiguous memory).
 template <typename T, int DIM>
-__global__ __launch_bounds__(kBlock) void k_coarsest(const double* __restrict__ KT,
-                                                     const double* __restrict__ UinvT,
+__global__ __launch_bounds__(kBlock) void k_coarsest(const double* __restrict__ K,
+                                                     const double* __restrict__ Uinv,
                                                      const T* __restrict__ f0, int64_t fcs,
                                                      T* __restrict__ theta0, Geom g, int N0,
                                                      const int64_t* __restrict__ mcur,
@@ -199,7 +177,7 @@ __global__ __launch_bounds__(kBlock) void k_coarsest(const double* __restrict__ 
   extern __shared__ double sh[];
   double* fv = sh;
   double* zv = sh + N0;
-  const int c = blockIdx.x;
+  const int c = blockIdx.y;
   const uint32_t m = uint32_t(*mcur);
   for (int k = threadIdx.x; k < N0; k += blockDim.x) {
     int i1, i2, i3;
@@ -214,18 +192,24 @@ __global__ __launch_bounds__(kBlock) void k_coarsest(const double* __restrict__ 
     if (2 * p + 1 < N0) zv[2 * p + 1] = z1;
   }
   __syncthreads();
-  for (int r = threadIdx.x; r < N0; r += blockDim.x) {
-    double s = 0.0;
-    for (int k = 0; k < N0; ++k) s += KT[int64_t(k) * N0 + r] * fv[k];
-    for (int k = r; k < N0; ++k) s += UinvT[int64_t(k) * N0 + r] * zv[k];
+  const int lane = threadIdx.x & 63;
+  const int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (r >= N0) return;
+  double s = 0.0;
+  for (int k = lane; k < N0; k += 64) {
+    s += K[int64_t(r) * N0 + k] * fv[k];
+    if (k >= r) s += Uinv[int64_t(r) * N0 + k] * zv[k];
+  }
+  s = wave_sum(s);
+  if (lane == 0) {
     int i1, i2, i3;
     unflatten<DIM>(r, g.n, i1, i2, i3);
     theta0[int64_t(c) * g.Np + pidx(g, i1, i2, i3)] = T(s);
   }
 }
 
-// Low-rank smoother, step 1 per chain: xi = Gamma^{-1/2} zeta, w = B^T theta,
-// u = w + (S - Gamma) xi.
+// Low-rank smoother (Alg. 3), step 1: xi = Gamma^{-1/2} zeta, w = B^T theta,
+// u = w + (S - Gamma) xi; one wavefront per observation j.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_lowrank_prep(const T* __restrict__ theta, int64_t Np,
                                                          int beta, const double* __restrict__ gisq,
@@ -239,29 +223,33 @@ __global__ __launch_bounds__(kBlock) void k_lowrank_prep(const T* __restrict__ t
                                                          uint32_t seed, uint32_t chain0) {
   extern __shared__ double sh[];
   double* xi = sh;
-  double* w = sh + beta;
-  const int c = blockIdx.x;
+  const int c = blockIdx.y;
   const T* th = theta + int64_t(c) * Np;
   const uint32_t m = uint32_t(*mcur);
-  for (int j = threadIdx.x; j < beta; j += blockDim.x) {
-    const Block4 blk = philox10(uint32_t(j >> 1), word, m, 1u, seed, chain0 + c);
+  for (int p = threadIdx.x; 2 * p < beta; p += blockDim.x) {
+    const Block4 blk = philox10(uint32_t(p), word, m, 1u, seed, chain0 + c);
     double z0, z1;
     Gauss<double>::pair(blk, z0, z1);
-    xi[j] = ((j & 1) ? z1 : z0) * gisq[j];
-    double acc = 0.0;
-    for (int64_t e = bptr[j]; e < bptr[j + 1]; ++e) acc += bval[e] * double(th[bidx[e]]);
-    w[j] = acc;
+    xi[2 * p] = z0 * gisq[2 * p];
+    if (2 * p + 1 < beta) xi[2 * p + 1] = z1 * gisq[2 * p + 1];
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < beta; j += blockDim.x) {
-    double acc = w[j];
-    for (int k = 0; k < beta; ++k) acc += SmG[int64_t(j) * beta + k] * xi[k];
-    xi_out[int64_t(c) * beta + j] = xi[j];
-    u_out[int64_t(c) * beta + j] = acc;
-  }
+  if (blockIdx.x == 0)
+    for (int j = threadIdx.x; j < beta; j += blockDim.x) xi_out[int64_t(c) * beta + j] = xi[j];
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (j >= beta) return;
+  double w = 0.0;
+  for (int64_t e = bptr[j] + lane; e < bptr[j + 1]; e += 64) w += bval[e] * double(th[bidx[e]]);
+  w = wave_sum(w);
+  double a = 0.0;
+  for (int k = lane; k < beta; k += 64) a += SmG[int64_t(j) * beta + k] * xi[k];
+  a = wave_sum(a);
+  if (lane == 0) u_out[int64_t(c) * beta + j] = w + a;
 }
 
-// Step 2 on the support rows: theta_r += sum_j C_rj xi_j - sum_j G_rj u_j.
+// Step 2 on the support rows: theta_r += sum_j C_rj xi_j - sum_j G_rj u_j,
+// one thread per (row, chain); C and G are shared by the chains through L2.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_lowrank_apply(T* __restrict__ theta, int64_t Np,
                                                           int beta, int nsupp,
@@ -282,6 +270,7 @@ __global__ __launch_bounds__(kBlock) void k_lowrank_apply(T* __restrict__ theta,
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nsupp) return;
   double a = 0.0, b = 0.0;
+#pragma unroll 8
   for (int j = 0; j < beta; ++j) {
     a += CT[int64_t(j) * nsupp + r] * xs[j];
     b += GT[int64_t(j) * nsupp + r] * us[j];
@@ -435,8 +424,8 @@ inline unsigned blocks_for(int64_t count) { return unsigned((count + kBlock - 1)
     }                           \
   } while (0)
 
-hipError_t launch_sweep_colour(const Launch& L, const DevLevel& lv, const void* f, int64_t fcs,
-                               uint32_t word, int colour) {
+hipError_t launch_sweep_colour(const Launch& L, const DevLevel& lv, void* theta, const void* f,
+                               int64_t fcs, uint32_t word, int colour) {
   if (L.mcur == nullptr) return hipErrorInvalidValue;
   const int n = lv.g.n;
   auto ext = [n](int p) { return p ? (n + 1) / 2 : (n - 1) / 2; };
@@ -448,22 +437,22 @@ hipError_t launch_sweep_colour(const Launch& L, const DevLevel& lv, const void* 
   MGMC_DISPATCH(L, {
     if (lv.cross)
       k_sweep<T, DIM, true><<<grid, kBlock, 0, L.stream>>>(
-          (const T*)lv.coef, (const T*)lv.invd, (const T*)lv.isqd, (T*)lv.theta, (const T*)f, fcs,
+          (const T*)lv.coef, (const T*)lv.invd, (const T*)lv.isqd, (T*)theta, (const T*)f, fcs,
           lv.g, colour, word, L.mcur, L.seed, L.chain0);
     else
       k_sweep<T, DIM, false><<<grid, kBlock, 0, L.stream>>>(
-          (const T*)lv.coef, (const T*)lv.invd, (const T*)lv.isqd, (T*)lv.theta, (const T*)f, fcs,
+          (const T*)lv.coef, (const T*)lv.invd, (const T*)lv.isqd, (T*)theta, (const T*)f, fcs,
           lv.g, colour, word, L.mcur, L.seed, L.chain0);
   });
   return hipGetLastError();
 }
 
-hipError_t launch_restrict(const Launch& L, const DevLevel& fine, const DevLevel& coarse,
-                           const void* f, int64_t fcs) {
+hipError_t launch_restrict(const Launch& L, const DevLevel& fine, const void* theta,
+                           const DevLevel& coarse, const void* f, int64_t fcs) {
   dim3 grid(blocks_for(coarse.N), L.nchains);
   MGMC_DISPATCH(L, {
     const T* cf = (const T*)fine.coef;
-    const T* th = (const T*)fine.theta;
+    const T* th = (const T*)theta;
     T* out = (T*)coarse.f;
     if (fine.wP) {
       if (fine.cross)
@@ -480,53 +469,57 @@ hipError_t launch_restrict(const Launch& L, const DevLevel& fine, const DevLevel
   return hipGetLastError();
 }
 
-hipError_t launch_prolong(const Launch& L, const DevLevel& fine, const DevLevel& coarse) {
+hipError_t launch_prolong(const Launch& L, const DevLevel& fine, void* theta,
+                          const DevLevel& coarse, const void* psi) {
   dim3 grid(blocks_for(fine.N), L.nchains);
   MGMC_DISPATCH(L, {
     if (fine.wP)
-      k_prolong<T, DIM, true><<<grid, kBlock, 0, L.stream>>>((T*)fine.theta, fine.g, (const T*)coarse.theta, coarse.g, fine.wP);
+      k_prolong<T, DIM, true><<<grid, kBlock, 0, L.stream>>>((T*)theta, fine.g, (const T*)psi, coarse.g, fine.wP);
     else
-      k_prolong<T, DIM, false><<<grid, kBlock, 0, L.stream>>>((T*)fine.theta, fine.g, (const T*)coarse.theta, coarse.g, nullptr);
+      k_prolong<T, DIM, false><<<grid, kBlock, 0, L.stream>>>((T*)theta, fine.g, (const T*)psi, coarse.g, nullptr);
   });
   return hipGetLastError();
 }
 
 hipError_t launch_coarsest(const Launch& L, const DevLevel& lv0, const void* f0, int64_t fcs,
-                           void* theta0, const double* KT, const double* UinvT) {
+                           void* theta0, const double* K, const double* Uinv) {
   if (L.mcur == nullptr) return hipErrorInvalidValue;
   const int N0 = int(lv0.N);
   const size_t shmem = size_t(2) * N0 * sizeof(double);
+  dim3 grid(unsigned((N0 + 3) / 4), unsigned(L.nchains));
   MGMC_DISPATCH(L, {
-    k_coarsest<T, DIM><<<L.nchains, kBlock, shmem, L.stream>>>(KT, UinvT, (const T*)f0, fcs, (T*)theta0, lv0.g, N0, L.mcur, L.seed, L.chain0);
+    k_coarsest<T, DIM><<<grid, kBlock, shmem, L.stream>>>(K, Uinv, (const T*)f0, fcs, (T*)theta0, lv0.g, N0, L.mcur, L.seed, L.chain0);
   });
   return hipGetLastError();
 }
 
-hipError_t launch_lowrank(const Launch& L, const DevLevel& lv, int dir, uint32_t word, int beta,
-                          const double* gisq, double* xi, double* u) {
+hipError_t launch_lowrank(const Launch& L, const DevLevel& lv, void* theta, int dir, uint32_t word,
+                          int beta, const double* gisq, double* xi, double* u) {
   if (L.mcur == nullptr) return hipErrorInvalidValue;
-  const size_t shmem = size_t(2) * beta * sizeof(double);
+  dim3 pgrid(unsigned((beta + 3) / 4), unsigned(L.nchains));
+  const size_t pshm = size_t(beta) * sizeof(double);
   if (L.fp32) {
-    k_lowrank_prep<float><<<L.nchains, kBlock, shmem, L.stream>>>((const float*)lv.theta, lv.g.Np, beta, gisq, lv.bptr, lv.bidx, lv.bval, lv.SmG[dir], xi, u, word, L.mcur, L.seed, L.chain0);
+    k_lowrank_prep<float><<<pgrid, kBlock, pshm, L.stream>>>((const float*)theta, lv.g.Np, beta, gisq, lv.bptr, lv.bidx, lv.bval, lv.SmG[dir], xi, u, word, L.mcur, L.seed, L.chain0);
   } else {
-    k_lowrank_prep<double><<<L.nchains, kBlock, shmem, L.stream>>>((const double*)lv.theta, lv.g.Np, beta, gisq, lv.bptr, lv.bidx, lv.bval, lv.SmG[dir], xi, u, word, L.mcur, L.seed, L.chain0);
+    k_lowrank_prep<double><<<pgrid, kBlock, pshm, L.stream>>>((const double*)theta, lv.g.Np, beta, gisq, lv.bptr, lv.bidx, lv.bval, lv.SmG[dir], xi, u, word, L.mcur, L.seed, L.chain0);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || lv.nsupp[dir] == 0) return e;
-  dim3 grid(blocks_for(lv.nsupp[dir]), L.nchains);
+  const size_t ashm = size_t(2) * beta * sizeof(double);
+  dim3 agrid(blocks_for(lv.nsupp[dir]), unsigned(L.nchains));
   if (L.fp32)
-    k_lowrank_apply<float><<<grid, kBlock, shmem, L.stream>>>((float*)lv.theta, lv.g.Np, beta, lv.nsupp[dir], lv.supp[dir], lv.CT[dir], lv.GT[dir], xi, u);
+    k_lowrank_apply<float><<<agrid, kBlock, ashm, L.stream>>>((float*)theta, lv.g.Np, beta, lv.nsupp[dir], lv.supp[dir], lv.CT[dir], lv.GT[dir], xi, u);
   else
-    k_lowrank_apply<double><<<grid, kBlock, shmem, L.stream>>>((double*)lv.theta, lv.g.Np, beta, lv.nsupp[dir], lv.supp[dir], lv.CT[dir], lv.GT[dir], xi, u);
+    k_lowrank_apply<double><<<agrid, kBlock, ashm, L.stream>>>((double*)theta, lv.g.Np, beta, lv.nsupp[dir], lv.supp[dir], lv.CT[dir], lv.GT[dir], xi, u);
   return hipGetLastError();
 }
 
-hipError_t launch_gather_v(const Launch& L, const DevLevel& lv, int beta, const double* ginv,
-                           double* v) {
+hipError_t launch_gather_v(const Launch& L, const DevLevel& lv, const void* theta, int beta,
+                           const double* ginv, double* v) {
   if (L.fp32)
-    k_gather_v<float><<<L.nchains, kBlock, 0, L.stream>>>((const float*)lv.theta, lv.g.Np, beta, lv.bptr, lv.bidx, lv.bval, ginv, v);
+    k_gather_v<float><<<L.nchains, kBlock, 0, L.stream>>>((const float*)theta, lv.g.Np, beta, lv.bptr, lv.bidx, lv.bval, ginv, v);
   else
-    k_gather_v<double><<<L.nchains, kBlock, 0, L.stream>>>((const double*)lv.theta, lv.g.Np, beta, lv.bptr, lv.bidx, lv.bval, ginv, v);
+    k_gather_v<double><<<L.nchains, kBlock, 0, L.stream>>>((const double*)theta, lv.g.Np, beta, lv.bptr, lv.bidx, lv.bval, ginv, v);
   return hipGetLastError();
 }
 

@@ -1,0 +1,517 @@
+// LDS-tiled 2D kernels: one launch per smoother sweep and per restriction.
+//
+// k_sweep2d_tiled runs every colour pass of one random Gauss-Seidel sweep
+// (Alg. 2/3 with M = D + L in colour order) on a TX x TY tile held in LDS
+// with a halo of NPASS sites: pass p updates the tile plus a ring of
+// NPASS-1-p sites, so after the last pass the tile interior is exactly what
+// NPASS global passes would give (neighbouring tiles recompute the shared
+// ring identically: the noise is counter-based).  NPASS = 2 is red-black on
+// the 5-point finest stencil (colours of equal parity sum never couple), 4 is
+// the four-colour order on 9-point Galerkin stencils.  Each block loops over
+// a group of chains, so the operator is read from HBM once per sweep and hit
+// in cache for the remaining chains.  With PROLONG the coarse-grid correction
+// theta += P psi (Alg. 1, prolongation step) is applied while the tile is
+// loaded, fusing it into the post-smoother.
+//
+// k_restrict2d_tiled computes f_{l-1} = P^T (f_l - A_l theta) (Alg. 1,
+// restriction step) for a tile of coarse nodes from fine residuals staged
+// in LDS.
+#include "device_common.h"
+#include "device_rng.h"
+#include "mgmc_internal.h"
+
+namespace mgmc {
+
+namespace {
+
+constexpr int kFwdOrder2[4] = {0, 3, 1, 2};
+
+template <typename T, bool USERP>
+__device__ __forceinline__ T prolong_at(const T* __restrict__ ps, const Geom& gc,
+                                        const double* __restrict__ wP, int x, int y) {
+  int Jx[2], Dx[2], Jy[2], Dy[2];
+  int nx, ny;
+  if ((x & 1) == 0) {
+    Jx[0] = x >> 1; Dx[0] = 0; nx = 1;
+  } else {
+    Jx[0] = (x - 1) >> 1; Dx[0] = 1; Jx[1] = (x + 1) >> 1; Dx[1] = -1; nx = 2;
+  }
+  if ((y & 1) == 0) {
+    Jy[0] = y >> 1; Dy[0] = 0; ny = 1;
+  } else {
+    Jy[0] = (y - 1) >> 1; Dy[0] = 1; Jy[1] = (y + 1) >> 1; Dy[1] = -1; ny = 2;
+  }
+  T s = T(0);
+  for (int ay = 0; ay < ny; ++ay)
+    for (int ax = 0; ax < nx; ++ax) {
+      const int64_t jc = pidx(gc, Jx[ax], Jy[ay], 0);
+      T w;
+      if (USERP)
+        w = T(wP[int64_t((Dx[ax] + 1) + 3 * (Dy[ay] + 1)) * gc.Np + jc]);
+      else
+        w = T(multilinear(Dx[ax], Dy[ay], 0));
+      s += w * ps[jc];
+    }
+  return s;
+}
+
+// LDS layout of a tile row: four sub-rows by x mod 4, each of odd length W,
+// so the lanes of a wavefront (pairs four sites apart, the same x mod 4)
+// read consecutive words and neighbour reads are free of bank conflicts.
+template <int RX>
+struct Swz {
+  static constexpr int W = ((RX + 3) / 4) | 1;
+  static constexpr int RS = 4 * W;  // row stride
+  static __device__ __forceinline__ int pos(int lx, int ly) { return ly * RS + (lx & 3) * W + (lx >> 2); }
+  // offsets of the x-neighbours of a site with lx & 3 == s
+  static __device__ __forceinline__ int east(int s) { return s < 3 ? W : 1 - 3 * W; }
+  static __device__ __forceinline__ int west(int s) { return s > 0 ? -W : 3 * W - 1; }
+};
+
+template <typename T, int NPASS, bool PROLONG, bool USERP, int TX, int TY>
+__global__ __launch_bounds__(kBlock) void k_sweep2d_tiled(
+    const T* __restrict__ coef, const T* __restrict__ invd, const T* __restrict__ isqd,
+    const T* __restrict__ theta_in, T* __restrict__ theta_out, int zero_in,
+    const T* __restrict__ f, int64_t fcs, Geom g,
+    const T* __restrict__ psi, Geom gc, const double* __restrict__ wP, int backward,
+    uint32_t word, const int64_t* __restrict__ mcur, uint32_t seed, uint32_t chain0, int tiles_x,
+    int cpb, int nchains) {
+  constexpr bool CROSS = (NPASS == 2);
+  constexpr int H = NPASS, RX = TX + 2 * H, RY = TY + 2 * H;
+  constexpr int Q = RX / 4 + 2;  // pair slots per row
+  using Z = Swz<RX>;
+  __shared__ T sh[RY * Z::RS];
+  const int n = g.n;
+  const int tx0 = int(blockIdx.x % tiles_x) * TX + 1;
+  const int ty0 = int(blockIdx.x / tiles_x) * TY + 1;
+  const int ox = tx0 - H, oy = ty0 - H;
+  const uint32_t m = uint32_t(*mcur);
+  const int cb = int(blockIdx.y) * cpb;
+  const int ce = min(nchains, cb + cpb);
+  for (int c = cb; c < ce; ++c) {
+    const T* thi = theta_in + int64_t(c) * g.Np;
+    T* tho = theta_out + int64_t(c) * g.Np;
+    const T* fc = f ? f + int64_t(c) * fcs : nullptr;
+    for (int idx = threadIdx.x; idx < RX * RY; idx += blockDim.x) {
+      const int x = ox + idx % RX, y = oy + idx / RX;
+      T v = T(0);
+      if (x >= 1 && x <= n && y >= 1 && y <= n) {
+        if (!zero_in) v = thi[pidx(g, x, y, 0)];
+        if (PROLONG) v += prolong_at<T, USERP>(psi + int64_t(c) * gc.Np, gc, wP, x, y);
+      }
+      sh[Z::pos(idx % RX, idx / RX)] = v;
+    }
+    __syncthreads();
+    for (int p = 0; p < NPASS; ++p) {
+      const int pos = backward ? NPASS - 1 - p : p;  // position in the forward order
+      const int hp = NPASS - 1 - p;
+      const int xlo = max(1, tx0 - hp), xhi = min(n, tx0 + TX - 1 + hp);
+      const int ylo = max(1, ty0 - hp), yhi = min(n, ty0 + TY - 1 + hp);
+      const int nrows = yhi - ylo + 1;
+      if (xlo <= xhi && nrows > 0) {
+        for (int item = threadIdx.x; item < nrows * Q; item += blockDim.x) {
+          const int y = ylo + item / Q;
+          const int qi = item % Q;
+          int colour;
+          if (NPASS == 2) {
+            const int ypar = y & 1;
+            const int xpar = (pos == 0) ? ypar : 1 - ypar;  // red (equal parities) first
+            colour = xpar | (ypar << 1);
+          } else {
+            colour = kFwdOrder2[pos];
+            if (((colour >> 1) & 1) != (y & 1)) continue;
+          }
+          const int xpar = colour & 1;
+          const int off = xpar ? 1 : 2;
+          const int q = (xlo - off + 5) / 4 - 1 + qi;  // first pair whose second site >= xlo
+          const int xa = 4 * q + off;
+          if (xa > xhi) continue;
+          // Issue every global load of the pair first (addresses clamped into the
+          // pass region so the loads are unconditional); the Philox and
+          // Box-Muller arithmetic below then hides their latency.
+          constexpr int NB = CROSS ? 4 : 8;
+          T cf[2][NB], rhs[2], ivd[2], isd[2];
+          int64_t gi[2];
+          int li[2];
+          bool live[2];
+#pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            const int x = xa + 2 * k;
+            live[k] = x >= xlo && x <= xhi;
+            const int xc = min(max(x, xlo), xhi);
+            gi[k] = pidx(g, xc, y, 0);
+            li[k] = Z::pos(xc - ox, y - oy);
+            rhs[k] = fc ? fc[gi[k]] : T(0);
+            int b = 0;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+              const int dx = t % 3 - 1, dy = t / 3 - 1;
+              if (dx == 0 && dy == 0) continue;
+              if (CROSS && dx != 0 && dy != 0) continue;
+              cf[k][b++] = coef[int64_t(t) * g.Np + gi[k]];
+            }
+            ivd[k] = invd[gi[k]];
+            isd[k] = isqd[gi[k]];
+          }
+          const int m1 = xpar ? (n + 1) / 2 : (n - 1) / 2;
+          const int qx = (m1 + 1) / 2;
+          const uint32_t pair = uint32_t(q) + uint32_t(qx) * uint32_t((y - 1) >> 1);
+          const Block4 blk = philox10(pair, word | uint32_t(colour), m, 0u, seed, chain0 + c);
+          T z[2];
+          Gauss<T>::pair(blk, z[0], z[1]);
+          // the two sites are two apart in x, so they sit in different sub-rows
+#pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            if (!live[k]) continue;
+            const int sx = (xa + 2 * k - ox) & 3;
+            const int oe = Z::east(sx), ow = Z::west(sx);
+            T s = rhs[k];
+            int b = 0;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+              const int dx = t % 3 - 1, dy = t / 3 - 1;
+              if (dx == 0 && dy == 0) continue;
+              if (CROSS && dx != 0 && dy != 0) continue;
+              const int o = dy * Z::RS + (dx < 0 ? ow : (dx > 0 ? oe : 0));
+              s -= cf[k][b++] * sh[li[k] + o];
+            }
+            sh[li[k]] = s * ivd[k] + z[k] * isd[k];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    for (int idx = threadIdx.x; idx < TX * TY; idx += blockDim.x) {
+      const int x = tx0 + idx % TX, y = ty0 + idx / TX;
+      if (x <= n && y <= n) tho[pidx(g, x, y, 0)] = sh[Z::pos(x - ox, y - oy)];
+    }
+    __syncthreads();
+  }
+}
+
+// Segment form of the tiled sweep.  Thread (sy, sx) owns the four sites
+// x = 4q+1 .. 4q+4 of one row; such a segment holds exactly one Philox pair
+// of each colour present in its row.  The thread loads its segment's stencil
+// (and the shared right-hand side) once per block into registers with
+// contiguous loads, and reuses them for every colour pass and every chain of
+// the block; only the states go through LDS.  Rows cover the tile plus
+// NPASS-1 halo rows, segments the tile plus one segment either side.
+template <typename T, int NPASS, bool PROLONG, bool USERP, int TYS, int NT>
+__global__ __launch_bounds__(NT) void k_sweep2d_seg(
+    const T* __restrict__ coef, const T* __restrict__ invd, const T* __restrict__ isqd,
+    const T* __restrict__ theta_in, T* __restrict__ theta_out, int zero_in,
+    const T* __restrict__ f, int64_t fcs, Geom g,
+    const T* __restrict__ psi, Geom gc, const double* __restrict__ wP, int backward,
+    uint32_t word, const int64_t* __restrict__ mcur, uint32_t seed, uint32_t chain0, int tiles_x,
+    int cpb, int nchains) {
+  constexpr bool CROSS = (NPASS == 2);
+  constexpr int TX = 64, SX = TX / 4 + 2;       // segments per row (tile + one each side)
+  constexpr int SY = TYS + 2 * (NPASS - 1);     // rows with owners
+  constexpr int HALF = SY / 2;                  // rows of each parity
+  constexpr int GA = (HALF * SX + 63) / 64 * 64;  // threads of the first parity group
+  constexpr int H = NPASS, RX = TX + 2 * H, RY = TYS + 2 * H;
+  constexpr int NB = CROSS ? 4 : 8;
+  static_assert(SY % 2 == 0, "owner rows must split evenly by parity");
+  static_assert(GA + HALF * SX <= NT, "block too small for the segment grid");
+  using Z = Swz<RX>;
+  __shared__ T sh[RY * Z::RS];
+  const int n = g.n;
+  const int tx0 = int(blockIdx.x % tiles_x) * TX + 1;
+  const int ty0 = int(blockIdx.x / tiles_x) * TYS + 1;
+  const int ox = tx0 - H, oy = ty0 - H;
+  const uint32_t m = uint32_t(*mcur);
+  // Owners grouped by row parity (each group starts on a wavefront boundary)
+  // so that every wavefront updates a single colour in each pass.
+  const int y0 = ty0 - (NPASS - 1);
+  const int grp = int(threadIdx.x) < GA ? 0 : 1;
+  const int u = int(threadIdx.x) - grp * GA;
+  const int sx = u % SX, srow = u / SX;
+  const bool owner = srow < HALF;
+  const int par0 = (y0 & 1);  // row offset of the group whose rows are even
+  const int r = 2 * srow + (grp == 0 ? par0 : 1 - par0);
+  const int q = (tx0 - 1) / 4 - 1 + sx;  // segment index: sites 4q+1 .. 4q+4
+  const int y = y0 + r;
+  const bool row_in = owner && y >= 1 && y <= n;
+  // stencil of the four sites in registers (zero outside the grid)
+  T cf[4][NB], ivd[4], isd[4], rhs[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int x = 4 * q + 1 + k;
+    const bool in = row_in && x >= 1 && x <= n;
+    const int64_t gi = in ? pidx(g, x, y, 0) : 0;
+    int b = 0;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int dx = t % 3 - 1, dy = t / 3 - 1;
+      if (dx == 0 && dy == 0) continue;
+      if (CROSS && dx != 0 && dy != 0) continue;
+      cf[k][b++] = in ? coef[int64_t(t) * g.Np + gi] : T(0);
+    }
+    ivd[k] = in ? invd[gi] : T(0);
+    isd[k] = in ? isqd[gi] : T(0);
+    rhs[k] = (in && f && fcs == 0) ? f[gi] : T(0);
+  }
+  const int cb = int(blockIdx.y) * cpb;
+  const int ce = min(nchains, cb + cpb);
+  for (int c = cb; c < ce; ++c) {
+    const T* thi = theta_in + int64_t(c) * g.Np;
+    T* tho = theta_out + int64_t(c) * g.Np;
+    if (f && fcs != 0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int x = 4 * q + 1 + k;
+        rhs[k] = (row_in && x >= 1 && x <= n) ? f[int64_t(c) * fcs + pidx(g, x, y, 0)] : T(0);
+      }
+    }
+    for (int idx = threadIdx.x; idx < RX * RY; idx += NT) {
+      const int xx = ox + idx % RX, yy = oy + idx / RX;
+      T v = T(0);
+      if (xx >= 1 && xx <= n && yy >= 1 && yy <= n) {
+        if (!zero_in) v = thi[pidx(g, xx, yy, 0)];
+        if (PROLONG) v += prolong_at<T, USERP>(psi + int64_t(c) * gc.Np, gc, wP, xx, yy);
+      }
+      sh[Z::pos(idx % RX, idx / RX)] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < NPASS; ++p) {
+      const int pos = backward ? NPASS - 1 - p : p;
+      const int hp = NPASS - 1 - p;
+      int colour;
+      if (NPASS == 2) {
+        const int ypar = y & 1;
+        colour = (pos == 0 ? ypar : 1 - ypar) | (ypar << 1);
+      } else {
+        colour = kFwdOrder2[pos];
+      }
+      const bool active = row_in && y >= ty0 - hp && y <= ty0 + TYS - 1 + hp &&
+                          (NPASS == 2 || ((colour >> 1) & 1) == (y & 1));
+      if (active) {
+        const int xpar = colour & 1;
+        const int k0 = xpar ? 0 : 1;  // offset of the colour's first site in the segment
+        const int m1 = xpar ? (n + 1) / 2 : (n - 1) / 2;
+        const int qx = (m1 + 1) / 2;
+        const uint32_t pair = uint32_t(q) + uint32_t(qx) * uint32_t((y - 1) >> 1);
+        const Block4 blk = philox10(pair, word | uint32_t(colour), m, 0u, seed, chain0 + c);
+        T z[2];
+        Gauss<T>::pair(blk, z[0], z[1]);
+        const int xlo = max(1, tx0 - hp), xhi = min(n, tx0 + TX - 1 + hp);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+#pragma unroll
+          for (int kk = 0; kk < 2; ++kk) {  // resolve the site index at compile time
+            if (kk != k0) continue;
+            const int k = kk + 2 * j;
+            const int x = 4 * q + 1 + k;
+            if (x < xlo || x > xhi) continue;
+            const int lx = x - ox;
+            const int li = Z::pos(lx, y - oy);
+            const int sxm = lx & 3;
+            const int oe = Z::east(sxm), ow = Z::west(sxm);
+            T s = rhs[k];
+            int b = 0;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+              const int dx = t % 3 - 1, dy = t / 3 - 1;
+              if (dx == 0 && dy == 0) continue;
+              if (CROSS && dx != 0 && dy != 0) continue;
+              const int o = dy * Z::RS + (dx < 0 ? ow : (dx > 0 ? oe : 0));
+              s -= cf[k][b++] * sh[li + o];
+            }
+            sh[li] = s * ivd[k] + z[j] * isd[k];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (row_in && sx >= 1 && sx <= TX / 4 && y >= ty0 && y <= ty0 + TYS - 1) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int x = 4 * q + 1 + k;
+        if (x <= n) tho[pidx(g, x, y, 0)] = sh[Z::pos(x - ox, y - oy)];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, bool CROSS, bool USERP, int CTX, int CTY>
+__global__ __launch_bounds__(kBlock) void k_restrict2d_tiled(
+    const T* __restrict__ coef, const T* __restrict__ theta, const T* __restrict__ f, int64_t fcs,
+    Geom gf, T* __restrict__ fcoarse, Geom gc, const double* __restrict__ wP, int tiles_x, int cpb,
+    int nchains) {
+  constexpr int RXr = 2 * CTX + 1, RYr = 2 * CTY + 1;  // fine residual region
+  constexpr int RXt = RXr + 2, RYt = RYr + 2;          // theta region (one more ring)
+  __shared__ T sth[RYt * RXt];
+  __shared__ T sr[RYr * RXr];
+  const int nf = gf.n, nc = gc.n;
+  const int cx0 = int(blockIdx.x % tiles_x) * CTX + 1;
+  const int cy0 = int(blockIdx.x / tiles_x) * CTY + 1;
+  const int rx0 = 2 * cx0 - 1, ry0 = 2 * cy0 - 1;  // residual region origin
+  const int tx0 = rx0 - 1, ty0 = ry0 - 1;          // theta region origin
+  const int cb = int(blockIdx.y) * cpb;
+  const int ce = min(nchains, cb + cpb);
+  for (int c = cb; c < ce; ++c) {
+    const T* th = theta + int64_t(c) * gf.Np;
+    const T* fc = f ? f + int64_t(c) * fcs : nullptr;
+    for (int idx = threadIdx.x; idx < RXt * RYt; idx += blockDim.x) {
+      const int x = tx0 + idx % RXt, y = ty0 + idx / RXt;
+      sth[idx] = (x >= 1 && x <= nf && y >= 1 && y <= nf) ? th[pidx(gf, x, y, 0)] : T(0);
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < RXr * RYr; idx += blockDim.x) {
+      const int lx = idx % RXr, ly = idx / RXr;
+      const int x = rx0 + lx, y = ry0 + ly;
+      T r = T(0);
+      if (x >= 1 && x <= nf && y >= 1 && y <= nf) {
+        const int64_t gi = pidx(gf, x, y, 0);
+        const int li = (ly + 1) * RXt + (lx + 1);
+        r = fc ? fc[gi] : T(0);
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+          const int dx = t % 3 - 1, dy = t / 3 - 1;
+          if (CROSS && dx != 0 && dy != 0) continue;
+          r -= coef[int64_t(t) * gf.Np + gi] * sth[li + dy * RXt + dx];
+        }
+      }
+      sr[idx] = r;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < CTX * CTY; idx += blockDim.x) {
+      const int J1 = cx0 + idx % CTX, J2 = cy0 + idx / CTX;
+      if (J1 > nc || J2 > nc) continue;
+      const int64_t iJ = pidx(gc, J1, J2, 0);
+      const int lx = 2 * (J1 - cx0) + 1, ly = 2 * (J2 - cy0) + 1;  // residual-region coords of 2J
+      T acc = T(0);
+#pragma unroll
+      for (int t1 = 0; t1 < 9; ++t1) {
+        const int ex = t1 % 3 - 1, ey = t1 / 3 - 1;
+        const T w = USERP ? T(wP[int64_t(t1) * gc.Np + iJ]) : T(multilinear(ex, ey, 0));
+        acc += w * sr[(ly + ey) * RXr + (lx + ex)];
+      }
+      fcoarse[int64_t(c) * gc.Np + iJ] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+constexpr int kTX = 64, kTY = 32;  // sweep tile
+constexpr int kCTX = 32, kCTY = 16;  // restriction tile (coarse nodes)
+
+int chains_per_block(int nchains, int64_t tiles) {
+  // enough blocks to cover the 256 compute units several times over, while
+  // keeping chains together so the operator stays cache-resident
+  int64_t cpb = (int64_t(nchains) * tiles) / 2048;
+  if (cpb < 1) cpb = 1;
+  if (cpb > nchains) cpb = nchains;
+  return int(cpb);
+}
+
+}  // namespace
+
+hipError_t launch_sweep_tiled(const Launch& L, const DevLevel& lv, const void* theta_in,
+                              void* theta_out, int zero_in, const void* f, int64_t fcs,
+                              uint32_t word, int backward, const DevLevel* coarse, const void* psi) {
+  if (L.mcur == nullptr || L.dim != 2 || theta_in == theta_out) return hipErrorInvalidValue;
+  if (coarse != nullptr && psi == nullptr) return hipErrorInvalidValue;
+  const int n = lv.g.n;
+  const int tiles_x = (n + kTX - 1) / kTX, tiles_y = (n + kTY - 1) / kTY;
+  const int64_t tiles = int64_t(tiles_x) * tiles_y;
+  const int cpb = chains_per_block(L.nchains, tiles);
+  dim3 grid(unsigned(tiles), unsigned((L.nchains + cpb - 1) / cpb));
+  const bool pro = coarse != nullptr;
+  const bool userp = pro && lv.wP != nullptr;
+  const Geom gc = pro ? coarse->g : Geom{};
+#define MGMC_SWEEP_T(T, NP, PR, UP)                                                                  \
+  k_sweep2d_tiled<T, NP, PR, UP, kTX, kTY><<<grid, kBlock, 0, L.stream>>>(                          \
+      (const T*)lv.coef, (const T*)lv.invd, (const T*)lv.isqd, (const T*)theta_in, (T*)theta_out,     \
+      zero_in, (const T*)f, fcs, lv.g, (const T*)psi, gc, userp ? lv.wP : nullptr, backward, word,     \
+      L.mcur,                                                                                          \
+      L.seed, L.chain0, tiles_x, cpb, L.nchains)
+#define MGMC_SWEEP_NP(T, NP)                      \
+  do {                                            \
+    if (!pro) MGMC_SWEEP_T(T, NP, false, false);  \
+    else if (!userp) MGMC_SWEEP_T(T, NP, true, false); \
+    else MGMC_SWEEP_T(T, NP, true, true);         \
+  } while (0)
+  if (L.fp32) {
+    if (lv.cross) MGMC_SWEEP_NP(float, 2); else MGMC_SWEEP_NP(float, 4);
+  } else {
+    if (lv.cross) MGMC_SWEEP_NP(double, 2); else MGMC_SWEEP_NP(double, 4);
+  }
+#undef MGMC_SWEEP_NP
+#undef MGMC_SWEEP_T
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_seg(const Launch& L, const DevLevel& lv, const void* theta_in,
+                            void* theta_out, int zero_in, const void* f, int64_t fcs,
+                            uint32_t word, int backward, const DevLevel* coarse, const void* psi,
+                            int variant, int cpb_override) {
+  if (L.mcur == nullptr || L.dim != 2 || theta_in == theta_out) return hipErrorInvalidValue;
+  if (coarse != nullptr && psi == nullptr) return hipErrorInvalidValue;
+  const int n = lv.g.n;
+  const bool big = variant == 1;
+  const int tys = lv.cross ? (big ? 26 : 12) : (big ? 22 : 8);
+  const int nt = big ? 512 : 256;
+  const int tiles_x = (n + 63) / 64, tiles_y = (n + tys - 1) / tys;
+  const int64_t tiles = int64_t(tiles_x) * tiles_y;
+  int cpb = cpb_override > 0 ? cpb_override : chains_per_block(L.nchains, tiles);
+  if (cpb > L.nchains) cpb = L.nchains;
+  dim3 grid(unsigned(tiles), unsigned((L.nchains + cpb - 1) / cpb));
+  const bool pro = coarse != nullptr;
+  const bool userp = pro && lv.wP != nullptr;
+  const Geom gc = pro ? coarse->g : Geom{};
+#define MGMC_SEG_T(T, NP, PR, UP, TYS, NT)                                                           \
+  k_sweep2d_seg<T, NP, PR, UP, TYS, NT><<<grid, NT, 0, L.stream>>>(                                 \
+      (const T*)lv.coef, (const T*)lv.invd, (const T*)lv.isqd, (const T*)theta_in, (T*)theta_out,     \
+      zero_in, (const T*)f, fcs, lv.g, (const T*)psi, gc, userp ? lv.wP : nullptr, backward, word,     \
+      L.mcur, L.seed, L.chain0, tiles_x, cpb, L.nchains)
+#define MGMC_SEG_NP(T, NP, TYS, NT)                             \
+  do {                                                          \
+    if (!pro) MGMC_SEG_T(T, NP, false, false, TYS, NT);         \
+    else if (!userp) MGMC_SEG_T(T, NP, true, false, TYS, NT);   \
+    else MGMC_SEG_T(T, NP, true, true, TYS, NT);                \
+  } while (0)
+#define MGMC_SEG_V(T)                                                   \
+  do {                                                                  \
+    if (lv.cross) {                                                     \
+      if (big) MGMC_SEG_NP(T, 2, 26, 512); else MGMC_SEG_NP(T, 2, 12, 256); \
+    } else {                                                            \
+      if (big) MGMC_SEG_NP(T, 4, 22, 512); else MGMC_SEG_NP(T, 4, 8, 256);  \
+    }                                                                   \
+  } while (0)
+  (void)tys;
+  (void)nt;
+  if (L.fp32) MGMC_SEG_V(float); else MGMC_SEG_V(double);
+#undef MGMC_SEG_V
+#undef MGMC_SEG_NP
+#undef MGMC_SEG_T
+  return hipGetLastError();
+}
+
+hipError_t launch_restrict_tiled(const Launch& L, const DevLevel& fine, const void* theta,
+                                 const DevLevel& coarse, const void* f, int64_t fcs) {
+  if (L.dim != 2) return hipErrorInvalidValue;
+  const int nc = coarse.g.n;
+  const int tiles_x = (nc + kCTX - 1) / kCTX, tiles_y = (nc + kCTY - 1) / kCTY;
+  const int64_t tiles = int64_t(tiles_x) * tiles_y;
+  const int cpb = chains_per_block(L.nchains, tiles);
+  dim3 grid(unsigned(tiles), unsigned((L.nchains + cpb - 1) / cpb));
+  const bool userp = fine.wP != nullptr;
+#define MGMC_RESTRICT_T(T, CR, UP)                                                              \
+  k_restrict2d_tiled<T, CR, UP, kCTX, kCTY><<<grid, kBlock, 0, L.stream>>>(                     \
+      (const T*)fine.coef, (const T*)theta, (const T*)f, fcs, fine.g, (T*)coarse.f, coarse.g,       \
+      fine.wP, tiles_x, cpb, L.nchains)
+  if (L.fp32) {
+    if (fine.cross) { if (userp) MGMC_RESTRICT_T(float, true, true); else MGMC_RESTRICT_T(float, true, false); }
+    else { if (userp) MGMC_RESTRICT_T(float, false, true); else MGMC_RESTRICT_T(float, false, false); }
+  } else {
+    if (fine.cross) { if (userp) MGMC_RESTRICT_T(double, true, true); else MGMC_RESTRICT_T(double, true, false); }
+    else { if (userp) MGMC_RESTRICT_T(double, false, true); else MGMC_RESTRICT_T(double, false, false); }
+  }
+#undef MGMC_RESTRICT_T
+  return hipGetLastError();
+}
+
+}  // namespace mgmc

@@ -30,7 +30,8 @@ struct DevLevel {
   void* invd = nullptr;          // [Np] 1 / A_ii
   void* isqd = nullptr;          // [Np] 1 / sqrt(A_ii)
   double* wP = nullptr;          // [S][Np of level l-1] user prolongation into this level
-  void* theta = nullptr;         // [nchains][Np]
+  void* buf[2] = {nullptr, nullptr};  // two [nchains][Np] state buffers: tiled sweeps read
+                                      // one and write the other (halos stay pre-sweep)
   void* f = nullptr;             // [nchains][Np] (levels below the finest)
   // observations B_l: columns (for B^T theta) and rows (for coarse rhs)
   int64_t* bptr = nullptr;       // [beta + 1]
@@ -62,17 +63,35 @@ struct Launch {
 // Noise counter word 1: level << 8 | sweep << 4 | colour.
 inline uint32_t noise_word(int level, int sigma) { return (uint32_t(level) << 8) | (uint32_t(sigma) << 4); }
 
-hipError_t launch_sweep_colour(const Launch& L, const DevLevel& lv, const void* f, int64_t fcs,
-                               uint32_t word, int colour);
-hipError_t launch_restrict(const Launch& L, const DevLevel& fine, const DevLevel& coarse,
-                           const void* f, int64_t fcs);
-hipError_t launch_prolong(const Launch& L, const DevLevel& fine, const DevLevel& coarse);
+// One colour pass, in place on theta.
+hipError_t launch_sweep_colour(const Launch& L, const DevLevel& lv, void* theta, const void* f,
+                               int64_t fcs, uint32_t word, int colour);
+// LDS-tiled 2D sweep (all colour passes in one launch) from theta_in into
+// theta_out (distinct buffers).  zero_in: the input state is zero (not read).
+// coarse != nullptr adds the prolongation P psi of the coarse state psi while
+// loading.
+hipError_t launch_sweep_tiled(const Launch& L, const DevLevel& lv, const void* theta_in,
+                              void* theta_out, int zero_in, const void* f, int64_t fcs,
+                              uint32_t word, int backward, const DevLevel* coarse, const void* psi);
+// Segment form of the tiled sweep (stencil held in registers across passes
+// and chains).  variant 0: 256 threads per block, 1: 512; cpb_override > 0
+// fixes the chains per block.
+hipError_t launch_sweep_seg(const Launch& L, const DevLevel& lv, const void* theta_in,
+                            void* theta_out, int zero_in, const void* f, int64_t fcs,
+                            uint32_t word, int backward, const DevLevel* coarse, const void* psi,
+                            int variant, int cpb_override);
+hipError_t launch_restrict_tiled(const Launch& L, const DevLevel& fine, const void* theta,
+                                 const DevLevel& coarse, const void* f, int64_t fcs);
+hipError_t launch_restrict(const Launch& L, const DevLevel& fine, const void* theta,
+                           const DevLevel& coarse, const void* f, int64_t fcs);
+hipError_t launch_prolong(const Launch& L, const DevLevel& fine, void* theta,
+                          const DevLevel& coarse, const void* psi);
 hipError_t launch_coarsest(const Launch& L, const DevLevel& lv0, const void* f0, int64_t fcs,
-                           void* theta0, const double* KT, const double* UinvT);
-hipError_t launch_lowrank(const Launch& L, const DevLevel& lv, int dir, uint32_t word, int beta,
-                          const double* gisq, double* xi, double* u);
-hipError_t launch_gather_v(const Launch& L, const DevLevel& lv, int beta, const double* ginv,
-                           double* v);
+                           void* theta0, const double* K, const double* Uinv);
+hipError_t launch_lowrank(const Launch& L, const DevLevel& lv, void* theta, int dir, uint32_t word,
+                          int beta, const double* gisq, double* xi, double* u);
+hipError_t launch_gather_v(const Launch& L, const DevLevel& lv, const void* theta, int beta,
+                           const double* ginv, double* v);
 hipError_t launch_coarse_rhs_lowrank(const Launch& L, const DevLevel& coarse, const double* v,
                                      int beta);
 hipError_t launch_fill_zero(const Launch& L, void* p, int64_t count);

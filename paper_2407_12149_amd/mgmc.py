@@ -15,10 +15,11 @@ LIB_PATH = os.path.join(_HERE, "libmgmc.so")
 
 MGMC_OK, MGMC_EINVAL, MGMC_ENOMEM, MGMC_EDEVICE, MGMC_ENOTSPD, MGMC_EUNSUPPORTED, MGMC_ESTATE = range(7)
 MGMC_FP64, MGMC_FP32 = 0, 1
+MGMC_OPT_TILED_SWEEPS, MGMC_OPT_SWEEP_VARIANT, MGMC_OPT_CHAINS_PER_BLOCK = 1, 2, 3
 
 EXPORTED = [
     "mgmc_setup", "mgmc_sample", "mgmc_posterior_sample", "mgmc_levels", "mgmc_level_sites",
-    "mgmc_set_graph", "mgmc_set_profiling", "mgmc_profile_read", "mgmc_destroy",
+    "mgmc_set_graph", "mgmc_set_option", "mgmc_set_profiling", "mgmc_profile_read", "mgmc_destroy",
     "mgmc_last_error",
 ]
 
@@ -74,6 +75,8 @@ def load_library():
     lib.mgmc_level_sites.argtypes = [vp, ctypes.c_int32]
     lib.mgmc_set_graph.restype = ctypes.c_int
     lib.mgmc_set_graph.argtypes = [vp, ctypes.c_int32]
+    lib.mgmc_set_option.restype = ctypes.c_int
+    lib.mgmc_set_option.argtypes = [vp, ctypes.c_int32, ctypes.c_int64]
     lib.mgmc_set_profiling.restype = ctypes.c_int
     lib.mgmc_set_profiling.argtypes = [vp, ctypes.c_int32]
     lib.mgmc_profile_read.restype = ctypes.c_int
@@ -165,6 +168,10 @@ def mgmc_set_graph(ctx, enabled):
     _check(load_library().mgmc_set_graph(ctx, 1 if enabled else 0))
 
 
+def mgmc_set_option(ctx, option, value):
+    _check(load_library().mgmc_set_option(ctx, int(option), int(value)))
+
+
 def mgmc_set_profiling(ctx, enabled):
     _check(load_library().mgmc_set_profiling(ctx, 1 if enabled else 0))
 
@@ -228,6 +235,9 @@ class Sampler:
 
     def set_graph(self, enabled):
         mgmc_set_graph(self.ctx, enabled)
+
+    def set_option(self, option, value):
+        mgmc_set_option(self.ctx, option, value)
 
     def set_profiling(self, enabled):
         mgmc_set_profiling(self.ctx, enabled)

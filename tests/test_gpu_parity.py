@@ -76,13 +76,19 @@ def rel_err(got, want):
     return np.abs(got - want).max() / max(np.abs(want).max(), 1e-300)
 
 
-def check_stepwise(prob, obs, nsamples, y=None, rhs=None, F=None, label=""):
+def check_stepwise(prob, obs, nsamples, y=None, rhs=None, F=None, label="", tiled=True,
+                   variant=None, cpb=None):
     from paper_2407_12149_amd import mgmc
     log(f"[parity] {label} dim={prob['dim']} n={prob['n']} levels={prob['levels']} "
-        f"beta={0 if obs is None else len(obs[0]) - 1} chains={prob['nchains']}")
+        f"beta={0 if obs is None else len(obs[0]) - 1} chains={prob['nchains']} tiled={tiled}")
     o = oracle_for(prob, obs, y=y, rhs=rhs)
     ref = oracle_runs(o, prob, nsamples, F=F)
     s = mgmc.Sampler(prob, obs=obs)
+    s.set_option(mgmc.MGMC_OPT_TILED_SWEEPS, 1 if tiled else 0)
+    if variant is not None:
+        s.set_option(mgmc.MGMC_OPT_SWEEP_VARIANT, variant)
+    if cpb is not None:
+        s.set_option(mgmc.MGMC_OPT_CHAINS_PER_BLOCK, cpb)
     Fd = None if F is None else torch.tensor(F, device="cuda")
     rhsd = None if rhs is None else torch.tensor(rhs, device="cuda")
     worst = 0.0
@@ -105,17 +111,32 @@ def check_stepwise(prob, obs, nsamples, y=None, rhs=None, F=None, label=""):
     return worst
 
 
-def test_prior_2d_stepwise():
+@pytest.mark.parametrize("tiled", [True, False])
+def test_prior_2d_stepwise(tiled):
     prob, obs = make_problem(2, 63, 4, 100.0, nchains=2)
-    check_stepwise(prob, obs, 8, F=workloads.subcube_qoi(63, 2), label="prior 63^2")
+    check_stepwise(prob, obs, 8, F=workloads.subcube_qoi(63, 2), label="prior 63^2", tiled=tiled)
 
 
-def test_posterior_2d_variable_stepwise():
+@pytest.mark.parametrize("tiled", [True, False])
+def test_posterior_2d_variable_stepwise(tiled):
     n = 127
     face = workloads.face_array(n, 2, workloads.fourier_log_field(2, nmodes=32, seed=4))
     prob, obs = make_problem(2, n, 4, 100.0, face=face, beta=8, gamma=1e-4, nchains=3)
     y = workloads.observed_values(8, seed=5)
-    check_stepwise(prob, obs, 5, y=y, F=workloads.subcube_qoi(n, 2), label="posterior 127^2")
+    check_stepwise(prob, obs, 5, y=y, F=workloads.subcube_qoi(n, 2), label="posterior 127^2",
+                   tiled=tiled)
+
+
+@pytest.mark.parametrize("variant,cpb", [(0, 0), (1, 0), (1, 4), (2, 3), (2, 0)])
+def test_posterior_2d_many_tiles_many_chains(variant, cpb):
+    """255^2 spans several sweep tiles in both directions with a ragged last
+    tile; 9 chains exercise chain groups per block (ragged when cpb = 4)."""
+    n = 255
+    face = workloads.face_array(n, 2, workloads.fourier_log_field(2, nmodes=8, seed=2))
+    prob, obs = make_problem(2, n, 5, 30.0, face=face, beta=5, gamma=1e-3, nchains=9)
+    y = workloads.observed_values(5, seed=6)
+    check_stepwise(prob, obs, 2, y=y, F=workloads.subcube_qoi(n, 2),
+                   label=f"posterior 255^2 variant {variant} cpb {cpb}", variant=variant, cpb=cpb)
 
 
 def test_prior_3d_stepwise():
@@ -137,13 +158,14 @@ def test_single_level_is_cholesky_sampler():
     check_stepwise(prob, obs, 3, y=y, label="one level 15^2")
 
 
-def test_user_prolongation_weights():
+@pytest.mark.parametrize("tiled", [True, False])
+def test_user_prolongation_weights(tiled):
     n = 63
     nc = 31
     rng = np.random.default_rng(3)
     w = rng.uniform(0.2, 1.0, size=(nc * nc, 9))
     prob, obs = make_problem(2, n, 3, 50.0, nchains=2, prolong_w=w.reshape(-1))
-    check_stepwise(prob, obs, 4, label="user P 63^2")
+    check_stepwise(prob, obs, 4, label="user P 63^2", tiled=tiled)
 
 
 def test_more_sweeps_and_rhs():
