@@ -78,6 +78,67 @@ def cpu_baseline(cfg, seconds_target, tau):
     }
 
 
+def batched(args):
+    """512 prior chains of five shapes (2D 127^2, 255^2, 511^2; 3D 63^3,
+    127^3), FP32 sweeps with FP64 coarsest sample, autotuned kernels, every
+    step of all chains one launch of a HIP graph; paired against FP64 runs of
+    the same chains (common random numbers) for the mean/variance error."""
+    import torch
+
+    from paper_2407_12149_amd import autotune, diagnostics, mgmc, workloads
+
+    cfg = workloads.config("batched512")
+    out = {"metric": "effective samples/s (batched FP32 MGMC, 512 chains of mixed sizes)",
+           "unit": "effective samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "batched512",
+                      "shapes": [f"{p['n']}^{p['dim']} x {p['nchains']}" for p in cfg["parts"]]}}
+    runs = {}
+    for prec in ("fp32", "fp64"):
+        samplers = []
+        for p in cfg["parts"]:
+            prob = dict(dim=p["dim"], n=p["n"], levels=p["levels"], kappa2=p["kappa2"],
+                        nchains=p["nchains"], seed=cfg["seed"], precision=prec)
+            log(f"[bench] batched {prec}: set-up {p['n']}^{p['dim']} x {p['nchains']}")
+            s = mgmc.Sampler(prob)
+            best = autotune.autotune(s, cache_path=args.tune_cache)
+            log(f"[bench] batched {prec}: tuned {best}")
+            samplers.append(s)
+        Fs = [torch.tensor(p["F"], device="cuda") for p in cfg["parts"]]
+        b = mgmc.Batch(samplers, updates_per_launch=10)
+        log(f"[bench] batched {prec}: warmup {args.warmup}")
+        b.sample(0, args.warmup)
+        torch.cuda.synchronize()
+        log(f"[bench] batched {prec}: timed {args.steps} steps")
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        start.record(b.stream)
+        qs = b.sample(args.warmup, args.steps, Fs=Fs)
+        stop.record(b.stream)
+        torch.cuda.synchronize()
+        seconds = start.elapsed_time(stop) / 1e3
+        qs = [q.cpu().numpy() for q in qs]
+        taus = [float(np.mean([diagnostics.iact_wolff(q[:, c])[0] for c in range(q.shape[1])]))
+                for q in qs]
+        ess = sum(q.shape[1] * args.steps / t for q, t in zip(qs, taus)) / seconds
+        runs[prec] = dict(seconds=seconds, qs=qs, taus=taus, ess=ess)
+        b.close()
+        for s in samplers:
+            s.close()
+    r32, r64 = runs["fp32"], runs["fp64"]
+    out["value"] = r32["ess"]
+    out["ms_per_step"] = r32["seconds"] * 1e3 / args.steps
+    out["vs_baseline"] = None
+    out["fp64"] = {"value": r64["ess"], "ms_per_step": r64["seconds"] * 1e3 / args.steps}
+    out["per_shape"] = []
+    for p, q32, q64, t in zip(cfg["parts"], r32["qs"], r64["qs"], r32["taus"]):
+        out["per_shape"].append({
+            "shape": f"{p['n']}^{p['dim']}", "chains": p["nchains"], "iact": t,
+            "mean_err_rel_sd": float(abs(q32.mean() - q64.mean()) / q64.std()),
+            "var_err_rel": float(abs(q32.var() - q64.var()) / q64.var())})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +148,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", type=int, default=1)
+    ap.add_argument("--fp32", type=int, default=1, help="also run the FP32 sampler (paired)")
+    ap.add_argument("--workload", default="posterior1023", choices=["posterior1023", "batched512"])
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2407_12149_amd", "tuning.json"))
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB, 20 times "
                          "(reference for the HBM byte counters)")
@@ -110,51 +174,73 @@ def main():
     from paper_2407_12149_amd import diagnostics, mgmc, workloads
 
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", 0)))
+    if args.workload == "batched512":
+        print(json.dumps(batched(args)), flush=True)
+        return
     log("[bench] generating workload posterior1023")
     cfg = workloads.config("posterior1023")
     n, dim, nch = cfg["n"], cfg["dim"], cfg["nchains"]
-    prob = dict(dim=dim, n=n, levels=cfg["levels"], kappa2=cfg["kappa2"], face_coef=cfg["face_coef"],
-                nchains=nch, seed=cfg["seed"], precision="fp64")
-    log("[bench] set-up")
-    t0 = time.perf_counter()
-    s = mgmc.Sampler(prob, obs=cfg["obs"])
-    setup_s = time.perf_counter() - t0
     F = torch.tensor(cfg["F"], device="cuda")
     y = cfg["y"]
 
-    log(f"[bench] warmup {args.warmup}")
-    s.set_graph(bool(args.graph))
-    s.posterior_sample(y, 0, args.warmup, F=F)
-    torch.cuda.synchronize()
+    def run(precision):
+        prob = dict(dim=dim, n=n, levels=cfg["levels"], kappa2=cfg["kappa2"],
+                    face_coef=cfg["face_coef"], nchains=nch, seed=cfg["seed"], precision=precision)
+        log(f"[bench] {precision}: set-up")
+        t0 = time.perf_counter()
+        s = mgmc.Sampler(prob, obs=cfg["obs"])
+        setup_s = time.perf_counter() - t0
+        log(f"[bench] {precision}: warmup {args.warmup}")
+        s.set_graph(bool(args.graph))
+        s.posterior_sample(y, 0, args.warmup, F=F)
+        torch.cuda.synchronize()
+        log(f"[bench] {precision}: timed {args.steps} steps")
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record(s.stream)
+        q = s.posterior_sample(y, args.warmup, args.steps, F=F)
+        stop.record(s.stream)
+        torch.cuda.synchronize()
+        seconds = start.elapsed_time(stop) / 1e3
+        qs = q.cpu().numpy()
+        taus = [diagnostics.iact_wolff(qs[:, c])[0] for c in range(nch)]
+        tau = float(np.mean(taus))
+        # kernel time of the finest-level sweeps, bracketed by HIP events on
+        # the sampler's stream during a further run of the same workload
+        log(f"[bench] {precision}: kernel timing {args.profile_steps} steps")
+        s.set_graph(False)
+        s.set_profiling(True)
+        s.posterior_sample(y, args.warmup + args.steps, args.profile_steps, F=F)
+        kms, launches = s.profile_read()
+        s.set_profiling(False)
+        s.close()
+        esz = 4 if precision == "fp32" else 8
+        per_launch_s = kms / 1e3 / max(launches, 1)
+        launches_per_sweep = launches / (2.0 * args.profile_steps)
+        bytes_launch = sweep_bytes(n, dim, nch, esz, dim) / launches_per_sweep
+        return dict(seconds=seconds, q=qs, tau=tau, setup_s=setup_s, per_launch_s=per_launch_s,
+                    launches_per_sweep=launches_per_sweep, bytes_launch=bytes_launch,
+                    achieved=bytes_launch / per_launch_s / 1e9)
 
-    log(f"[bench] timed {args.steps} steps")
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record(s.stream)
-    q = s.posterior_sample(y, args.warmup, args.steps, F=F)
-    stop.record(s.stream)
-    torch.cuda.synchronize()
-    seconds = start.elapsed_time(stop) / 1e3
-    qs = q.cpu().numpy()
-    taus = [diagnostics.iact_wolff(qs[:, c])[0] for c in range(nch)]
-    tau = float(np.mean(taus))
+    r64 = run("fp64")
+    seconds, tau = r64["seconds"], r64["tau"]
     value = args.steps * nch / (tau * seconds)
-
-    # kernel time of the finest-level sweeps, bracketed by HIP events on the
-    # sampler's stream during a further run of the same workload
-    log(f"[bench] kernel timing {args.profile_steps} steps")
-    s.set_graph(False)
-    s.set_profiling(True)
-    m1 = args.warmup + args.steps
-    s.posterior_sample(y, m1, args.profile_steps, F=F)
-    kms, launches = s.profile_read()
-    s.set_profiling(False)
-    per_launch_s = kms / 1e3 / max(launches, 1)
-    launches_per_sweep = launches / (2.0 * args.profile_steps)
-    bytes_sweep = sweep_bytes(n, dim, nch, 8, dim)
-    bytes_launch = bytes_sweep / launches_per_sweep
-    achieved = bytes_launch / per_launch_s / 1e9
+    achieved = r64["achieved"]
+    setup_s = r64["setup_s"]
+    extra = {}
+    if args.fp32:
+        r32 = run("fp32")
+        # paired comparison on common random numbers: same counters, same start
+        q64, q32 = r64["q"], r32["q"]
+        sd = q64.std()
+        extra["fp32"] = {
+            "value": args.steps * nch / (r32["tau"] * r32["seconds"]),
+            "ms_per_step": r32["seconds"] * 1e3 / args.steps, "iact": r32["tau"],
+            "sweep_gbs": r32["achieved"], "sweep_frac": r32["achieved"] / PEAK_HBM_GBS,
+            "mean_err_rel_sd": float(abs(q32.mean() - q64.mean()) / sd),
+            "var_err_rel": float(abs(q32.var() - q64.var()) / q64.var()),
+        }
 
     result = {
         "metric": "effective samples/s (plain MGMC posterior, FP64)",
@@ -175,10 +261,12 @@ def main():
         "setup_s": setup_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": None,
-                     "kernel": "finest-level smoother sweep", "launches_per_sweep": launches_per_sweep,
-                     "avg_launch_us": per_launch_s * 1e6, "bytes_per_launch": bytes_launch},
+                     "kernel": "finest-level smoother sweep",
+                     "launches_per_sweep": r64["launches_per_sweep"],
+                     "avg_launch_us": r64["per_launch_s"] * 1e6,
+                     "bytes_per_launch": r64["bytes_launch"]},
     }
-    s.close()
+    result.update(extra)
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
         result["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds, tau)

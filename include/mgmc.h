@@ -155,6 +155,27 @@ mgmc_status mgmc_set_option(mgmc_ctx* ctx, int32_t option, int64_t value);
 mgmc_status mgmc_set_profiling(mgmc_ctx* ctx, int32_t enabled);
 mgmc_status mgmc_profile_read(mgmc_ctx* ctx, double* total_ms, int64_t* launches);
 
+/* Time nupdates MGMC updates of the context's internal chain states with the
+ * current options (graph off), using the right-hand side of the last run; the
+ * caller's states are not touched.  Used by the autotuner.  Synchronises. */
+mgmc_status mgmc_time_updates(mgmc_ctx* ctx, int32_t nupdates, double* ms);
+
+/* Batches: independent contexts (any sizes, dimensions and precisions) whose
+ * updates run as parallel branches of one HIP graph, launched once per group
+ * of `updates_per_launch` steps on the batch stream.  The contexts must stay
+ * alive while the batch exists and must not be used concurrently. */
+typedef struct mgmc_batch mgmc_batch;
+mgmc_status mgmc_batch_create(mgmc_ctx* const* ctxs, int32_t count, int32_t updates_per_launch,
+                              void* hip_stream, mgmc_batch** out);
+/* Updates m0 .. m0+nsamples-1 of every context.  thetas[i], Fs[i], qois[i]
+ * follow mgmc_sample for context i (Fs/qois may be NULL, or hold NULLs).
+ * Contexts set up with observations sample their posterior for the last y
+ * given to mgmc_posterior_sample (ESTATE if none was given), the others the
+ * prior. */
+mgmc_status mgmc_batch_sample(mgmc_batch* batch, int64_t m0, int64_t nsamples, void* const* thetas,
+                              const double* const* Fs, double* const* qois);
+mgmc_status mgmc_batch_destroy(mgmc_batch* batch);
+
 /* Synchronise the context's stream and release everything it owns. */
 mgmc_status mgmc_destroy(mgmc_ctx* ctx);
 

@@ -322,7 +322,7 @@ hipError_t sweep2d(mgmc_ctx* c, const mgmc::DevLevel& lv, const void* in, void* 
   if (cpb <= 0) {
     // enough blocks to fill the device, chains grouped so each block reuses
     // its stencil registers; FP64 groups stay smaller (register pressure)
-    const int tys = lv.cross ? 12 : 8;
+    const int tys = lv.cross ? 12 : 22;
     const int64_t tiles = int64_t((lv.g.n + 63) / 64) * ((lv.g.n + tys - 1) / tys);
     const int nch = c->L.nchains, cap = c->L.fp32 ? 8 : 4;
     int64_t want = int64_t(nch) * tiles / 1024;
@@ -330,8 +330,11 @@ hipError_t sweep2d(mgmc_ctx* c, const mgmc::DevLevel& lv, const void* in, void* 
     const int groups = (nch + cpb - 1) / cpb;
     cpb = (nch + groups - 1) / groups;  // balance the chain groups
   }
+  // the four-colour (9-point) levels carry a 3-row halo: taller tiles
+  // (512 threads) keep the redundant halo work small
+  const int variant = c->sweep_variant == 2 || (c->sweep_variant == 1 && !lv.cross) ? 1 : 0;
   return mgmc::launch_sweep_seg(c->L, lv, in, out, zero_in, f, fcs, word, backward, coarse, psi,
-                                c->sweep_variant == 2 ? 1 : 0, cpb);
+                                variant, cpb);
 }
 
 // One MGMC update of every chain (Alg. 1), enqueued on the context stream.
@@ -657,6 +660,171 @@ mgmc_status mgmc_profile_read(mgmc_ctx* c, double* total_ms, int64_t* launches) 
   *total_ms = c->prof_ms;
   *launches = c->prof_launches;
   return MGMC_OK;
+}
+
+mgmc_status mgmc_time_updates(mgmc_ctx* c, int32_t nupdates, double* ms) {
+  if (!c || !ms || nupdates < 1) return fail(MGMC_EINVAL, "invalid timing arguments");
+  const void* fL = c->posterior_ready ? c->fL : nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
+  MGMC_HIP(hipEventCreate(&a));
+  MGMC_HIP(hipEventCreate(&b));
+  MGMC_HIP(hipStreamSynchronize(c->stream));
+  mgmc_status s = MGMC_OK;
+  hipError_t e = hipEventRecord(a, c->stream);
+  for (int k = 0; k < nupdates && s == MGMC_OK && e == hipSuccess; ++k) s = enqueue_cycle(c, fL, nullptr, nullptr, 0);
+  if (e == hipSuccess) e = hipEventRecord(b, c->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (s != MGMC_OK) return s;
+  if (e != hipSuccess) return fail(MGMC_EDEVICE, std::string("timing: ") + hipGetErrorString(e));
+  *ms = t;
+  return MGMC_OK;
+}
+
+}  // extern "C"
+
+struct mgmc_batch {
+  std::vector<mgmc_ctx*> ctx;
+  std::vector<hipStream_t> branch;
+  hipStream_t stream = nullptr;
+  int per_launch = 1;
+};
+
+extern "C" {
+
+mgmc_status mgmc_batch_create(mgmc_ctx* const* ctxs, int32_t count, int32_t updates_per_launch,
+                              void* hip_stream, mgmc_batch** out) {
+  g_err.clear();
+  if (!ctxs || !out || count < 1 || updates_per_launch < 1) return fail(MGMC_EINVAL, "invalid batch arguments");
+  if (!hip_stream) return fail(MGMC_EINVAL, "a batch needs a non-default stream (graph capture)");
+  *out = nullptr;
+  mgmc_batch* b = new (std::nothrow) mgmc_batch();
+  if (!b) return fail(MGMC_ENOMEM, "host allocation failed");
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  b->per_launch = updates_per_launch;
+  for (int i = 0; i < count; ++i) {
+    if (!ctxs[i]) {
+      delete b;
+      return fail(MGMC_EINVAL, "NULL context in batch");
+    }
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) {
+        delete b;
+        return fail(MGMC_EINVAL, "context listed twice in batch");
+      }
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      for (hipStream_t x : b->branch) (void)hipStreamDestroy(x);
+      delete b;
+      return fail(MGMC_EDEVICE, "stream creation failed");
+    }
+    b->ctx.push_back(ctxs[i]);
+    b->branch.push_back(st);
+  }
+  *out = b;
+  return MGMC_OK;
+}
+
+mgmc_status mgmc_batch_sample(mgmc_batch* b, int64_t m0, int64_t nsamples, void* const* thetas,
+                              const double* const* Fs, double* const* qois) {
+  g_err.clear();
+  if (!b || !thetas) return fail(MGMC_EINVAL, "invalid batch sample arguments");
+  const int nb = int(b->ctx.size());
+  for (int i = 0; i < nb; ++i) {
+    mgmc_status s = check_run_args(b->ctx[i], m0, nsamples, thetas[i], Fs ? Fs[i] : nullptr, qois ? qois[i] : nullptr);
+    if (s != MGMC_OK) return s;
+    if (b->ctx[i]->beta > 0 && !b->ctx[i]->posterior_ready) return fail(MGMC_ESTATE, "posterior context without data y");
+  }
+  if (nsamples == 0) return MGMC_OK;
+  // every context works on the batch stream, with its branch stream during capture
+  std::vector<hipStream_t> saved(nb);
+  for (int i = 0; i < nb; ++i) {
+    saved[i] = b->ctx[i]->stream;
+    MGMC_HIP(hipStreamSynchronize(saved[i]));
+  }
+  auto use_stream = [&](int i, hipStream_t st) {
+    b->ctx[i]->stream = st;
+    b->ctx[i]->L.stream = st;
+  };
+  auto restore = [&]() {
+    for (int i = 0; i < nb; ++i) use_stream(i, saved[i]);
+  };
+  mgmc_status s = MGMC_OK;
+  for (int i = 0; i < nb && s == MGMC_OK; ++i) {
+    use_stream(i, b->stream);
+    mgmc_ctx* c = b->ctx[i];
+    const int top = c->levels - 1;
+    hipError_t e = mgmc::launch_unpack(c->L, c->lv[top], thetas[i], c->lv[top].buf[0]);
+    if (e == hipSuccess) e = mgmc::launch_set_m(c->stream, c->mcur, m0);
+    if (e != hipSuccess) s = fail(MGMC_EDEVICE, std::string("batch start: ") + hipGetErrorString(e));
+  }
+  // capture `per` updates of every context as parallel branches of one graph
+  auto capture = [&](int per, hipGraphExec_t* exec) -> mgmc_status {
+    hipGraph_t graph = nullptr;
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> join(nb, nullptr);
+    MGMC_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    for (int i = 0; i < nb; ++i) MGMC_HIP(hipEventCreateWithFlags(&join[i], hipEventDisableTiming));
+    mgmc_status st = MGMC_OK;
+    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) e = hipEventRecord(fork, b->stream);
+    for (int i = 0; i < nb && e == hipSuccess && st == MGMC_OK; ++i) {
+      e = hipStreamWaitEvent(b->branch[i], fork, 0);
+      if (e != hipSuccess) break;
+      use_stream(i, b->branch[i]);
+      b->ctx[i]->capturing = true;
+      mgmc_ctx* c = b->ctx[i];
+      const void* fL = c->posterior_ready ? c->fL : nullptr;
+      for (int k = 0; k < per && st == MGMC_OK; ++k)
+        st = enqueue_cycle(c, fL, Fs ? Fs[i] : nullptr, qois ? qois[i] : nullptr, m0);
+      c->capturing = false;
+      if (st == MGMC_OK) e = hipEventRecord(join[i], b->branch[i]);
+      if (e == hipSuccess && st == MGMC_OK) e = hipStreamWaitEvent(b->stream, join[i], 0);
+    }
+    hipError_t e2 = hipStreamEndCapture(b->stream, &graph);
+    for (int i = 0; i < nb; ++i) use_stream(i, b->stream);
+    if (st == MGMC_OK && e == hipSuccess && e2 == hipSuccess) e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipEventDestroy(fork);
+    for (hipEvent_t x : join) (void)hipEventDestroy(x);
+    if (st != MGMC_OK) return st;
+    if (e != hipSuccess) return fail(MGMC_EDEVICE, std::string("batch capture: ") + hipGetErrorString(e));
+    if (e2 != hipSuccess) return fail(MGMC_EDEVICE, std::string("batch capture end: ") + hipGetErrorString(e2));
+    return MGMC_OK;
+  };
+  const int64_t per = std::min<int64_t>(b->per_launch, nsamples);
+  const int64_t full = nsamples / per, rest = nsamples % per;
+  hipGraphExec_t exec = nullptr, exec_rest = nullptr;
+  if (s == MGMC_OK) s = capture(int(per), &exec);
+  if (s == MGMC_OK && rest) s = capture(int(rest), &exec_rest);
+  hipError_t e = hipSuccess;
+  for (int64_t k = 0; s == MGMC_OK && k < full && e == hipSuccess; ++k) e = hipGraphLaunch(exec, b->stream);
+  if (s == MGMC_OK && rest && e == hipSuccess) e = hipGraphLaunch(exec_rest, b->stream);
+  if (s == MGMC_OK && e != hipSuccess) s = fail(MGMC_EDEVICE, std::string("batch launch: ") + hipGetErrorString(e));
+  for (int i = 0; i < nb && s == MGMC_OK; ++i) {
+    mgmc_ctx* c = b->ctx[i];
+    const int top = c->levels - 1;
+    hipError_t e3 = mgmc::launch_pack(c->L, c->lv[top], c->lv[top].buf[0], thetas[i]);
+    if (e3 != hipSuccess) s = fail(MGMC_EDEVICE, std::string("batch finish: ") + hipGetErrorString(e3));
+  }
+  hipError_t e4 = hipStreamSynchronize(b->stream);
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (exec_rest) (void)hipGraphExecDestroy(exec_rest);
+  restore();
+  if (s == MGMC_OK && e4 != hipSuccess) s = fail(MGMC_EDEVICE, std::string("batch sync: ") + hipGetErrorString(e4));
+  return s;
+}
+
+mgmc_status mgmc_batch_destroy(mgmc_batch* b) {
+  if (!b) return MGMC_OK;
+  mgmc_status s = MGMC_OK;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) s = fail(MGMC_EDEVICE, "stream synchronisation failed");
+  for (hipStream_t x : b->branch) (void)hipStreamDestroy(x);
+  delete b;
+  return s;
 }
 
 mgmc_status mgmc_destroy(mgmc_ctx* c) {

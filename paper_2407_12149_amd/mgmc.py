@@ -20,7 +20,8 @@ MGMC_OPT_TILED_SWEEPS, MGMC_OPT_SWEEP_VARIANT, MGMC_OPT_CHAINS_PER_BLOCK = 1, 2,
 EXPORTED = [
     "mgmc_setup", "mgmc_sample", "mgmc_posterior_sample", "mgmc_levels", "mgmc_level_sites",
     "mgmc_set_graph", "mgmc_set_option", "mgmc_set_profiling", "mgmc_profile_read", "mgmc_destroy",
-    "mgmc_last_error",
+    "mgmc_last_error", "mgmc_time_updates", "mgmc_batch_create", "mgmc_batch_sample",
+    "mgmc_batch_destroy",
 ]
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -81,6 +82,16 @@ def load_library():
     lib.mgmc_set_profiling.argtypes = [vp, ctypes.c_int32]
     lib.mgmc_profile_read.restype = ctypes.c_int
     lib.mgmc_profile_read.argtypes = [vp, _dp, ctypes.POINTER(ctypes.c_int64)]
+    lib.mgmc_time_updates.restype = ctypes.c_int
+    lib.mgmc_time_updates.argtypes = [vp, ctypes.c_int32, _dp]
+    lib.mgmc_batch_create.restype = ctypes.c_int
+    lib.mgmc_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_int32, vp,
+                                      ctypes.POINTER(vp)]
+    lib.mgmc_batch_sample.restype = ctypes.c_int
+    lib.mgmc_batch_sample.argtypes = [vp, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(vp),
+                                      ctypes.POINTER(vp), ctypes.POINTER(vp)]
+    lib.mgmc_batch_destroy.restype = ctypes.c_int
+    lib.mgmc_batch_destroy.argtypes = [vp]
     lib.mgmc_destroy.restype = ctypes.c_int
     lib.mgmc_destroy.argtypes = [vp]
     lib.mgmc_last_error.restype = ctypes.c_char_p
@@ -184,6 +195,36 @@ def mgmc_profile_read(ctx):
     return ms.value, cnt.value
 
 
+def mgmc_time_updates(ctx, nupdates):
+    ms = ctypes.c_double()
+    _check(load_library().mgmc_time_updates(ctx, int(nupdates), ctypes.byref(ms)))
+    return ms.value
+
+
+def mgmc_batch_create(ctxs, updates_per_launch, stream):
+    arr = (ctypes.c_void_p * len(ctxs))(*[c.value for c in ctxs])
+    handle = ctypes.c_void_p()
+    _check(load_library().mgmc_batch_create(arr, len(ctxs), int(updates_per_launch),
+                                            _stream_handle(stream), ctypes.byref(handle)))
+    return handle
+
+
+def mgmc_batch_sample(batch, m0, nsamples, thetas, Fs=None, qois=None):
+    k = len(thetas)
+
+    def ptrs(ts):
+        if ts is None:
+            return None
+        return (ctypes.c_void_p * k)(*[None if t is None else t.data_ptr() for t in ts])
+
+    _check(load_library().mgmc_batch_sample(batch, int(m0), int(nsamples), ptrs(thetas),
+                                            ptrs(Fs), ptrs(qois)))
+
+
+def mgmc_batch_destroy(batch):
+    _check(load_library().mgmc_batch_destroy(batch))
+
+
 def mgmc_destroy(ctx):
     _check(load_library().mgmc_destroy(ctx))
 
@@ -245,10 +286,56 @@ class Sampler:
     def profile_read(self):
         return mgmc_profile_read(self.ctx)
 
+    def time_updates(self, nupdates):
+        return mgmc_time_updates(self.ctx, nupdates)
+
     def close(self):
         if self.ctx is not None:
             mgmc_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several samplers (any sizes) updated together: each step of all their
+    chains is one launch of a HIP graph with one branch per sampler."""
+
+    def __init__(self, samplers, updates_per_launch=10, stream=None):
+        import torch
+        self.torch = torch
+        self.samplers = list(samplers)
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.handle = mgmc_batch_create([s.ctx for s in self.samplers], updates_per_launch,
+                                        self.stream)
+
+    def sample(self, m0, nsamples, Fs=None):
+        """Advance every sampler's chains; returns one QoI series per sampler
+        (None where no F is given)."""
+        torch = self.torch
+        cur = torch.cuda.current_stream()
+        self.stream.wait_stream(cur)
+        for s in self.samplers:
+            self.stream.wait_stream(s.stream)
+        qois = None
+        with torch.cuda.stream(self.stream):
+            if Fs is not None:
+                qois = [None if F is None else
+                        torch.zeros(nsamples, s.nchains, dtype=torch.float64, device=s.device)
+                        for s, F in zip(self.samplers, Fs)]
+            mgmc_batch_sample(self.handle, m0, nsamples, [s.theta for s in self.samplers],
+                              Fs, qois)
+        cur.wait_stream(self.stream)
+        return qois
+
+    def close(self):
+        if self.handle is not None:
+            mgmc_batch_destroy(self.handle)
+            self.handle = None
 
     def __del__(self):
         try:

@@ -173,4 +173,11 @@ def config(name):
         return dict(name=name, dim=dim, n=n, levels=7, kappa2=100.0, face_coef=face,
                     obs=(ptr, idx, val, gamma), y=observed_values(m, seed=3), nchains=8,
                     nsamples=10000, seed=0, F=subcube_qoi(n, dim))
+    if name == "batched512":
+        # 512 prior chains of five shapes, kappa = 5, constant coefficient
+        shapes = [(2, 127, 5, 103), (2, 255, 6, 103), (2, 511, 7, 102), (3, 63, 4, 102),
+                  (3, 127, 5, 102)]
+        parts = [dict(dim=d, n=n, levels=lv, kappa2=25.0, face_coef=None, obs=None, y=None,
+                      nchains=c, F=subcube_qoi(n, d)) for d, n, lv, c in shapes]
+        return dict(name=name, parts=parts, nsamples=5000, seed=0)
     raise KeyError(name)

@@ -296,3 +296,50 @@ def test_fp32_tracks_fp64_on_common_random_numbers():
     assert rel.max().item() <= 1e-2
     s64.close()
     s32.close()
+
+
+def test_batch_graph_equals_individual_runs():
+    """Contexts of different sizes and dimensions advanced as branches of one
+    graph give bitwise the same chains and QoI as separate runs."""
+    from paper_2407_12149_amd import mgmc
+    log("[batch] 3 contexts, graph branches")
+    specs = [make_problem(2, 127, 5, 25.0, nchains=3),
+             make_problem(2, 63, 4, 25.0, nchains=2, beta=3, gamma=1e-3),
+             make_problem(3, 15, 3, 25.0, nchains=2)]
+    specs[0][0]["precision"] = "fp32"
+    y = workloads.observed_values(3, seed=1)
+    Fs = [torch.tensor(workloads.subcube_qoi(p["n"], p["dim"]), device="cuda") for p, _ in specs]
+    ref = []
+    for (p, o), F in zip(specs, Fs):
+        s = mgmc.Sampler(p, obs=o)
+        q = s.posterior_sample(y, 0, 5, F=F) if o is not None else s.sample(0, 5, F=F)
+        torch.cuda.synchronize()
+        ref.append((s.theta.clone(), q.clone()))
+        s.close()
+    samplers = [mgmc.Sampler(p, obs=o) for p, o in specs]
+    samplers[1].posterior_sample(y, 0, 0)  # bind the data y
+    b = mgmc.Batch(samplers, updates_per_launch=2)
+    qs = b.sample(0, 5, Fs=Fs)
+    torch.cuda.synchronize()
+    for (th, q), s, qb in zip(ref, samplers, qs):
+        assert torch.equal(th, s.theta)
+        assert torch.equal(q, qb)
+    b.close()
+    for s in samplers:
+        s.close()
+
+
+def test_autotune_picks_and_caches(tmp_path):
+    from paper_2407_12149_amd import autotune, mgmc
+    prob, obs = make_problem(2, 255, 6, 25.0, nchains=4)
+    log("[autotune] 255^2 x 4")
+    s = mgmc.Sampler(prob)
+    cache = str(tmp_path / "tune.json")
+    best = autotune.autotune(s, cache_path=cache, updates=2)
+    assert not best["cached"] and best["ms"] > 0
+    again = autotune.autotune(s, cache_path=cache)
+    assert again["cached"] and again["variant"] == best["variant"] and again["cpb"] == best["cpb"]
+    s.close()
+    # the tuned options keep oracle parity
+    prob2 = dict(prob, nchains=4)
+    check_stepwise(prob2, None, 2, label="tuned 255^2", variant=best["variant"], cpb=best["cpb"])
