@@ -208,7 +208,7 @@ mgmc_status upload_level(mgmc_ctx* c, int l) {
   }
   mgmc_status s = c->alloc_bytes(d.buf[0], size_t(nch) * Np * c->esz);
   if (s != MGMC_OK) return s;
-  if (dim == 2 && l >= 1) {  // second buffer for the tiled (out-of-place) sweeps
+  if (l >= 1) {  // second buffer: out-of-place 2D sweeps, 3D residual scratch
     s = c->alloc_bytes(d.buf[1], size_t(nch) * Np * c->esz);
     if (s != MGMC_OK) return s;
   }
@@ -351,6 +351,17 @@ mgmc_status enqueue_cycle(mgmc_ctx* c, const void* fL, const double* F, double* 
   auto state = [&](int l) { return c->lv[l].buf[cur[l]]; };
   auto in_place_sweep = [&](int l, const void* f, int64_t fcs, uint32_t word, bool backward) -> mgmc_status {
     mgmc::DevLevel& lv = c->lv[l];
+    if (c->prob.dim == 3 && lv.cross && c->tiled) {
+      // 7-point level: the four colours of one parity never couple
+      for (int pp = 0; pp < 2; ++pp) {
+        const int parity = backward ? 1 - pp : pp;
+        mgmc_status st = timed(c, l == top, [&] {
+          return mgmc::launch_sweep_parity3d(L, lv, state(l), f, fcs, word, parity);
+        });
+        if (st != MGMC_OK) return st;
+      }
+      return MGMC_OK;
+    }
     for (int qq = 0; qq < nq; ++qq) {
       const int q = backward ? nq - 1 - qq : qq;
       mgmc_status st = timed(c, l == top, [&] {
@@ -386,6 +397,8 @@ mgmc_status enqueue_cycle(mgmc_ctx* c, const void* fL, const double* F, double* 
       }
       if (tiled)
         MGMC_LAUNCH(mgmc::launch_restrict_tiled(L, lv, state(l), c->lv[l - 1], f, fcs));
+      else if (c->prob.dim == 3 && c->tiled)
+        MGMC_LAUNCH(mgmc::launch_restrict_2stage(L, lv, state(l), lv.buf[1 - cur[l]], c->lv[l - 1], f, fcs));
       else
         MGMC_LAUNCH(mgmc::launch_restrict(L, lv, state(l), c->lv[l - 1], f, fcs));
       if (beta) {

@@ -81,6 +81,46 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const T* __restrict__ coef,
   if (2 * q + 1 < m1) gs_update<T, DIM, CROSS>(coef, invd, isqd, th, fc, g, ia + 2, z1);
 }
 
+// Parity pass of a 3D 7-point sweep: all colours with parity sum `parity`
+// (they never couple through axis neighbours), one thread per Philox pair of
+// the row's colour.  Equivalent to the four colour passes of that parity.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sweep_parity3d(const T* __restrict__ coef,
+                                                           const T* __restrict__ invd,
+                                                           const T* __restrict__ isqd,
+                                                           T* __restrict__ theta,
+                                                           const T* __restrict__ f, int64_t fcs,
+                                                           Geom g, int parity, uint32_t word,
+                                                           const int64_t* __restrict__ mcur,
+                                                           uint32_t seed, uint32_t chain0) {
+  const int n = g.n;
+  const int qmax = ((n + 1) / 2 + 1) / 2;  // pairs per row for the odd x-sublattice
+  const int64_t total = int64_t(qmax) * n * n;
+  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gid >= total) return;
+  const int c = blockIdx.y;
+  const int q = int(gid % qmax);
+  const int64_t row = gid / qmax;
+  const int i2 = 1 + int(row % n), i3 = 1 + int(row / n);
+  const int xpar = (parity + i2 + i3) & 1;  // x parity giving parity sum `parity`
+  const int colour = xpar | ((i2 & 1) << 1) | ((i3 & 1) << 2);
+  const int m1 = xpar ? (n + 1) / 2 : (n - 1) / 2;
+  const int qx = (m1 + 1) / 2;
+  if (q >= qx) return;
+  const int m2 = (i2 & 1) ? (n + 1) / 2 : (n - 1) / 2;
+  const int s2 = (i2 - 1) >> 1, s3 = (i3 - 1) >> 1;
+  const uint32_t pair = uint32_t(q) + uint32_t(qx) * (uint32_t(s2) + uint32_t(m2) * uint32_t(s3));
+  const Block4 blk = philox10(pair, word | uint32_t(colour), uint32_t(*mcur), 0u, seed, chain0 + c);
+  T z0, z1;
+  Gauss<T>::pair(blk, z0, z1);
+  T* th = theta + int64_t(c) * g.Np;
+  const T* fc = f ? f + int64_t(c) * fcs : nullptr;
+  const int i1 = 4 * q + (xpar ? 1 : 2);
+  const int64_t ia = pidx(g, i1, i2, i3);
+  gs_update<T, 3, true>(coef, invd, isqd, th, fc, g, ia, z0);
+  if (2 * q + 1 < m1) gs_update<T, 3, true>(coef, invd, isqd, th, fc, g, ia + 2, z1);
+}
+
 template <typename T, int DIM, bool CROSS, bool USERP>
 __global__ __launch_bounds__(kBlock) void k_restrict(const T* __restrict__ coef,
                                                      const T* __restrict__ theta,
@@ -113,6 +153,56 @@ __global__ __launch_bounds__(kBlock) void k_restrict(const T* __restrict__ coef,
     }
     const T w = USERP ? T(wP[int64_t(t1) * gc.Np + iJ]) : T(multilinear(ex, ey, ez));
     acc += w * r;
+  }
+  fcoarse[int64_t(c) * gc.Np + iJ] = acc;
+}
+
+// Two-stage restriction (used in 3D): r = f - A theta at every fine site,
+// then f_{l-1}(J) = sum_delta w_J(delta) r(2J + delta).
+template <typename T, int DIM, bool CROSS>
+__global__ __launch_bounds__(kBlock) void k_residual(const T* __restrict__ coef,
+                                                     const T* __restrict__ theta,
+                                                     const T* __restrict__ f, int64_t fcs, Geom g,
+                                                     int64_t N, T* __restrict__ r) {
+  constexpr int S = DIM == 2 ? 9 : 27;
+  const int64_t lin = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (lin >= N) return;
+  const int c = blockIdx.y;
+  int i1, i2, i3;
+  unflatten<DIM>(lin, g.n, i1, i2, i3);
+  const int64_t ii = pidx(g, i1, i2, i3);
+  const T* th = theta + int64_t(c) * g.Np;
+  T acc = f ? f[int64_t(c) * fcs + ii] : T(0);
+#pragma unroll
+  for (int t = 0; t < S; ++t) {
+    const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = DIM == 3 ? t / 9 - 1 : 0;
+    const int nz = (dx != 0) + (dy != 0) + (dz != 0);
+    if (CROSS && nz > 1) continue;
+    acc -= coef[int64_t(t) * g.Np + ii] * th[ii + poff(g, dx, dy, dz)];
+  }
+  r[int64_t(c) * g.Np + ii] = acc;
+}
+
+template <typename T, int DIM, bool USERP>
+__global__ __launch_bounds__(kBlock) void k_restrict_residual(const T* __restrict__ r, Geom gf,
+                                                              T* __restrict__ fcoarse, Geom gc,
+                                                              const double* __restrict__ wP) {
+  constexpr int S = DIM == 2 ? 9 : 27;
+  const int nc = gc.n;
+  const int64_t total = int64_t(nc) * nc * (DIM == 3 ? nc : 1);
+  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gid >= total) return;
+  const int c = blockIdx.y;
+  int J1, J2, J3;
+  unflatten<DIM>(gid, nc, J1, J2, J3);
+  const int64_t iJ = pidx(gc, J1, J2, J3);
+  const T* rc = r + int64_t(c) * gf.Np;
+  T acc = T(0);
+#pragma unroll
+  for (int t1 = 0; t1 < S; ++t1) {
+    const int ex = t1 % 3 - 1, ey = (t1 / 3) % 3 - 1, ez = DIM == 3 ? t1 / 9 - 1 : 0;
+    const T w = USERP ? T(wP[int64_t(t1) * gc.Np + iJ]) : T(multilinear(ex, ey, ez));
+    acc += w * rc[pidx(gf, 2 * J1 + ex, 2 * J2 + ey, DIM == 3 ? 2 * J3 + ez : 0)];
   }
   fcoarse[int64_t(c) * gc.Np + iJ] = acc;
 }
@@ -447,6 +537,19 @@ hipError_t launch_sweep_colour(const Launch& L, const DevLevel& lv, void* theta,
   return hipGetLastError();
 }
 
+hipError_t launch_sweep_parity3d(const Launch& L, const DevLevel& lv, void* theta, const void* f,
+                                  int64_t fcs, uint32_t word, int parity) {
+  if (L.mcur == nullptr || L.dim != 3 || !lv.cross) return hipErrorInvalidValue;
+  const int n = lv.g.n;
+  const int64_t total = int64_t(((n + 1) / 2 + 1) / 2) * n * n;
+  dim3 grid(blocks_for(total), L.nchains);
+  if (L.fp32)
+    k_sweep_parity3d<float><<<grid, kBlock, 0, L.stream>>>((const float*)lv.coef, (const float*)lv.invd, (const float*)lv.isqd, (float*)theta, (const float*)f, fcs, lv.g, parity, word, L.mcur, L.seed, L.chain0);
+  else
+    k_sweep_parity3d<double><<<grid, kBlock, 0, L.stream>>>((const double*)lv.coef, (const double*)lv.invd, (const double*)lv.isqd, (double*)theta, (const double*)f, fcs, lv.g, parity, word, L.mcur, L.seed, L.chain0);
+  return hipGetLastError();
+}
+
 hipError_t launch_restrict(const Launch& L, const DevLevel& fine, const void* theta,
                            const DevLevel& coarse, const void* f, int64_t fcs) {
   dim3 grid(blocks_for(coarse.N), L.nchains);
@@ -465,6 +568,24 @@ hipError_t launch_restrict(const Launch& L, const DevLevel& fine, const void* th
       else
         k_restrict<T, DIM, false, false><<<grid, kBlock, 0, L.stream>>>(cf, th, (const T*)f, fcs, fine.g, out, coarse.g, nullptr);
     }
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_restrict_2stage(const Launch& L, const DevLevel& fine, const void* theta,
+                                  void* scratch, const DevLevel& coarse, const void* f,
+                                  int64_t fcs) {
+  if (scratch == nullptr || scratch == theta) return hipErrorInvalidValue;
+  dim3 g1(blocks_for(fine.N), L.nchains), g2(blocks_for(coarse.N), L.nchains);
+  MGMC_DISPATCH(L, {
+    if (fine.cross)
+      k_residual<T, DIM, true><<<g1, kBlock, 0, L.stream>>>((const T*)fine.coef, (const T*)theta, (const T*)f, fcs, fine.g, fine.N, (T*)scratch);
+    else
+      k_residual<T, DIM, false><<<g1, kBlock, 0, L.stream>>>((const T*)fine.coef, (const T*)theta, (const T*)f, fcs, fine.g, fine.N, (T*)scratch);
+    if (fine.wP)
+      k_restrict_residual<T, DIM, true><<<g2, kBlock, 0, L.stream>>>((const T*)scratch, fine.g, (T*)coarse.f, coarse.g, fine.wP);
+    else
+      k_restrict_residual<T, DIM, false><<<g2, kBlock, 0, L.stream>>>((const T*)scratch, fine.g, (T*)coarse.f, coarse.g, nullptr);
   });
   return hipGetLastError();
 }

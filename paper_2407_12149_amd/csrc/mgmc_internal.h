@@ -66,6 +66,10 @@ inline uint32_t noise_word(int level, int sigma) { return (uint32_t(level) << 8)
 // One colour pass, in place on theta.
 hipError_t launch_sweep_colour(const Launch& L, const DevLevel& lv, void* theta, const void* f,
                                int64_t fcs, uint32_t word, int colour);
+// Parity pass (0: even parity sum first in forward order, 1: odd) of a 3D
+// sweep on a 7-point level, in place.
+hipError_t launch_sweep_parity3d(const Launch& L, const DevLevel& lv, void* theta, const void* f,
+                                 int64_t fcs, uint32_t word, int parity);
 // LDS-tiled 2D sweep (all colour passes in one launch) from theta_in into
 // theta_out (distinct buffers).  zero_in: the input state is zero (not read).
 // coarse != nullptr adds the prolongation P psi of the coarse state psi while
@@ -84,6 +88,11 @@ hipError_t launch_restrict_tiled(const Launch& L, const DevLevel& fine, const vo
                                  const DevLevel& coarse, const void* f, int64_t fcs);
 hipError_t launch_restrict(const Launch& L, const DevLevel& fine, const void* theta,
                            const DevLevel& coarse, const void* f, int64_t fcs);
+// Residual into scratch (a second state buffer of the fine level), then
+// restriction of the residual: for 3D, where a coarse node's support is large.
+hipError_t launch_restrict_2stage(const Launch& L, const DevLevel& fine, const void* theta,
+                                  void* scratch, const DevLevel& coarse, const void* f,
+                                  int64_t fcs);
 hipError_t launch_prolong(const Launch& L, const DevLevel& fine, void* theta,
                           const DevLevel& coarse, const void* psi);
 hipError_t launch_coarsest(const Launch& L, const DevLevel& lv0, const void* f0, int64_t fcs,

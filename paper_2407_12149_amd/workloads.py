@@ -98,6 +98,35 @@ def gaussian_log_field(dim, corr_len, variance, seed, nfeatures=1024):
     return log_a
 
 
+def lognormal_faces_fft(n, dim, corr_len, variance, seed):
+    """Face coefficients a = exp(g) of a stationary Gaussian field g with
+    squared-exponential covariance variance * exp(-|r|^2 / (2 corr_len^2)),
+    synthesised spectrally on a periodic grid of spacing h/2 covering the
+    unit cube twice over (so that the periodisation is negligible), then read
+    at the face midpoints.  2D only (the 3D workloads use gaussian_log_field)."""
+    if dim != 2:
+        raise ValueError("spectral synthesis is provided for 2D")
+    h = 1.0 / (n + 1)
+    m = 4 * (n + 1)  # grid of spacing h/2 over a periodic box of side 2
+    rng = np.random.default_rng(seed)
+    k = np.fft.fftfreq(m, d=h / 2) * 2.0 * np.pi
+    kx, ky = np.meshgrid(k, k, indexing="ij")
+    # spectral density of the squared-exponential covariance in 2D
+    spec = variance * 2.0 * np.pi * corr_len ** 2 * np.exp(-0.5 * corr_len ** 2 * (kx ** 2 + ky ** 2))
+    box = m * (h / 2)
+    amp = np.sqrt(spec / box ** 2) * m * m
+    noise = rng.normal(size=(m, m)) + 1j * rng.normal(size=(m, m))
+    field = np.real(np.fft.ifft2(amp * noise))
+    # grid point (a, b) sits at (a h/2, b h/2): node i at 2i, face f + 1/2 at 2f + 1
+    gxy = field.T  # index [y][x]
+    per = (n + 1) * n
+    ax = np.exp(gxy[2 * np.arange(1, n + 1)][:, 2 * np.arange(n + 1) + 1])  # [y node][x face]
+    ay = np.exp(gxy[2 * np.arange(n + 1) + 1][:, 2 * np.arange(1, n + 1)])  # [y face][x node]
+    out = np.concatenate([ax.reshape(-1), ay.reshape(-1)])
+    assert out.size == 2 * per
+    return out
+
+
 # --------------------------------------------------------------------------
 # observations, data and quantity of interest
 # --------------------------------------------------------------------------
@@ -173,6 +202,13 @@ def config(name):
         return dict(name=name, dim=dim, n=n, levels=7, kappa2=100.0, face_coef=face,
                     obs=(ptr, idx, val, gamma), y=observed_values(m, seed=3), nchains=8,
                     nsamples=10000, seed=0, F=subcube_qoi(n, dim))
+    if name == "learned511":
+        # learned prolongation: 511^2, lognormal a (correlation length 0.05,
+        # variance 2), kappa = 1, prior; fields 0..1999 train, 2000.. held out
+        n, dim = 511, 2
+        return dict(name=name, dim=dim, n=n, levels=7, kappa2=1.0, corr_len=0.05, variance=2.0,
+                    train_fields=2000, test_fields=200, field_seed0=1000, nchains=1,
+                    nsamples=10000, burn_in=1000, seed=0, F=subcube_qoi(n, dim))
     if name == "batched512":
         # 512 prior chains of five shapes, kappa = 5, constant coefficient
         shapes = [(2, 127, 5, 103), (2, 255, 6, 103), (2, 511, 7, 102), (3, 63, 4, 102),
