@@ -176,6 +176,57 @@ mgmc_status mgmc_batch_sample(mgmc_batch* batch, int64_t m0, int64_t nsamples, v
                               const double* const* Fs, double* const* qois);
 mgmc_status mgmc_batch_destroy(mgmc_batch* batch);
 
+/* Learned prolongation.  The sampler keeps its target for any full-rank P
+ * with Galerkin coarse operators (invariance theorem of Sec. 3, proved for
+ * general transfers; Sec. 3.1 notes P is not unique), so the finest transfer
+ * may be chosen to speed up mixing.  This network maps the coefficient near
+ * each coarse node J to the 9 weights of J in problem.prolong_w (2D):
+ *   features: log a on the 24 faces around fine nodes 2J + {-1,0,1}^2;
+ *   conv3x3 24->16, ReLU, conv3x3 16->16, ReLU, conv3x3 16->9 (zero padding
+ *   on the nc x nc coarse grid, FP32);
+ *   rho = softplus(output); weight of J at fine node i = 2J + delta is
+ *   rho_J(delta) / sum of rho over the coarse nodes covering i (nodes outside
+ *   the grid count 1), and 1 at delta = 0 (FP64).  Equal rho give the
+ *   multilinear P.
+ * Training minimises the two-grid loss, the fraction of an error's energy the
+ * coarse correction I - P (P^T A P)^{-1} P^T A of the convergence analysis
+ * (Sec. 4) leaves behind,
+ *   L = mean over fields, crops, errors of 1 - g^T Ac^{-1} g / e^T A e,
+ *   g = P^T A e, Ac = P^T A P,
+ * on 15 x 15 coarse-node crops tiling each field (fine window of 31 x 31
+ * nodes with zero Dirichlet data outside it; scale s = h^2).
+ * Parameters: pnet_param_count() floats, [W1 16x24x9][b1 16][W2 16x16x9]
+ * [b2 16][W3 9x16x9][b3 9], W[cout][cin][t], t = (dx+1) + 3 (dy+1).
+ * Calls are asynchronous on hip_stream unless they return host values. */
+typedef struct mgmc_pnet mgmc_pnet;
+int64_t mgmc_pnet_param_count(void);
+/* n: odd fine grid size (nc = (n-1)/2 coarse nodes per axis); buffers for
+ * up to max_batch fields and max_errors errors per field; parameters start
+ * at 0.  Errors: EINVAL, ENOMEM, EDEVICE. */
+mgmc_status mgmc_pnet_create(int32_t n, int32_t max_batch, int32_t max_errors, void* hip_stream,
+                             mgmc_pnet** out);
+/* host float parameters in/out; set_params also resets the Adam state.
+ * Both synchronise. */
+mgmc_status mgmc_pnet_set_params(mgmc_pnet* net, const float* params);
+mgmc_status mgmc_pnet_get_params(mgmc_pnet* net, float* params);
+/* faces: device FP64 [batch][2 (n+1) n] face coefficients (face_coef layout);
+ * w: device FP64 [batch][nc*nc][9] learned weights (prolong_w layout). */
+mgmc_status mgmc_pnet_weights(mgmc_pnet* net, const double* faces, int32_t batch, double* w);
+/* errors: device FP64 [batch][nerrors][n*n] error vectors; kappa2 of the
+ * operator.  loss: host FP64 scalar or NULL; grad: host float
+ * [param_count] or NULL; synchronises when either is given.  EINVAL when
+ * nc < 15 (no crop fits). */
+mgmc_status mgmc_pnet_loss_grad(mgmc_pnet* net, const double* faces, const double* errors,
+                                int32_t batch, int32_t nerrors, double kappa2, double* loss,
+                                float* grad);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on the
+ * gradient of the loss; loss (host, may be NULL) receives the loss before the
+ * step. */
+mgmc_status mgmc_pnet_train_step(mgmc_pnet* net, const double* faces, const double* errors,
+                                 int32_t batch, int32_t nerrors, double kappa2, float lr,
+                                 double* loss);
+mgmc_status mgmc_pnet_destroy(mgmc_pnet* net);
+
 /* Synchronise the context's stream and release everything it owns. */
 mgmc_status mgmc_destroy(mgmc_ctx* ctx);
 

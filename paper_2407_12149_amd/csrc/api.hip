@@ -42,6 +42,13 @@ inline int64_t padded_of(const mgmc::Geom& g, int dim, int64_t lin) {
 
 }  // namespace
 
+namespace mgmc {
+int record_error(int status, const char* msg) {
+  g_err = msg;
+  return status;
+}
+}  // namespace mgmc
+
 struct mgmc_ctx {
   mgmc_problem prob{};
   hipStream_t stream = nullptr;

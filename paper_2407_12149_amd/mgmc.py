@@ -21,7 +21,9 @@ EXPORTED = [
     "mgmc_setup", "mgmc_sample", "mgmc_posterior_sample", "mgmc_levels", "mgmc_level_sites",
     "mgmc_set_graph", "mgmc_set_option", "mgmc_set_profiling", "mgmc_profile_read", "mgmc_destroy",
     "mgmc_last_error", "mgmc_time_updates", "mgmc_batch_create", "mgmc_batch_sample",
-    "mgmc_batch_destroy",
+    "mgmc_batch_destroy", "mgmc_pnet_param_count", "mgmc_pnet_create", "mgmc_pnet_set_params",
+    "mgmc_pnet_get_params", "mgmc_pnet_weights", "mgmc_pnet_loss_grad", "mgmc_pnet_train_step",
+    "mgmc_pnet_destroy",
 ]
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -94,6 +96,26 @@ def load_library():
     lib.mgmc_batch_destroy.argtypes = [vp]
     lib.mgmc_destroy.restype = ctypes.c_int
     lib.mgmc_destroy.argtypes = [vp]
+    _fp = ctypes.POINTER(ctypes.c_float)
+    lib.mgmc_pnet_param_count.restype = ctypes.c_int64
+    lib.mgmc_pnet_param_count.argtypes = []
+    lib.mgmc_pnet_create.restype = ctypes.c_int
+    lib.mgmc_pnet_create.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp,
+                                     ctypes.POINTER(vp)]
+    lib.mgmc_pnet_set_params.restype = ctypes.c_int
+    lib.mgmc_pnet_set_params.argtypes = [vp, _fp]
+    lib.mgmc_pnet_get_params.restype = ctypes.c_int
+    lib.mgmc_pnet_get_params.argtypes = [vp, _fp]
+    lib.mgmc_pnet_weights.restype = ctypes.c_int
+    lib.mgmc_pnet_weights.argtypes = [vp, vp, ctypes.c_int32, vp]
+    lib.mgmc_pnet_loss_grad.restype = ctypes.c_int
+    lib.mgmc_pnet_loss_grad.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                        _dp, _fp]
+    lib.mgmc_pnet_train_step.restype = ctypes.c_int
+    lib.mgmc_pnet_train_step.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_double, ctypes.c_float, _dp]
+    lib.mgmc_pnet_destroy.restype = ctypes.c_int
+    lib.mgmc_pnet_destroy.argtypes = [vp]
     lib.mgmc_last_error.restype = ctypes.c_char_p
     lib.mgmc_last_error.argtypes = []
     _lib = lib
@@ -231,6 +253,121 @@ def mgmc_destroy(ctx):
 
 def mgmc_last_error():
     return load_library().mgmc_last_error().decode()
+
+
+def mgmc_pnet_param_count():
+    return int(load_library().mgmc_pnet_param_count())
+
+
+def mgmc_pnet_create(n, max_batch, max_errors, stream=None):
+    handle = ctypes.c_void_p()
+    _check(load_library().mgmc_pnet_create(int(n), int(max_batch), int(max_errors),
+                                           _stream_handle(stream), ctypes.byref(handle)))
+    return handle
+
+
+def mgmc_pnet_set_params(net, params):
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    _check(load_library().mgmc_pnet_set_params(net, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+
+def mgmc_pnet_get_params(net):
+    a = np.zeros(mgmc_pnet_param_count(), dtype=np.float32)
+    _check(load_library().mgmc_pnet_get_params(net, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+    return a
+
+
+def mgmc_pnet_weights(net, faces, batch, w):
+    _check(load_library().mgmc_pnet_weights(net, _ptr(faces), int(batch), _ptr(w)))
+
+
+def mgmc_pnet_loss_grad(net, faces, errors, batch, nerrors, kappa2, want_grad=True):
+    """(loss, grad or None); faces and errors are device tensors."""
+    loss = ctypes.c_double()
+    grad = np.zeros(mgmc_pnet_param_count(), dtype=np.float32) if want_grad else None
+    _check(load_library().mgmc_pnet_loss_grad(
+        net, _ptr(faces), _ptr(errors), int(batch), int(nerrors), float(kappa2), ctypes.byref(loss),
+        None if grad is None else grad.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+    return loss.value, grad
+
+
+def mgmc_pnet_train_step(net, faces, errors, batch, nerrors, kappa2, lr, want_loss=True):
+    loss = ctypes.c_double()
+    _check(load_library().mgmc_pnet_train_step(net, _ptr(faces), _ptr(errors), int(batch),
+                                               int(nerrors), float(kappa2), float(lr),
+                                               ctypes.byref(loss) if want_loss else None))
+    return loss.value if want_loss else None
+
+
+def mgmc_pnet_destroy(net):
+    _check(load_library().mgmc_pnet_destroy(net))
+
+
+class PNet:
+    """Learned prolongation network on its own torch stream (fine grid n)."""
+
+    def __init__(self, n, max_batch=1, max_errors=1, params=None, device="cuda"):
+        import torch
+        self.n = n
+        self.nc = (n - 1) // 2
+        self.device = torch.device(device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        self.handle = mgmc_pnet_create(n, max_batch, max_errors, self.stream)
+        if params is not None:
+            self.set_params(params)
+
+    def _wait(self):
+        import torch
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def set_params(self, params):
+        mgmc_pnet_set_params(self.handle, params)
+
+    def params(self):
+        return mgmc_pnet_get_params(self.handle)
+
+    def weights(self, faces):
+        """faces: device FP64 [batch][2 (n+1) n] -> device FP64 [batch][nc*nc][9]."""
+        import torch
+        faces = faces.reshape(-1, 2 * (self.n + 1) * self.n).contiguous()
+        w = torch.empty((faces.shape[0], self.nc * self.nc, 9), dtype=torch.float64,
+                        device=self.device)
+        self._wait()
+        mgmc_pnet_weights(self.handle, faces, faces.shape[0], w)
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        faces.record_stream(self.stream)
+        w.record_stream(self.stream)
+        return w
+
+    def loss_grad(self, faces, errors, kappa2, want_grad=True):
+        faces = faces.reshape(-1, 2 * (self.n + 1) * self.n).contiguous()
+        b = faces.shape[0]
+        errors = errors.reshape(b, -1, self.n * self.n).contiguous()
+        self._wait()
+        return mgmc_pnet_loss_grad(self.handle, faces, errors, b, errors.shape[1], kappa2, want_grad)
+
+    def train_step(self, faces, errors, kappa2, lr, want_loss=True):
+        faces = faces.reshape(-1, 2 * (self.n + 1) * self.n).contiguous()
+        b = faces.shape[0]
+        errors = errors.reshape(b, -1, self.n * self.n).contiguous()
+        self._wait()
+        out = mgmc_pnet_train_step(self.handle, faces, errors, b, errors.shape[1], kappa2, lr,
+                                   want_loss)
+        if not want_loss:
+            faces.record_stream(self.stream)
+            errors.record_stream(self.stream)
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            mgmc_pnet_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Sampler:
