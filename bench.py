@@ -26,6 +26,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+METRIC = "effective samples/s, plain vs learned-prolong MGMC at 1 GPU; sweep HBM GB/s"
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "sweep_seg_posterior1023_fp64_pmc.md")
+SWEEP_SOURCE = os.path.join(ROOT, "paper_2407_12149_amd", "csrc", "kernels_tiled.hip")
 
 
 def log(msg):
@@ -39,6 +42,29 @@ def sweep_bytes(n, dim, nchains, esz, faces_per_site):
     once for all chains."""
     N = n ** dim
     return N * nchains * 2 * esz + N * esz + N * (faces_per_site + 1) * esz
+
+
+def measured_traffic():
+    """HBM bytes per finest-sweep launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a copy kernel of known size), or
+    None when the sweep kernel's source changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        src = hashlib.sha256(open(SWEEP_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    if fields.get("source_sha256") != src:
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(cfg, seconds_target, tau):
@@ -243,7 +269,7 @@ def main():
         }
 
     result = {
-        "metric": "effective samples/s (plain MGMC posterior, FP64)",
+        "metric": METRIC,
         "value": value,
         "unit": "effective samples/s",
         "n_gpus": 1,
@@ -260,7 +286,7 @@ def main():
         "iact": tau,
         "setup_s": setup_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": measured_traffic(),
                      "kernel": "finest-level smoother sweep",
                      "launches_per_sweep": r64["launches_per_sweep"],
                      "avg_launch_us": r64["per_launch_s"] * 1e6,

@@ -138,13 +138,19 @@ mgmc_status mgmc_set_graph(mgmc_ctx* ctx, int32_t enabled);
  *     the prolongation fused into the post-smoother; 0 launches one kernel
  *     per colour (the form used for 3D).
  *   MGMC_OPT_SWEEP_VARIANT: form of the one-launch 2D sweep: 0 stages the
- *     stencil through LDS per chain, 1 (default) keeps each thread's stencil
- *     in registers across colours and chains (256 threads per block), 2 the
- *     same with 512 threads per block.
+ *     stencil through LDS per chain, 1 keeps each thread's stencil in
+ *     registers across colours and chains (256 threads per block), 2 the
+ *     same with 512 threads per block (taller tiles), 3 (default) chooses
+ *     per level.
  *   MGMC_OPT_CHAINS_PER_BLOCK: chains processed by one block of the 2D
  *     sweep; 0 (default) chooses from the grid size and precision. */
 enum { MGMC_OPT_TILED_SWEEPS = 1, MGMC_OPT_SWEEP_VARIANT = 2, MGMC_OPT_CHAINS_PER_BLOCK = 3 };
 mgmc_status mgmc_set_option(mgmc_ctx* ctx, int32_t option, int64_t value);
+
+/* Per-level form of MGMC_OPT_SWEEP_VARIANT or MGMC_OPT_CHAINS_PER_BLOCK for
+ * level `level` (0 = coarsest); -1 returns the level to the context-wide
+ * setting.  Results are identical for every setting.  Errors: EINVAL. */
+mgmc_status mgmc_set_level_option(mgmc_ctx* ctx, int32_t level, int32_t option, int64_t value);
 
 /* Kernel timing of the finest-level smoother sweeps (the hot loop of the
  * update): when enabled, every launch of a finest-level sweep kernel is

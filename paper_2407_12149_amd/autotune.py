@@ -1,8 +1,12 @@
-"""Autotuner of the sweep kernels: a grid search over the kernel form (LDS
-tiles, or register-held stencil with 256 or 512 threads per block) and the
-number of chains processed per block, timed on the device through the
-library's own update timer, with results cached in a JSON file keyed by
-problem shape, precision, chain count and device name."""
+"""Autotuner of the sweep kernels.
+
+For every level that runs smoother sweeps (levels >= 1) it searches the
+kernel form (LDS tiles, or register-held stencil with 256 or 512 threads per
+block) and the number of chains processed per block, by coordinate descent
+from the finest level down: each level's candidates are timed with the
+library's own update timer while the other levels keep their current best.
+Results are cached in a JSON file keyed by problem shape, precision, chain
+count and device name."""
 import json
 import os
 
@@ -20,39 +24,63 @@ def _key(sampler):
                                      sampler.nchains, dev))
 
 
+def apply(sampler, levels):
+    """Set per-level (variant, chains per block) pairs; None entries reset."""
+    for l, vc in enumerate(levels):
+        v, c = (-1, -1) if vc is None else vc
+        sampler.set_level_option(l, mgmc.MGMC_OPT_SWEEP_VARIANT, v)
+        sampler.set_level_option(l, mgmc.MGMC_OPT_CHAINS_PER_BLOCK, c)
+
+
+def _time(sampler, updates):
+    sampler.time_updates(1)  # warm-up
+    return sampler.time_updates(updates) / updates
+
+
 def autotune(sampler, cache_path=None, updates=3, verbose=False):
-    """Pick the fastest (variant, chains per block) for this sampler, apply it
-    and return {"variant": v, "cpb": c, "ms": t, "cached": bool}."""
+    """Pick the fastest per-level settings for this sampler, apply them and
+    return {"levels": [[variant, cpb] or None per level], "ms": t, "cached": bool}."""
     key = _key(sampler)
+    nlev = int(sampler.problem["levels"])
     cache = {}
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as fh:
             cache = json.load(fh)
-    if key in cache:
+    if key in cache and "levels" in cache[key]:
         best = dict(cache[key], cached=True)
-    elif sampler.problem["dim"] != 2:
-        best = {"variant": 1, "cpb": 0, "ms": None, "cached": False}  # 3D: per-colour kernels
+    elif sampler.problem["dim"] != 2 or nlev < 2:
+        best = {"levels": [None] * nlev, "ms": None, "cached": False}  # per-colour kernels
     else:
-        results = []
-        for v in CANDIDATE_VARIANTS:
-            for c in CANDIDATE_CPB:
-                if c > sampler.nchains or (v == 0 and c != 0):
-                    continue
-                sampler.set_option(mgmc.MGMC_OPT_SWEEP_VARIANT, v)
-                sampler.set_option(mgmc.MGMC_OPT_CHAINS_PER_BLOCK, c)
-                sampler.time_updates(1)  # warm-up
-                ms = sampler.time_updates(updates) / updates
-                results.append((ms, v, c))
-                if verbose:
-                    print(f"[autotune] {key} variant={v} cpb={c}: {ms:.3f} ms/update", flush=True)
-        ms, v, c = min(results)
-        best = {"variant": v, "cpb": c, "ms": ms, "cached": False}
+        sampler.set_option(mgmc.MGMC_OPT_SWEEP_VARIANT, 3)
+        sampler.set_option(mgmc.MGMC_OPT_CHAINS_PER_BLOCK, 0)
+        levels = [None] * nlev
+        apply(sampler, levels)
+        ms_best = _time(sampler, updates)
+        for l in range(nlev - 1, 0, -1):
+            choice = None
+            for v in CANDIDATE_VARIANTS:
+                for c in CANDIDATE_CPB:
+                    if c > sampler.nchains or (v == 0 and c != 0):
+                        continue
+                    sampler.set_level_option(l, mgmc.MGMC_OPT_SWEEP_VARIANT, v)
+                    sampler.set_level_option(l, mgmc.MGMC_OPT_CHAINS_PER_BLOCK, c)
+                    ms = _time(sampler, updates)
+                    if verbose:
+                        print(f"[autotune] {key} level {l} variant={v} cpb={c}: {ms:.3f} ms/update",
+                              flush=True)
+                    if ms < ms_best:
+                        ms_best, choice = ms, [v, c]
+            if choice is not None:
+                levels[l] = choice
+            apply(sampler, levels)
+        best = {"levels": levels, "ms": ms_best, "cached": False}
         if cache_path:
-            cache[key] = {"variant": v, "cpb": c, "ms": ms}
+            cache[key] = {"levels": levels, "ms": ms_best}
             tmp = cache_path + ".tmp"
             with open(tmp, "w") as fh:
                 json.dump(cache, fh, indent=1, sort_keys=True)
             os.replace(tmp, cache_path)
-    sampler.set_option(mgmc.MGMC_OPT_SWEEP_VARIANT, best["variant"])
-    sampler.set_option(mgmc.MGMC_OPT_CHAINS_PER_BLOCK, best["cpb"])
+    sampler.set_option(mgmc.MGMC_OPT_SWEEP_VARIANT, 3)
+    sampler.set_option(mgmc.MGMC_OPT_CHAINS_PER_BLOCK, 0)
+    apply(sampler, best["levels"])
     return best

@@ -71,8 +71,9 @@ struct mgmc_ctx {
   bool posterior_ready = false;
   bool use_graph = false;
   bool tiled = true;    // one launch per 2D sweep; false: one launch per colour
-  int sweep_variant = 1;  // 0: LDS-staged tiles, 1: segment owners (256 threads), 2: (512)
+  int sweep_variant = 3;  // 0: LDS-staged tiles, 1/2: segment owners with 256/512 threads, 3: per level
   int sweep_cpb = 0;      // chains per block of the 2D sweeps; 0 picks by size
+  std::vector<int> lvl_variant, lvl_cpb;  // per-level overrides, -1 = context-wide setting
   std::vector<void*> allocs;
   // profiling: a ring of event pairs around finest-level sweep launches
   bool profiling = false;
@@ -320,12 +321,14 @@ mgmc_status timed(mgmc_ctx* c, bool finest, F&& body) {
   } while (0)
 
 // One 2D sweep from theta_in into theta_out in the selected kernel form.
-hipError_t sweep2d(mgmc_ctx* c, const mgmc::DevLevel& lv, const void* in, void* out, int zero_in,
-                   const void* f, int64_t fcs, uint32_t word, int backward,
-                   const mgmc::DevLevel* coarse, const void* psi) {
-  if (c->sweep_variant == 0)
+hipError_t sweep2d(mgmc_ctx* c, int l, const void* in, void* out, int zero_in, const void* f,
+                   int64_t fcs, uint32_t word, int backward, const mgmc::DevLevel* coarse,
+                   const void* psi) {
+  const mgmc::DevLevel& lv = c->lv[l];
+  const int sv = c->lvl_variant[l] >= 0 ? c->lvl_variant[l] : c->sweep_variant;
+  if (sv == 0)
     return mgmc::launch_sweep_tiled(c->L, lv, in, out, zero_in, f, fcs, word, backward, coarse, psi);
-  int cpb = c->sweep_cpb;
+  int cpb = c->lvl_cpb[l] >= 0 ? c->lvl_cpb[l] : c->sweep_cpb;
   if (cpb <= 0) {
     // enough blocks to fill the device, chains grouped so each block reuses
     // its stencil registers; FP64 groups stay smaller (register pressure)
@@ -337,9 +340,9 @@ hipError_t sweep2d(mgmc_ctx* c, const mgmc::DevLevel& lv, const void* in, void* 
     const int groups = (nch + cpb - 1) / cpb;
     cpb = (nch + groups - 1) / groups;  // balance the chain groups
   }
-  // the four-colour (9-point) levels carry a 3-row halo: taller tiles
-  // (512 threads) keep the redundant halo work small
-  const int variant = c->sweep_variant == 2 || (c->sweep_variant == 1 && !lv.cross) ? 1 : 0;
+  // 512-thread blocks (taller tiles, less redundant halo work) or 256-thread
+  // blocks (more blocks in flight); the automatic choice takes 256 threads
+  const int variant = sv == 2 ? 1 : 0;
   return mgmc::launch_sweep_seg(c->L, lv, in, out, zero_in, f, fcs, word, backward, coarse, psi,
                                 variant, cpb);
 }
@@ -392,7 +395,7 @@ mgmc_status enqueue_cycle(mgmc_ctx* c, const void* fL, const double* F, double* 
         if (tiled) {
           const int zin = (zero_start && j == 0) ? 1 : 0;
           mgmc_status st = timed(c, l == top, [&] {
-            return sweep2d(c, lv, state(l), lv.buf[1 - cur[l]], zin, f, fcs, word, 0, nullptr, nullptr);
+            return sweep2d(c, l, state(l), lv.buf[1 - cur[l]], zin, f, fcs, word, 0, nullptr, nullptr);
           });
           if (st != MGMC_OK) return st;
           cur[l] ^= 1;
@@ -425,7 +428,7 @@ mgmc_status enqueue_cycle(mgmc_ctx* c, const void* fL, const double* F, double* 
         if (tiled && !last_in_place) {
           const mgmc::DevLevel* coarse = (j == 0) ? &c->lv[l - 1] : nullptr;
           mgmc_status st = timed(c, l == top, [&] {
-            return sweep2d(c, lv, state(l), lv.buf[1 - cur[l]], 0, f, fcs, word, 1, coarse, coarse ? psi : nullptr);
+            return sweep2d(c, l, state(l), lv.buf[1 - cur[l]], 0, f, fcs, word, 1, coarse, coarse ? psi : nullptr);
           });
           if (st != MGMC_OK) return st;
           cur[l] ^= 1;
@@ -514,6 +517,8 @@ mgmc_status mgmc_setup(const mgmc_problem* problem, const mgmc_obs* obs, void* h
   c->prob.prolong_w = nullptr;
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->levels = problem->levels;
+  c->lvl_variant.assign(size_t(c->levels), -1);
+  c->lvl_cpb.assign(size_t(c->levels), -1);
   c->S = problem->dim == 2 ? 9 : 27;
   c->esz = problem->precision == MGMC_FP32 ? 4 : 8;
   c->L.stream = c->stream;
@@ -637,7 +642,7 @@ mgmc_status mgmc_set_option(mgmc_ctx* c, int32_t option, int64_t value) {
       c->tiled = value != 0;
       return MGMC_OK;
     case MGMC_OPT_SWEEP_VARIANT:
-      if (value < 0 || value > 2) return fail(MGMC_EINVAL, "sweep variant must be 0, 1 or 2");
+      if (value < 0 || value > 3) return fail(MGMC_EINVAL, "sweep variant must be 0, 1, 2 or 3");
       c->sweep_variant = int(value);
       return MGMC_OK;
     case MGMC_OPT_CHAINS_PER_BLOCK:
@@ -646,6 +651,23 @@ mgmc_status mgmc_set_option(mgmc_ctx* c, int32_t option, int64_t value) {
       return MGMC_OK;
     default:
       return fail(MGMC_EINVAL, "unknown option");
+  }
+}
+
+mgmc_status mgmc_set_level_option(mgmc_ctx* c, int32_t level, int32_t option, int64_t value) {
+  if (!c) return fail(MGMC_EINVAL, "context is NULL");
+  if (level < 0 || level >= c->levels) return fail(MGMC_EINVAL, "level out of range");
+  switch (option) {
+    case MGMC_OPT_SWEEP_VARIANT:
+      if (value < -1 || value > 3) return fail(MGMC_EINVAL, "sweep variant must be -1, 0, 1, 2 or 3");
+      c->lvl_variant[level] = int(value);
+      return MGMC_OK;
+    case MGMC_OPT_CHAINS_PER_BLOCK:
+      if (value < -1 || value > 65535) return fail(MGMC_EINVAL, "chains per block out of range");
+      c->lvl_cpb[level] = int(value);
+      return MGMC_OK;
+    default:
+      return fail(MGMC_EINVAL, "option has no per-level form");
   }
 }
 

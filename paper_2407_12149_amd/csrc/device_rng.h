@@ -21,14 +21,15 @@ __device__ __forceinline__ Block4 philox10(uint32_t c0, uint32_t c1, uint32_t c2
                                            uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t a = 0xD2511F53u * c0, ah = __umulhi(0xD2511F53u, c0);
-    const uint32_t b = 0xCD9E8D57u * c2, bh = __umulhi(0xCD9E8D57u, c2);
-    const uint32_t n0 = bh ^ c1 ^ k0;
-    const uint32_t n2 = ah ^ c3 ^ k1;
+    // one 32 x 32 -> 64-bit multiply gives both halves of each product
+    const uint64_t pa = uint64_t(0xD2511F53u) * c0;
+    const uint64_t pb = uint64_t(0xCD9E8D57u) * c2;
+    const uint32_t n0 = uint32_t(pb >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = uint32_t(pa >> 32) ^ c3 ^ k1;
     c0 = n0;
-    c1 = b;
+    c1 = uint32_t(pb);
     c2 = n2;
-    c3 = a;
+    c3 = uint32_t(pa);
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }

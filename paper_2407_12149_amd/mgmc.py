@@ -21,7 +21,7 @@ EXPORTED = [
     "mgmc_setup", "mgmc_sample", "mgmc_posterior_sample", "mgmc_levels", "mgmc_level_sites",
     "mgmc_set_graph", "mgmc_set_option", "mgmc_set_profiling", "mgmc_profile_read", "mgmc_destroy",
     "mgmc_last_error", "mgmc_time_updates", "mgmc_batch_create", "mgmc_batch_sample",
-    "mgmc_batch_destroy", "mgmc_pnet_param_count", "mgmc_pnet_create", "mgmc_pnet_set_params",
+    "mgmc_batch_destroy", "mgmc_set_level_option", "mgmc_pnet_param_count", "mgmc_pnet_create", "mgmc_pnet_set_params",
     "mgmc_pnet_get_params", "mgmc_pnet_weights", "mgmc_pnet_loss_grad", "mgmc_pnet_train_step",
     "mgmc_pnet_destroy",
 ]
@@ -80,6 +80,8 @@ def load_library():
     lib.mgmc_set_graph.argtypes = [vp, ctypes.c_int32]
     lib.mgmc_set_option.restype = ctypes.c_int
     lib.mgmc_set_option.argtypes = [vp, ctypes.c_int32, ctypes.c_int64]
+    lib.mgmc_set_level_option.restype = ctypes.c_int
+    lib.mgmc_set_level_option.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64]
     lib.mgmc_set_profiling.restype = ctypes.c_int
     lib.mgmc_set_profiling.argtypes = [vp, ctypes.c_int32]
     lib.mgmc_profile_read.restype = ctypes.c_int
@@ -203,6 +205,10 @@ def mgmc_set_graph(ctx, enabled):
 
 def mgmc_set_option(ctx, option, value):
     _check(load_library().mgmc_set_option(ctx, int(option), int(value)))
+
+
+def mgmc_set_level_option(ctx, level, option, value):
+    _check(load_library().mgmc_set_level_option(ctx, int(level), int(option), int(value)))
 
 
 def mgmc_set_profiling(ctx, enabled):
@@ -416,6 +422,9 @@ class Sampler:
 
     def set_option(self, option, value):
         mgmc_set_option(self.ctx, option, value)
+
+    def set_level_option(self, level, option, value):
+        mgmc_set_level_option(self.ctx, level, option, value)
 
     def set_profiling(self, enabled):
         mgmc_set_profiling(self.ctx, enabled)

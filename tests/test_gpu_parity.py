@@ -77,7 +77,7 @@ def rel_err(got, want):
 
 
 def check_stepwise(prob, obs, nsamples, y=None, rhs=None, F=None, label="", tiled=True,
-                   variant=None, cpb=None):
+                   variant=None, cpb=None, levels=None):
     from paper_2407_12149_amd import mgmc
     log(f"[parity] {label} dim={prob['dim']} n={prob['n']} levels={prob['levels']} "
         f"beta={0 if obs is None else len(obs[0]) - 1} chains={prob['nchains']} tiled={tiled}")
@@ -89,6 +89,9 @@ def check_stepwise(prob, obs, nsamples, y=None, rhs=None, F=None, label="", tile
         s.set_option(mgmc.MGMC_OPT_SWEEP_VARIANT, variant)
     if cpb is not None:
         s.set_option(mgmc.MGMC_OPT_CHAINS_PER_BLOCK, cpb)
+    if levels is not None:
+        from paper_2407_12149_amd import autotune
+        autotune.apply(s, levels)
     Fd = None if F is None else torch.tensor(F, device="cuda")
     rhsd = None if rhs is None else torch.tensor(rhs, device="cuda")
     worst = 0.0
@@ -127,7 +130,7 @@ def test_posterior_2d_variable_stepwise(tiled):
                    tiled=tiled)
 
 
-@pytest.mark.parametrize("variant,cpb", [(0, 0), (1, 0), (1, 4), (2, 3), (2, 0)])
+@pytest.mark.parametrize("variant,cpb", [(0, 0), (1, 0), (1, 4), (2, 3), (2, 0), (3, 0)])
 def test_posterior_2d_many_tiles_many_chains(variant, cpb):
     """255^2 spans several sweep tiles in both directions with a ragged last
     tile; 9 chains exercise chain groups per block (ragged when cpb = 4)."""
@@ -137,6 +140,16 @@ def test_posterior_2d_many_tiles_many_chains(variant, cpb):
     y = workloads.observed_values(5, seed=6)
     check_stepwise(prob, obs, 2, y=y, F=workloads.subcube_qoi(n, 2),
                    label=f"posterior 255^2 variant {variant} cpb {cpb}", variant=variant, cpb=cpb)
+
+
+def test_per_level_kernel_forms():
+    """A different sweep form and chain grouping on every level."""
+    n = 255
+    face = workloads.face_array(n, 2, workloads.fourier_log_field(2, nmodes=8, seed=4))
+    prob, obs = make_problem(2, n, 5, 30.0, face=face, beta=4, gamma=1e-3, nchains=7)
+    y = workloads.observed_values(4, seed=8)
+    check_stepwise(prob, obs, 2, y=y, label="posterior 255^2 mixed per-level forms",
+                   levels=[None, [2, 3], [0, 0], [1, 5], [2, 1]])
 
 
 def test_prior_3d_stepwise():
@@ -338,8 +351,9 @@ def test_autotune_picks_and_caches(tmp_path):
     best = autotune.autotune(s, cache_path=cache, updates=2)
     assert not best["cached"] and best["ms"] > 0
     again = autotune.autotune(s, cache_path=cache)
-    assert again["cached"] and again["variant"] == best["variant"] and again["cpb"] == best["cpb"]
+    assert again["cached"] and again["levels"] == best["levels"]
     s.close()
     # the tuned options keep oracle parity
+    log(f"[autotune] per-level choice {best['levels']}")
     prob2 = dict(prob, nchains=4)
-    check_stepwise(prob2, None, 2, label="tuned 255^2", variant=best["variant"], cpb=best["cpb"])
+    check_stepwise(prob2, None, 2, label="tuned 255^2", levels=best["levels"])
