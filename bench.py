@@ -176,7 +176,9 @@ def main():
     ap.add_argument("--graph", type=int, default=1)
     ap.add_argument("--fp32", type=int, default=1, help="also run the FP32 sampler (paired)")
     ap.add_argument("--workload", default="posterior1023", choices=["posterior1023", "batched512"])
-    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2407_12149_amd", "tuning.json"))
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON cache of the per-level kernel choices (default: tune afresh)")
+    ap.add_argument("--tune", type=int, default=1, help="autotune the sweep kernels before timing")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB, 20 times "
                          "(reference for the HBM byte counters)")
@@ -197,7 +199,7 @@ def main():
 
     import torch
 
-    from paper_2407_12149_amd import diagnostics, mgmc, workloads
+    from paper_2407_12149_amd import autotune, diagnostics, mgmc, workloads
 
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", 0)))
     if args.workload == "batched512":
@@ -216,6 +218,11 @@ def main():
         t0 = time.perf_counter()
         s = mgmc.Sampler(prob, obs=cfg["obs"])
         setup_s = time.perf_counter() - t0
+        tuned = None
+        if args.tune:
+            s.posterior_sample(y, 0, 2, want_qoi=False)  # right-hand side for the update timer
+            tuned = autotune.autotune(s, cache_path=args.tune_cache)
+            log(f"[bench] {precision}: tuned {tuned}")
         log(f"[bench] {precision}: warmup {args.warmup}")
         s.set_graph(bool(args.graph))
         s.posterior_sample(y, 0, args.warmup, F=F)
@@ -245,7 +252,7 @@ def main():
         per_launch_s = kms / 1e3 / max(launches, 1)
         launches_per_sweep = launches / (2.0 * args.profile_steps)
         bytes_launch = sweep_bytes(n, dim, nch, esz, dim) / launches_per_sweep
-        return dict(seconds=seconds, q=qs, tau=tau, setup_s=setup_s, per_launch_s=per_launch_s,
+        return dict(seconds=seconds, q=qs, tau=tau, setup_s=setup_s, per_launch_s=per_launch_s, tuned=tuned,
                     launches_per_sweep=launches_per_sweep, bytes_launch=bytes_launch,
                     achieved=bytes_launch / per_launch_s / 1e9)
 
@@ -282,7 +289,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "posterior1023", "grid": "1023x1023", "levels": cfg["levels"],
-                   "chains": nch, "sensors": 64, "cycle": "V(1,1)", "graph": bool(args.graph)},
+                   "chains": nch, "sensors": 64, "cycle": "V(1,1)", "graph": bool(args.graph),
+                   "kernel_forms": r64["tuned"]["levels"] if r64["tuned"] else "default"},
         "iact": tau,
         "setup_s": setup_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",

@@ -84,7 +84,7 @@ typedef struct {
 } mgmc_problem;
 
 typedef struct {
-  int32_t beta;            /* number of observations, >= 1 */
+  int32_t beta;            /* number of observations, 1 <= beta <= 2048 */
   const int64_t* ptr;      /* host, beta + 1 offsets into idx/val (CSR over observations) */
   const int32_t* idx;      /* host, fine site index of each weight */
   const double* val;       /* host, weights: column j of B_L (Sec. 2.3 eq. B_ell_definition) */
@@ -99,7 +99,8 @@ typedef struct {
  * hip_stream: a hipStream_t (NULL = default stream) used by every later call.
  * Host arrays are copied; the caller may free them on return.
  * Errors: EINVAL (shape, levels, nu, NULL arrays, gamma <= 0, site index out
- * of range), ENOTSPD, ENOMEM, EDEVICE. */
+ * of range), ENOTSPD, ENOMEM, EDEVICE, EUNSUPPORTED (some level l >= 1 whose
+ * observation matrix B_l holds more than 8192 - 2 beta weights). */
 mgmc_status mgmc_setup(const mgmc_problem* problem, const mgmc_obs* obs, void* hip_stream,
                        mgmc_ctx** out);
 

@@ -20,7 +20,7 @@ def build(verbose: bool = False) -> str:
         "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
         "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
         "-o", LIB + ".tmp",
-    ] + [os.path.join(HERE, s) for s in SOURCES] + ["-lpthread"]
+    ] + [os.path.join(HERE, s) for s in SOURCES] + ["-lpthread", "-Wl,-z,defs"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -58,11 +58,10 @@ struct mgmc_ctx {
   std::vector<mgmc::DevLevel> lv;
   double* K = nullptr;
   double* Uinv = nullptr;
-  double* gisq = nullptr;
-  double* ginv = nullptr;
-  double* xi = nullptr;
-  double* u = nullptr;
-  double* v = nullptr;
+  double* gisq = nullptr;  // Gamma^{-1/2}
+  double* gam = nullptr;   // Gamma (diagonal)
+  double* t = nullptr;     // [nchains][beta] low-rank scratch
+  double* v = nullptr;     // [nchains][beta] Gamma^{-1} B^T theta after pre-smoothing
   int64_t* mcur = nullptr;
   double* qpart = nullptr;
   void* fL = nullptr;  // padded finest right-hand side, shared by the chains
@@ -162,7 +161,7 @@ mgmc_status validate(const mgmc_problem* p, const mgmc_obs* obs) {
         return fail(MGMC_EINVAL, "prolongation weights must be finite");
   }
   if (obs) {
-    if (obs->beta < 1 || obs->beta > 4096) return fail(MGMC_EINVAL, "beta must be in [1, 4096]");
+    if (obs->beta < 1 || obs->beta > 2048) return fail(MGMC_EINVAL, "beta must be in [1, 2048]");
     if (!obs->ptr || !obs->idx || !obs->val || !obs->gamma) return fail(MGMC_EINVAL, "observation arrays must not be NULL");
     if (obs->ptr[0] != 0) return fail(MGMC_EINVAL, "obs ptr[0] must be 0");
     for (int j = 0; j < obs->beta; ++j) {
@@ -238,6 +237,9 @@ mgmc_status upload_level(mgmc_ctx* c, int l) {
       }
       bptr[j + 1] = int64_t(bidx.size());
     }
+    d.bnnz = int64_t(bidx.size());
+    if (l >= 1 && d.bnnz > 8192 - 2 * int64_t(beta))
+      return fail(MGMC_EUNSUPPORTED, "observation weights on a level exceed the low-rank kernel's LDS (8192 - 2 beta)");
     if ((s = c->upload(d.bptr, bptr)) != MGMC_OK) return s;
     if ((s = c->upload(d.bidx, bidx)) != MGMC_OK) return s;
     if ((s = c->upload(d.bval, bval)) != MGMC_OK) return s;
@@ -254,6 +256,11 @@ mgmc_status upload_level(mgmc_ctx* c, int l) {
       brptr.push_back(int64_t(brcol.size()));
     }
     d.nbrows = int32_t(brow.size());
+    {
+      std::vector<int32_t> row_of(size_t(Np), -1);
+      for (size_t r = 0; r < brow.size(); ++r) row_of[size_t(brow[r])] = int32_t(r);
+      if ((s = c->upload(d.brow_of, row_of)) != MGMC_OK) return s;
+    }
     if ((s = c->upload(d.brow, brow)) != MGMC_OK) return s;
     if ((s = c->upload(d.brptr, brptr)) != MGMC_OK) return s;
     if ((s = c->upload(d.brcol, brcol)) != MGMC_OK) return s;
@@ -263,19 +270,18 @@ mgmc_status upload_level(mgmc_ctx* c, int l) {
         const int64_t ns = int64_t(h.supp[dir].size());
         d.nsupp[dir] = int32_t(ns);
         std::vector<int32_t> supp(ns);
-        std::vector<double> CT(size_t(beta) * ns), GT(size_t(beta) * ns);
+        std::vector<double> GT(size_t(beta) * ns);
         for (int64_t r = 0; r < ns; ++r) {
           supp[r] = int32_t(pad[h.supp[dir][r]]);
-          for (int j = 0; j < beta; ++j) {
-            CT[size_t(j) * ns + r] = h.C[dir][size_t(r) * beta + j];
-            GT[size_t(j) * ns + r] = h.G[dir][size_t(r) * beta + j];
-          }
+          for (int j = 0; j < beta; ++j) GT[size_t(j) * ns + r] = h.G[dir][size_t(r) * beta + j];
         }
         if ((s = c->upload(d.supp[dir], supp)) != MGMC_OK) return s;
-        if ((s = c->upload(d.CT[dir], CT)) != MGMC_OK) return s;
         if ((s = c->upload(d.GT[dir], GT)) != MGMC_OK) return s;
-        if ((s = c->upload(d.SmG[dir], h.SmG[dir])) != MGMC_OK) return s;
       }
+      std::vector<double> SinvT(size_t(beta) * beta);
+      for (int a = 0; a < beta; ++a)
+        for (int j = 0; j < beta; ++j) SinvT[size_t(j) * beta + a] = h.Sinv[0][size_t(a) * beta + j];
+      if ((s = c->upload(d.SinvT, SinvT)) != MGMC_OK) return s;
     }
   }
   return MGMC_OK;
@@ -328,21 +334,24 @@ hipError_t sweep2d(mgmc_ctx* c, int l, const void* in, void* out, int zero_in, c
   const int sv = c->lvl_variant[l] >= 0 ? c->lvl_variant[l] : c->sweep_variant;
   if (sv == 0)
     return mgmc::launch_sweep_tiled(c->L, lv, in, out, zero_in, f, fcs, word, backward, coarse, psi);
+  // 512-thread blocks (taller tiles, less redundant halo work) or 256-thread
+  // blocks; the automatic choice takes 512 threads for FP64 four-colour
+  // sweeps with the fused prolongation (register pressure), else 256
+  const bool auto512 = !c->L.fp32 && !lv.cross && coarse != nullptr;
+  const int variant = (sv == 2 || (sv == 3 && auto512)) ? 1 : 0;
   int cpb = c->lvl_cpb[l] >= 0 ? c->lvl_cpb[l] : c->sweep_cpb;
   if (cpb <= 0) {
-    // enough blocks to fill the device, chains grouped so each block reuses
-    // its stencil registers; FP64 groups stay smaller (register pressure)
-    const int tys = lv.cross ? 12 : 22;
+    // each block reuses its stencil registers for a group of up to 8 chains
+    // (reloading the stencil per chain costs more than the state traffic),
+    // as long as at least 512 blocks remain to fill the device
+    const int nch = c->L.nchains;
+    const int tys = lv.cross ? (variant ? 26 : 12) : (variant ? 22 : 8);
     const int64_t tiles = int64_t((lv.g.n + 63) / 64) * ((lv.g.n + tys - 1) / tys);
-    const int nch = c->L.nchains, cap = c->L.fp32 ? 8 : 4;
-    int64_t want = int64_t(nch) * tiles / 1024;
-    cpb = int(std::max<int64_t>(1, std::min<int64_t>(cap, want)));
+    cpb = std::min(nch, 8);
+    while (cpb > 1 && tiles * ((nch + cpb - 1) / cpb) < 512) cpb /= 2;
     const int groups = (nch + cpb - 1) / cpb;
-    cpb = (nch + groups - 1) / groups;  // balance the chain groups
+    cpb = (nch + groups - 1) / groups;  // balance the groups
   }
-  // 512-thread blocks (taller tiles, less redundant halo work) or 256-thread
-  // blocks (more blocks in flight); the automatic choice takes 256 threads
-  const int variant = sv == 2 ? 1 : 0;
   return mgmc::launch_sweep_seg(c->L, lv, in, out, zero_in, f, fcs, word, backward, coarse, psi,
                                 variant, cpb);
 }
@@ -403,18 +412,26 @@ mgmc_status enqueue_cycle(mgmc_ctx* c, const void* fL, const double* F, double* 
           mgmc_status st = in_place_sweep(l, f, fcs, word, false);
           if (st != MGMC_OK) return st;
         }
-        if (beta) MGMC_LAUNCH(mgmc::launch_lowrank(L, lv, state(l), 0, word, beta, c->gisq, c->xi, c->u));
+        if (beta)
+          MGMC_LAUNCH(mgmc::launch_lowrank(L, lv, state(l), 0, word, beta, c->gisq, c->gam, c->t,
+                                           j == nu1 - 1 ? c->v : nullptr));
+      }
+      mgmc::LowRankRhs lr;
+      if (beta) {
+        const mgmc::DevLevel& cl = c->lv[l - 1];
+        lr.row_of = cl.brow_of;
+        lr.ptr = cl.brptr;
+        lr.col = cl.brcol;
+        lr.val = cl.brval;
+        lr.v = c->v;
+        lr.beta = beta;
       }
       if (tiled)
-        MGMC_LAUNCH(mgmc::launch_restrict_tiled(L, lv, state(l), c->lv[l - 1], f, fcs));
+        MGMC_LAUNCH(mgmc::launch_restrict_tiled(L, lv, state(l), c->lv[l - 1], f, fcs, lr));
       else if (c->prob.dim == 3 && c->tiled)
-        MGMC_LAUNCH(mgmc::launch_restrict_2stage(L, lv, state(l), lv.buf[1 - cur[l]], c->lv[l - 1], f, fcs));
+        MGMC_LAUNCH(mgmc::launch_restrict_2stage(L, lv, state(l), lv.buf[1 - cur[l]], c->lv[l - 1], f, fcs, lr));
       else
-        MGMC_LAUNCH(mgmc::launch_restrict(L, lv, state(l), c->lv[l - 1], f, fcs));
-      if (beta) {
-        MGMC_LAUNCH(mgmc::launch_gather_v(L, lv, state(l), beta, c->ginv, c->v));
-        MGMC_LAUNCH(mgmc::launch_coarse_rhs_lowrank(L, c->lv[l - 1], c->v, beta));
-      }
+        MGMC_LAUNCH(mgmc::launch_restrict(L, lv, state(l), c->lv[l - 1], f, fcs, lr));
     }
     MGMC_LAUNCH(mgmc::launch_coarsest(L, c->lv[0], c->lv[0].f, c->lv[0].g.Np, state(0), c->K, c->Uinv));
     for (int l = 1; l <= top; ++l) {
@@ -437,7 +454,8 @@ mgmc_status enqueue_cycle(mgmc_ctx* c, const void* fL, const double* F, double* 
           mgmc_status st = in_place_sweep(l, f, fcs, word, true);
           if (st != MGMC_OK) return st;
         }
-        if (beta) MGMC_LAUNCH(mgmc::launch_lowrank(L, lv, state(l), 1, word, beta, c->gisq, c->xi, c->u));
+        if (beta)
+          MGMC_LAUNCH(mgmc::launch_lowrank(L, lv, state(l), 1, word, beta, c->gisq, c->gam, c->t, nullptr));
       }
     }
   }
@@ -551,16 +569,12 @@ mgmc_status mgmc_setup(const mgmc_problem* problem, const mgmc_obs* obs, void* h
   if ((s = c->alloc(c->qpart, size_t(c->qnb) * problem->nchains)) != MGMC_OK) return cleanup(s);
   if ((s = c->alloc_bytes(c->fL, size_t(c->lv[top].g.Np) * c->esz)) != MGMC_OK) return cleanup(s);
   if (c->beta > 0) {
-    std::vector<double> gisq(c->beta), ginv(c->beta);
-    for (int j = 0; j < c->beta; ++j) {
-      gisq[j] = 1.0 / std::sqrt(c->H.gamma[j]);
-      ginv[j] = 1.0 / c->H.gamma[j];
-    }
+    std::vector<double> gisq(c->beta);
+    for (int j = 0; j < c->beta; ++j) gisq[j] = 1.0 / std::sqrt(c->H.gamma[j]);
     if ((s = c->upload(c->gisq, gisq)) != MGMC_OK) return cleanup(s);
-    if ((s = c->upload(c->ginv, ginv)) != MGMC_OK) return cleanup(s);
+    if ((s = c->upload(c->gam, c->H.gamma)) != MGMC_OK) return cleanup(s);
     const size_t bc = size_t(c->beta) * problem->nchains;
-    if ((s = c->alloc(c->xi, bc)) != MGMC_OK) return cleanup(s);
-    if ((s = c->alloc(c->u, bc)) != MGMC_OK) return cleanup(s);
+    if ((s = c->alloc(c->t, bc)) != MGMC_OK) return cleanup(s);
     if ((s = c->alloc(c->v, bc)) != MGMC_OK) return cleanup(s);
   }
   // keep only what later calls need on the host: the observation columns

@@ -16,6 +16,17 @@ static __device__ __forceinline__ int64_t pidx(const Geom& g, int i1, int i2, in
   return int64_t(i1 + 3) + int64_t(g.px) * (int64_t(i2) + int64_t(g.py) * i3);
 }
 
+// (B_{l-1} v)(J) for coarse padded site iJ and chain c (0 without a low-rank term).
+static __device__ __forceinline__ double lowrank_rhs(const LowRankRhs& lr, int c, int64_t iJ) {
+  if (lr.row_of == nullptr) return 0.0;
+  const int r = lr.row_of[iJ];
+  if (r < 0) return 0.0;
+  double s = 0.0;
+  for (int64_t e = lr.ptr[r]; e < lr.ptr[r + 1]; ++e)
+    s += lr.val[e] * lr.v[int64_t(c) * lr.beta + lr.col[e]];
+  return s;
+}
+
 static __device__ __forceinline__ int64_t poff(const Geom& g, int dx, int dy, int dz) {
   return int64_t(dx) + int64_t(g.px) * (int64_t(dy) + int64_t(g.py) * dz);
 }

@@ -375,6 +375,7 @@ mgmc_status lowrank_level(HostHierarchy& H, int l, std::string& err) {
     lv.C[dir] = std::move(Cs);
     lv.G[dir] = std::move(Gs);
     lv.SmG[dir] = std::move(SmG);
+    lv.Sinv[dir] = std::move(Sinv);
   }
   return MGMC_OK;
 }

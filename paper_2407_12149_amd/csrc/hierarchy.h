@@ -26,9 +26,10 @@ struct HostLevel {
   std::vector<std::vector<std::pair<int64_t, double>>> Bcol;
   // Low-rank smoother for forward (0) and backward (1) sweeps (Alg. 3):
   // rows where C = M^{-1} B is non-zero, C and G = C S^{-1} on those rows
-  // (row-major nsupp x beta), and S - Gamma = B^T C (beta x beta).
+  // (row-major nsupp x beta), S - Gamma = B^T C and S^{-1} (beta x beta,
+  // row-major).
   std::vector<int64_t> supp[2];
-  std::vector<double> C[2], G[2], SmG[2];
+  std::vector<double> C[2], G[2], SmG[2], Sinv[2];
 };
 
 struct HostHierarchy {

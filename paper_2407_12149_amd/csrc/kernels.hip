@@ -10,8 +10,10 @@
 //  * k_prolong: theta_i += sum_J P_iJ psi_J (Alg. 1, prolongation step).
 //  * k_coarsest: theta_0 = K f_0 + U^{-1} z, an exact draw from
 //    N(At_0^{-1} f_0, At_0^{-1}) (Sec. 3.4).
-//  * k_lowrank_*: the low-rank correction of Alg. 3 (see launch_lowrank).
+//  * k_lowrank_*: the low-rank correction of Alg. 3 (see k_lowrank_prep).
 //  * k_qoi_*: q = F^T theta per chain, fixed-order reductions.
+#include <algorithm>
+
 #include "device_common.h"
 #include "device_rng.h"
 #include "mgmc_internal.h"
@@ -126,7 +128,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(const T* __restrict__ coef,
                                                      const T* __restrict__ theta,
                                                      const T* __restrict__ f, int64_t fcs, Geom gf,
                                                      T* __restrict__ fcoarse, Geom gc,
-                                                     const double* __restrict__ wP) {
+                                                     const double* __restrict__ wP, LowRankRhs lr) {
   constexpr int S = DIM == 2 ? 9 : 27;
   const int nc = gc.n;
   const int64_t total = int64_t(nc) * nc * (DIM == 3 ? nc : 1);
@@ -154,7 +156,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(const T* __restrict__ coef,
     const T w = USERP ? T(wP[int64_t(t1) * gc.Np + iJ]) : T(multilinear(ex, ey, ez));
     acc += w * r;
   }
-  fcoarse[int64_t(c) * gc.Np + iJ] = acc;
+  fcoarse[int64_t(c) * gc.Np + iJ] = T(double(acc) - lowrank_rhs(lr, c, iJ));
 }
 
 // Two-stage restriction (used in 3D): r = f - A theta at every fine site,
@@ -186,7 +188,8 @@ __global__ __launch_bounds__(kBlock) void k_residual(const T* __restrict__ coef,
 template <typename T, int DIM, bool USERP>
 __global__ __launch_bounds__(kBlock) void k_restrict_residual(const T* __restrict__ r, Geom gf,
                                                               T* __restrict__ fcoarse, Geom gc,
-                                                              const double* __restrict__ wP) {
+                                                              const double* __restrict__ wP,
+                                                              LowRankRhs lr) {
   constexpr int S = DIM == 2 ? 9 : 27;
   const int nc = gc.n;
   const int64_t total = int64_t(nc) * nc * (DIM == 3 ? nc : 1);
@@ -204,7 +207,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict_residual(const T* __restric
     const T w = USERP ? T(wP[int64_t(t1) * gc.Np + iJ]) : T(multilinear(ex, ey, ez));
     acc += w * rc[pidx(gf, 2 * J1 + ex, 2 * J2 + ey, DIM == 3 ? 2 * J3 + ez : 0)];
   }
-  fcoarse[int64_t(c) * gc.Np + iJ] = acc;
+  fcoarse[int64_t(c) * gc.Np + iJ] = T(double(acc) - lowrank_rhs(lr, c, iJ));
 }
 
 template <typename T, int DIM, bool USERP>
@@ -298,23 +301,29 @@ __global__ __launch_bounds__(kBlock) void k_coarsest(const double* __restrict__ 
   }
 }
 
-// Low-rank smoother (Alg. 3), step 1: xi = Gamma^{-1/2} zeta, w = B^T theta,
-// u = w + (S - Gamma) xi; one wavefront per observation j.
+// Low-rank smoother (Alg. 3), first step, one block per chain, one thread
+// per observation j: xi_j = Gamma_j^{-1/2} zeta_j and t_j = (B^T theta)_j -
+// Gamma_j xi_j.  The correction theta' = theta* - G B^T theta* of the sweep
+// output theta* = theta + C xi (C = M^{-1} B, G = C S^{-1}, S = Gamma + B^T C)
+// equals theta - G t, because C - G (S - Gamma) = G Gamma.  With v_out it
+// also writes v = Gamma^{-1} B^T theta' = xi + S^{-1} t (B^T G = I - Gamma
+// S^{-1}), which feeds the low-rank part of the coarse right-hand side.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_lowrank_prep(const T* __restrict__ theta, int64_t Np,
-                                                         int beta, const double* __restrict__ gisq,
-                                                         const int64_t* __restrict__ bptr,
-                                                         const int32_t* __restrict__ bidx,
-                                                         const double* __restrict__ bval,
-                                                         const double* __restrict__ SmG,
-                                                         double* __restrict__ xi_out,
-                                                         double* __restrict__ u_out, uint32_t word,
-                                                         const int64_t* __restrict__ mcur,
-                                                         uint32_t seed, uint32_t chain0) {
+__global__ __launch_bounds__(kBlock) void k_lowrank_prep(
+    const T* __restrict__ theta, int64_t Np, int beta, const double* __restrict__ gisq,
+    const double* __restrict__ gam, const int64_t* __restrict__ bptr,
+    const int32_t* __restrict__ bidx, const double* __restrict__ bval,
+    const double* __restrict__ SinvT, double* __restrict__ t_out, double* __restrict__ v_out,
+    uint32_t word, const int64_t* __restrict__ mcur, uint32_t seed, uint32_t chain0) {
   extern __shared__ double sh[];
-  double* xi = sh;
-  const int c = blockIdx.y;
+  double* xi = sh;              // [beta]
+  double* tv = sh + beta;       // [beta]
+  double* prod = sh + 2 * beta; // [nnz] weighted site values, then [4][beta] partial sums
+  const int c = blockIdx.x;
   const T* th = theta + int64_t(c) * Np;
+  const int64_t nnz = bptr[beta];
+  // every entry of B^T theta at once: one load chain per entry, no serial walk
+  for (int64_t e = threadIdx.x; e < nnz; e += blockDim.x) prod[e] = bval[e] * double(th[bidx[e]]);
   const uint32_t m = uint32_t(*mcur);
   for (int p = threadIdx.x; 2 * p < beta; p += blockDim.x) {
     const Block4 blk = philox10(uint32_t(p), word, m, 1u, seed, chain0 + c);
@@ -324,85 +333,74 @@ __global__ __launch_bounds__(kBlock) void k_lowrank_prep(const T* __restrict__ t
     if (2 * p + 1 < beta) xi[2 * p + 1] = z1 * gisq[2 * p + 1];
   }
   __syncthreads();
-  if (blockIdx.x == 0)
-    for (int j = threadIdx.x; j < beta; j += blockDim.x) xi_out[int64_t(c) * beta + j] = xi[j];
-  const int lane = threadIdx.x & 63;
-  const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (j >= beta) return;
-  double w = 0.0;
-  for (int64_t e = bptr[j] + lane; e < bptr[j + 1]; e += 64) w += bval[e] * double(th[bidx[e]]);
-  w = wave_sum(w);
-  double a = 0.0;
-  for (int k = lane; k < beta; k += 64) a += SmG[int64_t(j) * beta + k] * xi[k];
-  a = wave_sum(a);
-  if (lane == 0) u_out[int64_t(c) * beta + j] = w + a;
+  for (int j = threadIdx.x; j < beta; j += blockDim.x) {
+    double w = 0.0;
+    for (int64_t e = bptr[j]; e < bptr[j + 1]; ++e) w += prod[e];
+    const double t = w - gam[j] * xi[j];
+    tv[j] = t;
+    t_out[int64_t(c) * beta + j] = t;
+  }
+  if (v_out == nullptr) return;
+  __syncthreads();
+  // v = xi + S^{-1} t: four threads per row, each over a quarter of the columns
+  double* part = prod;
+  const int q = int(threadIdx.x) & 3;
+  for (int j = int(threadIdx.x) >> 2; j < beta; j += int(blockDim.x) >> 2) {
+    double a = 0.0;
+#pragma unroll 8
+    for (int k = q; k < beta; k += 4) a += SinvT[int64_t(k) * beta + j] * tv[k];
+    part[q * beta + j] = a;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < beta; j += blockDim.x)
+    v_out[int64_t(c) * beta + j] = xi[j] + ((part[j] + part[beta + j]) + (part[2 * beta + j] + part[3 * beta + j]));
 }
 
-// Step 2 on the support rows: theta_r += sum_j C_rj xi_j - sum_j G_rj u_j,
-// one thread per (row, chain); C and G are shared by the chains through L2.
-template <typename T>
+// Second step on the support rows: theta_r -= sum_j G_rj t_j for up to CB
+// chains per thread, so each entry of G is read once per chain group; four
+// threads share a row, each over a quarter of the columns.
+template <typename T, int CB>
 __global__ __launch_bounds__(kBlock) void k_lowrank_apply(T* __restrict__ theta, int64_t Np,
                                                           int beta, int nsupp,
                                                           const int32_t* __restrict__ supp,
-                                                          const double* __restrict__ CT,
                                                           const double* __restrict__ GT,
-                                                          const double* __restrict__ xi,
-                                                          const double* __restrict__ u) {
-  extern __shared__ double sh[];
-  double* xs = sh;
-  double* us = sh + beta;
-  const int c = blockIdx.y;
-  for (int j = threadIdx.x; j < beta; j += blockDim.x) {
-    xs[j] = xi[int64_t(c) * beta + j];
-    us[j] = u[int64_t(c) * beta + j];
+                                                          const double* __restrict__ t,
+                                                          int nchains) {
+  extern __shared__ double sh[];  // [CB][beta] t of the chain group, then [4][CB][64] partials
+  double* red = sh + CB * beta;
+  const int c0 = blockIdx.y * CB;
+  const int nc = min(CB, nchains - c0);
+  for (int e = threadIdx.x; e < CB * beta; e += blockDim.x) {
+    const int cc = e / beta, j = e % beta;
+    sh[e] = cc < nc ? t[int64_t(c0 + cc) * beta + j] : 0.0;
   }
   __syncthreads();
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nsupp) return;
-  double a = 0.0, b = 0.0;
-#pragma unroll 8
-  for (int j = 0; j < beta; ++j) {
-    a += CT[int64_t(j) * nsupp + r] * xs[j];
-    b += GT[int64_t(j) * nsupp + r] * us[j];
+  const int lr = int(threadIdx.x) & 63, q = int(threadIdx.x) >> 6;  // row in block, quarter
+  const int r = blockIdx.x * 64 + lr;
+  double acc[CB];
+#pragma unroll
+  for (int cc = 0; cc < CB; ++cc) acc[cc] = 0.0;
+  if (r < nsupp) {
+#pragma unroll 4
+    for (int j = q; j < beta; j += 4) {
+      const double g = GT[int64_t(j) * nsupp + r];
+#pragma unroll
+      for (int cc = 0; cc < CB; ++cc) acc[cc] += g * sh[cc * beta + j];
+    }
   }
-  T* th = theta + int64_t(c) * Np;
+#pragma unroll
+  for (int cc = 0; cc < CB; ++cc) red[(q * CB + cc) * 64 + lr] = acc[cc];
+  __syncthreads();
+  if (q != 0 || r >= nsupp) return;
   const int64_t at = supp[r];
-  th[at] = T(double(th[at]) + a - b);
-}
-
-// v = Gamma^{-1} B^T theta after the pre-smoother (feeds the coarse rhs).
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_gather_v(const T* __restrict__ theta, int64_t Np,
-                                                     int beta, const int64_t* __restrict__ bptr,
-                                                     const int32_t* __restrict__ bidx,
-                                                     const double* __restrict__ bval,
-                                                     const double* __restrict__ ginv,
-                                                     double* __restrict__ v) {
-  const int c = blockIdx.x;
-  const T* th = theta + int64_t(c) * Np;
-  for (int j = threadIdx.x; j < beta; j += blockDim.x) {
-    double acc = 0.0;
-    for (int64_t e = bptr[j]; e < bptr[j + 1]; ++e) acc += bval[e] * double(th[bidx[e]]);
-    v[int64_t(c) * beta + j] = acc * ginv[j];
+#pragma unroll
+  for (int cc = 0; cc < CB; ++cc) {
+    if (cc >= nc) break;
+    const double d = (red[cc * 64 + lr] + red[(CB + cc) * 64 + lr]) +
+                     (red[(2 * CB + cc) * 64 + lr] + red[(3 * CB + cc) * 64 + lr]);
+    T* th = theta + int64_t(c0 + cc) * Np;
+    th[at] = T(double(th[at]) - d);
   }
-}
-
-// f_{l-1} -= B_{l-1} v on the rows of B_{l-1}: the low-rank part of the
-// restricted residual, P^T B_l v = B_{l-1} v.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_coarse_rhs_lr(T* __restrict__ fc, int64_t Np,
-                                                          const double* __restrict__ v, int beta,
-                                                          int nrows, const int32_t* __restrict__ brow,
-                                                          const int64_t* __restrict__ brptr,
-                                                          const int32_t* __restrict__ brcol,
-                                                          const double* __restrict__ brval) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrows) return;
-  const int c = blockIdx.y;
-  double s = 0.0;
-  for (int64_t e = brptr[r]; e < brptr[r + 1]; ++e) s += brval[e] * v[int64_t(c) * beta + brcol[e]];
-  T* f = fc + int64_t(c) * Np;
-  f[brow[r]] = T(double(f[brow[r]]) - s);
 }
 
 template <typename T>
@@ -551,7 +549,8 @@ hipError_t launch_sweep_parity3d(const Launch& L, const DevLevel& lv, void* thet
 }
 
 hipError_t launch_restrict(const Launch& L, const DevLevel& fine, const void* theta,
-                           const DevLevel& coarse, const void* f, int64_t fcs) {
+                           const DevLevel& coarse, const void* f, int64_t fcs,
+                           const LowRankRhs& lr) {
   dim3 grid(blocks_for(coarse.N), L.nchains);
   MGMC_DISPATCH(L, {
     const T* cf = (const T*)fine.coef;
@@ -559,14 +558,14 @@ hipError_t launch_restrict(const Launch& L, const DevLevel& fine, const void* th
     T* out = (T*)coarse.f;
     if (fine.wP) {
       if (fine.cross)
-        k_restrict<T, DIM, true, true><<<grid, kBlock, 0, L.stream>>>(cf, th, (const T*)f, fcs, fine.g, out, coarse.g, fine.wP);
+        k_restrict<T, DIM, true, true><<<grid, kBlock, 0, L.stream>>>(cf, th, (const T*)f, fcs, fine.g, out, coarse.g, fine.wP, lr);
       else
-        k_restrict<T, DIM, false, true><<<grid, kBlock, 0, L.stream>>>(cf, th, (const T*)f, fcs, fine.g, out, coarse.g, fine.wP);
+        k_restrict<T, DIM, false, true><<<grid, kBlock, 0, L.stream>>>(cf, th, (const T*)f, fcs, fine.g, out, coarse.g, fine.wP, lr);
     } else {
       if (fine.cross)
-        k_restrict<T, DIM, true, false><<<grid, kBlock, 0, L.stream>>>(cf, th, (const T*)f, fcs, fine.g, out, coarse.g, nullptr);
+        k_restrict<T, DIM, true, false><<<grid, kBlock, 0, L.stream>>>(cf, th, (const T*)f, fcs, fine.g, out, coarse.g, nullptr, lr);
       else
-        k_restrict<T, DIM, false, false><<<grid, kBlock, 0, L.stream>>>(cf, th, (const T*)f, fcs, fine.g, out, coarse.g, nullptr);
+        k_restrict<T, DIM, false, false><<<grid, kBlock, 0, L.stream>>>(cf, th, (const T*)f, fcs, fine.g, out, coarse.g, nullptr, lr);
     }
   });
   return hipGetLastError();
@@ -574,7 +573,7 @@ hipError_t launch_restrict(const Launch& L, const DevLevel& fine, const void* th
 
 hipError_t launch_restrict_2stage(const Launch& L, const DevLevel& fine, const void* theta,
                                   void* scratch, const DevLevel& coarse, const void* f,
-                                  int64_t fcs) {
+                                  int64_t fcs, const LowRankRhs& lr) {
   if (scratch == nullptr || scratch == theta) return hipErrorInvalidValue;
   dim3 g1(blocks_for(fine.N), L.nchains), g2(blocks_for(coarse.N), L.nchains);
   MGMC_DISPATCH(L, {
@@ -583,9 +582,9 @@ hipError_t launch_restrict_2stage(const Launch& L, const DevLevel& fine, const v
     else
       k_residual<T, DIM, false><<<g1, kBlock, 0, L.stream>>>((const T*)fine.coef, (const T*)theta, (const T*)f, fcs, fine.g, fine.N, (T*)scratch);
     if (fine.wP)
-      k_restrict_residual<T, DIM, true><<<g2, kBlock, 0, L.stream>>>((const T*)scratch, fine.g, (T*)coarse.f, coarse.g, fine.wP);
+      k_restrict_residual<T, DIM, true><<<g2, kBlock, 0, L.stream>>>((const T*)scratch, fine.g, (T*)coarse.f, coarse.g, fine.wP, lr);
     else
-      k_restrict_residual<T, DIM, false><<<g2, kBlock, 0, L.stream>>>((const T*)scratch, fine.g, (T*)coarse.f, coarse.g, nullptr);
+      k_restrict_residual<T, DIM, false><<<g2, kBlock, 0, L.stream>>>((const T*)scratch, fine.g, (T*)coarse.f, coarse.g, nullptr, lr);
   });
   return hipGetLastError();
 }
@@ -615,43 +614,31 @@ hipError_t launch_coarsest(const Launch& L, const DevLevel& lv0, const void* f0,
 }
 
 hipError_t launch_lowrank(const Launch& L, const DevLevel& lv, void* theta, int dir, uint32_t word,
-                          int beta, const double* gisq, double* xi, double* u) {
-  if (L.mcur == nullptr) return hipErrorInvalidValue;
-  dim3 pgrid(unsigned((beta + 3) / 4), unsigned(L.nchains));
-  const size_t pshm = size_t(beta) * sizeof(double);
-  if (L.fp32) {
-    k_lowrank_prep<float><<<pgrid, kBlock, pshm, L.stream>>>((const float*)theta, lv.g.Np, beta, gisq, lv.bptr, lv.bidx, lv.bval, lv.SmG[dir], xi, u, word, L.mcur, L.seed, L.chain0);
-  } else {
-    k_lowrank_prep<double><<<pgrid, kBlock, pshm, L.stream>>>((const double*)theta, lv.g.Np, beta, gisq, lv.bptr, lv.bidx, lv.bval, lv.SmG[dir], xi, u, word, L.mcur, L.seed, L.chain0);
-  }
+                          int beta, const double* gisq, const double* gam, double* t,
+                          double* v_out) {
+  if (L.mcur == nullptr || (v_out != nullptr && lv.SinvT == nullptr)) return hipErrorInvalidValue;
+  if (lv.bnnz > 8192 - 2 * int64_t(beta) || beta > 2048) return hipErrorInvalidValue;
+  const size_t pshm = size_t(std::max<int64_t>(2 * beta + lv.bnnz, 6 * int64_t(beta))) * sizeof(double);
+  if (L.fp32)
+    k_lowrank_prep<float><<<L.nchains, kBlock, pshm, L.stream>>>((const float*)theta, lv.g.Np, beta, gisq, gam, lv.bptr, lv.bidx, lv.bval, lv.SinvT, t, v_out, word, L.mcur, L.seed, L.chain0);
+  else
+    k_lowrank_prep<double><<<L.nchains, kBlock, pshm, L.stream>>>((const double*)theta, lv.g.Np, beta, gisq, gam, lv.bptr, lv.bidx, lv.bval, lv.SinvT, t, v_out, word, L.mcur, L.seed, L.chain0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || lv.nsupp[dir] == 0) return e;
-  const size_t ashm = size_t(2) * beta * sizeof(double);
-  dim3 agrid(blocks_for(lv.nsupp[dir]), unsigned(L.nchains));
-  if (L.fp32)
-    k_lowrank_apply<float><<<agrid, kBlock, ashm, L.stream>>>((float*)theta, lv.g.Np, beta, lv.nsupp[dir], lv.supp[dir], lv.CT[dir], lv.GT[dir], xi, u);
-  else
-    k_lowrank_apply<double><<<agrid, kBlock, ashm, L.stream>>>((double*)theta, lv.g.Np, beta, lv.nsupp[dir], lv.supp[dir], lv.CT[dir], lv.GT[dir], xi, u);
-  return hipGetLastError();
-}
-
-hipError_t launch_gather_v(const Launch& L, const DevLevel& lv, const void* theta, int beta,
-                           const double* ginv, double* v) {
-  if (L.fp32)
-    k_gather_v<float><<<L.nchains, kBlock, 0, L.stream>>>((const float*)theta, lv.g.Np, beta, lv.bptr, lv.bidx, lv.bval, ginv, v);
-  else
-    k_gather_v<double><<<L.nchains, kBlock, 0, L.stream>>>((const double*)theta, lv.g.Np, beta, lv.bptr, lv.bidx, lv.bval, ginv, v);
-  return hipGetLastError();
-}
-
-hipError_t launch_coarse_rhs_lowrank(const Launch& L, const DevLevel& coarse, const double* v,
-                                     int beta) {
-  if (coarse.nbrows == 0) return hipSuccess;
-  dim3 grid(blocks_for(coarse.nbrows), L.nchains);
-  if (L.fp32)
-    k_coarse_rhs_lr<float><<<grid, kBlock, 0, L.stream>>>((float*)coarse.f, coarse.g.Np, v, beta, coarse.nbrows, coarse.brow, coarse.brptr, coarse.brcol, coarse.brval);
-  else
-    k_coarse_rhs_lr<double><<<grid, kBlock, 0, L.stream>>>((double*)coarse.f, coarse.g.Np, v, beta, coarse.nbrows, coarse.brow, coarse.brptr, coarse.brcol, coarse.brval);
+  // chain groups of 8 share each G entry; LDS holds t of the group and the
+  // partial sums (<= 64 KiB)
+  const int cb = beta <= 768 ? 8 : 1;
+  const size_t ashm = (size_t(cb) * beta + size_t(4) * cb * 64) * sizeof(double);
+  dim3 agrid(unsigned((lv.nsupp[dir] + 63) / 64), unsigned((L.nchains + cb - 1) / cb));
+#define MGMC_LR_APPLY(T, CB)                                                                      \
+  k_lowrank_apply<T, CB><<<agrid, kBlock, ashm, L.stream>>>((T*)theta, lv.g.Np, beta, lv.nsupp[dir], \
+                                                           lv.supp[dir], lv.GT[dir], t, L.nchains)
+  if (L.fp32) {
+    if (cb == 8) MGMC_LR_APPLY(float, 8); else MGMC_LR_APPLY(float, 1);
+  } else {
+    if (cb == 8) MGMC_LR_APPLY(double, 8); else MGMC_LR_APPLY(double, 1);
+  }
+#undef MGMC_LR_APPLY
   return hipGetLastError();
 }
 

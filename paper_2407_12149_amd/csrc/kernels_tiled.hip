@@ -26,33 +26,55 @@ namespace {
 
 constexpr int kFwdOrder2[4] = {0, 3, 1, 2};
 
+// (P psi)(x, y) for fine node (x, y): the coarse nodes J with |x - 2 J| <= 1
+// per axis are J0 = x >> 1 (offset x & 1) and, for odd x, J1 = (x + 1) >> 1
+// (offset -1); for even x, J1 = J0 enters with weight 0, so every node takes
+// the same four reads and the sum runs in a fixed order (J0y,J0x), (J0y,J1x),
+// (J1y,J0x), (J1y,J1x).  get(jx, jy) reads psi at coarse node (jx, jy).
+template <typename T, bool USERP, class Get>
+__device__ __forceinline__ T prolong_sum(Get get, const Geom& gc, const double* __restrict__ wP,
+                                         int x, int y) {
+  const int px = x & 1, py = y & 1;
+  const int jx0 = x >> 1, jx1 = (x + 1) >> 1, jy0 = y >> 1, jy1 = (y + 1) >> 1;
+  const T v00 = get(jx0, jy0), v01 = get(jx1, jy0), v10 = get(jx0, jy1), v11 = get(jx1, jy1);
+  T w00, w01, w10, w11;
+  if (USERP) {
+    auto W = [&](int jx, int jy, int dx, int dy) {
+      return T(wP[int64_t((dx + 1) + 3 * (dy + 1)) * gc.Np + pidx(gc, jx, jy, 0)]);
+    };
+    w00 = W(jx0, jy0, px, py);
+    w01 = px ? W(jx1, jy0, -1, py) : T(0);
+    w10 = py ? W(jx0, jy1, px, -1) : T(0);
+    w11 = (px && py) ? W(jx1, jy1, -1, -1) : T(0);
+  } else {
+    const T hx0 = px ? T(0.5) : T(1), hx1 = px ? T(0.5) : T(0);
+    const T hy0 = py ? T(0.5) : T(1), hy1 = py ? T(0.5) : T(0);
+    w00 = hx0 * hy0;
+    w01 = hx1 * hy0;
+    w10 = hx0 * hy1;
+    w11 = hx1 * hy1;
+  }
+  T s = w00 * v00;
+  s += w01 * v01;
+  s += w10 * v10;
+  s += w11 * v11;
+  return s;
+}
+
 template <typename T, bool USERP>
 __device__ __forceinline__ T prolong_at(const T* __restrict__ ps, const Geom& gc,
                                         const double* __restrict__ wP, int x, int y) {
-  int Jx[2], Dx[2], Jy[2], Dy[2];
-  int nx, ny;
-  if ((x & 1) == 0) {
-    Jx[0] = x >> 1; Dx[0] = 0; nx = 1;
-  } else {
-    Jx[0] = (x - 1) >> 1; Dx[0] = 1; Jx[1] = (x + 1) >> 1; Dx[1] = -1; nx = 2;
-  }
-  if ((y & 1) == 0) {
-    Jy[0] = y >> 1; Dy[0] = 0; ny = 1;
-  } else {
-    Jy[0] = (y - 1) >> 1; Dy[0] = 1; Jy[1] = (y + 1) >> 1; Dy[1] = -1; ny = 2;
-  }
-  T s = T(0);
-  for (int ay = 0; ay < ny; ++ay)
-    for (int ax = 0; ax < nx; ++ax) {
-      const int64_t jc = pidx(gc, Jx[ax], Jy[ay], 0);
-      T w;
-      if (USERP)
-        w = T(wP[int64_t((Dx[ax] + 1) + 3 * (Dy[ay] + 1)) * gc.Np + jc]);
-      else
-        w = T(multilinear(Dx[ax], Dy[ay], 0));
-      s += w * ps[jc];
-    }
-  return s;
+  return prolong_sum<T, USERP>([&](int jx, int jy) { return ps[pidx(gc, jx, jy, 0)]; }, gc, wP, x, y);
+}
+
+// The same from a coarse patch staged in LDS: sp holds the coarse nodes J
+// with J - (jx0, jy0) in [0, cw) x [0, ch), row-major.
+template <typename T, bool USERP>
+__device__ __forceinline__ T prolong_lds(const T* __restrict__ sp, int cw, int jx0, int jy0,
+                                         const Geom& gc, const double* __restrict__ wP, int x,
+                                         int y) {
+  return prolong_sum<T, USERP>([&](int jx, int jy) { return sp[(jy - jy0) * cw + (jx - jx0)]; }, gc,
+                               wP, x, y);
 }
 
 // LDS layout of a tile row: four sub-rows by x mod 4, each of odd length W,
@@ -215,6 +237,10 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
   static_assert(GA + HALF * SX <= NT, "block too small for the segment grid");
   using Z = Swz<RX>;
   __shared__ T sh[RY * Z::RS];
+  // coarse patch under the tile region for the fused prolongation
+  constexpr int CRX = RX / 2 + 2, CRY = RY / 2 + 2;
+  constexpr int KP = PROLONG ? (CRX * CRY + NT - 1) / NT : 0;
+  __shared__ T spsi[PROLONG ? CRY * CRX : 1];
   const int n = g.n;
   const int tx0 = int(blockIdx.x % tiles_x) * TX + 1;
   const int ty0 = int(blockIdx.x / tiles_x) * TYS + 1;
@@ -251,6 +277,33 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
     isd[k] = in ? isqd[gi] : T(0);
     rhs[k] = (in && f && fcs == 0) ? f[gi] : T(0);
   }
+  // The passes this thread updates sites in ("slots"): on red-black levels
+  // both passes (each row holds both colours), on four-colour levels the
+  // two passes whose colours live on rows of this thread's parity.
+  auto pass_colour = [&](int p) -> int {
+    const int pos = backward ? NPASS - 1 - p : p;
+    if (NPASS == 2) {
+      const int ypar = y & 1;
+      return (pos == 0 ? ypar : 1 - ypar) | (ypar << 1);
+    }
+    return kFwdOrder2[pos];
+  };
+  auto pass_active = [&](int p) -> bool {
+    const int hp = NPASS - 1 - p;
+    return row_in && y >= ty0 - hp && y <= ty0 + TYS - 1 + hp &&
+           (NPASS == 2 || ((pass_colour(p) >> 1) & 1) == (y & 1));
+  };
+  int pslot[2];
+  if (NPASS == 2) {
+    pslot[0] = 0;
+    pslot[1] = 1;
+  } else {  // forward positions of colours {0, 1} (even rows) or {3, 2} (odd rows)
+    const int pos0 = (y & 1) ? 1 : 0, pos1 = pos0 + 2;
+    pslot[0] = backward ? NPASS - 1 - pos0 : pos0;
+    pslot[1] = backward ? NPASS - 1 - pos1 : pos1;
+  }
+  constexpr int KF = (RX * RY + NT - 1) / NT;  // tile elements loaded per thread
+  constexpr bool HOIST = CROSS || !PROLONG || sizeof(T) == 4;
   const int cb = int(blockIdx.y) * cpb;
   const int ce = min(nchains, cb + cpb);
   for (int c = cb; c < ce; ++c) {
@@ -263,38 +316,71 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
         rhs[k] = (row_in && x >= 1 && x <= n) ? f[int64_t(c) * fcs + pidx(g, x, y, 0)] : T(0);
       }
     }
-    for (int idx = threadIdx.x; idx < RX * RY; idx += NT) {
+    // issue the tile loads (and those of the coarse patch) into registers ...
+    const int jx0 = ox >> 1, jy0 = oy >> 1;  // first coarse node under the region
+    T pv[KP > 0 ? KP : 1];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int e = int(threadIdx.x) + k * NT;
+      const int Jx = jx0 + e % CRX, Jy = jy0 + e / CRX;
+      pv[k] = (e < CRX * CRY && Jx >= 1 && Jx <= gc.n && Jy >= 1 && Jy <= gc.n)
+                  ? psi[int64_t(c) * gc.Np + pidx(gc, Jx, Jy, 0)]
+                  : T(0);
+    }
+    T fv[KF];
+#pragma unroll
+    for (int k = 0; k < KF; ++k) {
+      const int idx = int(threadIdx.x) + k * NT;
       const int xx = ox + idx % RX, yy = oy + idx / RX;
-      T v = T(0);
-      if (xx >= 1 && xx <= n && yy >= 1 && yy <= n) {
-        if (!zero_in) v = thi[pidx(g, xx, yy, 0)];
-        if (PROLONG) v += prolong_at<T, USERP>(psi + int64_t(c) * gc.Np, gc, wP, xx, yy);
+      fv[k] = (!zero_in && idx < RX * RY && xx >= 1 && xx <= n && yy >= 1 && yy <= n)
+                  ? thi[pidx(g, xx, yy, 0)]
+                  : T(0);
+    }
+    // ... and draw this chain's noise while they are in flight (except where
+    // registers are scarce: FP64 four-colour levels with the prolongation)
+    auto draw = [&](int p, T& z0, T& z1) {
+      const int colour = pass_colour(p);
+      const int xpar = colour & 1;
+      const int m1 = xpar ? (n + 1) / 2 : (n - 1) / 2;
+      const int qx = (m1 + 1) / 2;
+      const uint32_t pair = uint32_t(q) + uint32_t(qx) * uint32_t((y - 1) >> 1);
+      const Block4 blk = philox10(pair, word | uint32_t(colour), m, 0u, seed, chain0 + c);
+      Gauss<T>::pair(blk, z0, z1);
+    };
+    T zz[2][2];
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      zz[sl][0] = zz[sl][1] = T(0);
+      if (HOIST && pass_active(pslot[sl])) draw(pslot[sl], zz[sl][0], zz[sl][1]);
+    }
+    if (PROLONG) {
+#pragma unroll
+      for (int k = 0; k < KP; ++k) {
+        const int e = int(threadIdx.x) + k * NT;
+        if (e < CRX * CRY) spsi[e] = pv[k];
       }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < KF; ++k) {
+      const int idx = int(threadIdx.x) + k * NT;
+      if (idx >= RX * RY) continue;
+      const int xx = ox + idx % RX, yy = oy + idx / RX;
+      T v = fv[k];
+      if (PROLONG && xx >= 1 && xx <= n && yy >= 1 && yy <= n)
+        v += prolong_lds<T, USERP>(spsi, CRX, jx0, jy0, gc, wP, xx, yy);
       sh[Z::pos(idx % RX, idx / RX)] = v;
     }
     __syncthreads();
 #pragma unroll
     for (int p = 0; p < NPASS; ++p) {
-      const int pos = backward ? NPASS - 1 - p : p;
       const int hp = NPASS - 1 - p;
-      int colour;
-      if (NPASS == 2) {
-        const int ypar = y & 1;
-        colour = (pos == 0 ? ypar : 1 - ypar) | (ypar << 1);
-      } else {
-        colour = kFwdOrder2[pos];
-      }
-      const bool active = row_in && y >= ty0 - hp && y <= ty0 + TYS - 1 + hp &&
-                          (NPASS == 2 || ((colour >> 1) & 1) == (y & 1));
-      if (active) {
+      if ((p == pslot[0] || p == pslot[1]) && pass_active(p)) {
+        const int colour = pass_colour(p);
         const int xpar = colour & 1;
         const int k0 = xpar ? 0 : 1;  // offset of the colour's first site in the segment
-        const int m1 = xpar ? (n + 1) / 2 : (n - 1) / 2;
-        const int qx = (m1 + 1) / 2;
-        const uint32_t pair = uint32_t(q) + uint32_t(qx) * uint32_t((y - 1) >> 1);
-        const Block4 blk = philox10(pair, word | uint32_t(colour), m, 0u, seed, chain0 + c);
-        T z[2];
-        Gauss<T>::pair(blk, z[0], z[1]);
+        T z[2] = {p == pslot[0] ? zz[0][0] : zz[1][0], p == pslot[0] ? zz[0][1] : zz[1][1]};
+        if (!HOIST) draw(p, z[0], z[1]);
         const int xlo = max(1, tx0 - hp), xhi = min(n, tx0 + TX - 1 + hp);
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
@@ -339,7 +425,7 @@ template <typename T, bool CROSS, bool USERP, int CTX, int CTY>
 __global__ __launch_bounds__(kBlock) void k_restrict2d_tiled(
     const T* __restrict__ coef, const T* __restrict__ theta, const T* __restrict__ f, int64_t fcs,
     Geom gf, T* __restrict__ fcoarse, Geom gc, const double* __restrict__ wP, int tiles_x, int cpb,
-    int nchains) {
+    int nchains, LowRankRhs lr) {
   constexpr int RXr = 2 * CTX + 1, RYr = 2 * CTY + 1;  // fine residual region
   constexpr int RXt = RXr + 2, RYt = RYr + 2;          // theta region (one more ring)
   __shared__ T sth[RYt * RXt];
@@ -389,7 +475,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict2d_tiled(
         const T w = USERP ? T(wP[int64_t(t1) * gc.Np + iJ]) : T(multilinear(ex, ey, 0));
         acc += w * sr[(ly + ey) * RXr + (lx + ex)];
       }
-      fcoarse[int64_t(c) * gc.Np + iJ] = acc;
+      fcoarse[int64_t(c) * gc.Np + iJ] = T(double(acc) - lowrank_rhs(lr, c, iJ));
     }
     __syncthreads();
   }
@@ -491,7 +577,8 @@ hipError_t launch_sweep_seg(const Launch& L, const DevLevel& lv, const void* the
 }
 
 hipError_t launch_restrict_tiled(const Launch& L, const DevLevel& fine, const void* theta,
-                                 const DevLevel& coarse, const void* f, int64_t fcs) {
+                                 const DevLevel& coarse, const void* f, int64_t fcs,
+                                 const LowRankRhs& lr) {
   if (L.dim != 2) return hipErrorInvalidValue;
   const int nc = coarse.g.n;
   const int tiles_x = (nc + kCTX - 1) / kCTX, tiles_y = (nc + kCTY - 1) / kCTY;
@@ -502,7 +589,7 @@ hipError_t launch_restrict_tiled(const Launch& L, const DevLevel& fine, const vo
 #define MGMC_RESTRICT_T(T, CR, UP)                                                              \
   k_restrict2d_tiled<T, CR, UP, kCTX, kCTY><<<grid, kBlock, 0, L.stream>>>(                     \
       (const T*)fine.coef, (const T*)theta, (const T*)f, fcs, fine.g, (T*)coarse.f, coarse.g,       \
-      fine.wP, tiles_x, cpb, L.nchains)
+      fine.wP, tiles_x, cpb, L.nchains, lr)
   if (L.fp32) {
     if (fine.cross) { if (userp) MGMC_RESTRICT_T(float, true, true); else MGMC_RESTRICT_T(float, true, false); }
     else { if (userp) MGMC_RESTRICT_T(float, false, true); else MGMC_RESTRICT_T(float, false, false); }

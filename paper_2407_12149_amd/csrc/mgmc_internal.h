@@ -35,6 +35,7 @@ struct DevLevel {
   void* f = nullptr;             // [nchains][Np] (levels below the finest)
   // observations B_l: columns (for B^T theta) and rows (for coarse rhs)
   int64_t* bptr = nullptr;       // [beta + 1]
+  int64_t bnnz = 0;              // entries of B_l
   int32_t* bidx = nullptr;       // padded site of each weight
   double* bval = nullptr;
   int32_t nbrows = 0;
@@ -42,12 +43,23 @@ struct DevLevel {
   int64_t* brptr = nullptr;      // [nbrows + 1]
   int32_t* brcol = nullptr;      // observation index
   double* brval = nullptr;
+  int32_t* brow_of = nullptr;    // [Np]: row of B_l at a padded site, -1 if none
   // low-rank smoother for forward (0) / backward (1) sweeps
   int32_t nsupp[2] = {0, 0};
   int32_t* supp[2] = {nullptr, nullptr};   // padded sites
-  double* CT[2] = {nullptr, nullptr};      // [beta][nsupp]
-  double* GT[2] = {nullptr, nullptr};      // [beta][nsupp]
-  double* SmG[2] = {nullptr, nullptr};     // [beta][beta], S - Gamma
+  double* GT[2] = {nullptr, nullptr};      // [beta][nsupp], G = C S^{-1}
+  double* SinvT = nullptr;                 // [beta][beta], S^{-1} of the forward sweep, transposed
+};
+
+// The low-rank part of the restricted residual, B_{l-1} v with
+// v = Gamma^{-1} B_l^T theta (per chain), added by the restriction kernels.
+struct LowRankRhs {
+  const int32_t* row_of = nullptr;  // coarse level: row of B_{l-1} at a padded site, or -1
+  const int64_t* ptr = nullptr;
+  const int32_t* col = nullptr;
+  const double* val = nullptr;
+  const double* v = nullptr;        // [nchains][beta]
+  int beta = 0;
 };
 
 struct Launch {
@@ -84,25 +96,30 @@ hipError_t launch_sweep_seg(const Launch& L, const DevLevel& lv, const void* the
                             void* theta_out, int zero_in, const void* f, int64_t fcs,
                             uint32_t word, int backward, const DevLevel* coarse, const void* psi,
                             int variant, int cpb_override);
+// Restriction f_{l-1} = P^T (f_l - A_l theta) - B_{l-1} v (the last term
+// from lr when lr.row_of is set).
 hipError_t launch_restrict_tiled(const Launch& L, const DevLevel& fine, const void* theta,
-                                 const DevLevel& coarse, const void* f, int64_t fcs);
+                                 const DevLevel& coarse, const void* f, int64_t fcs,
+                                 const LowRankRhs& lr);
 hipError_t launch_restrict(const Launch& L, const DevLevel& fine, const void* theta,
-                           const DevLevel& coarse, const void* f, int64_t fcs);
+                           const DevLevel& coarse, const void* f, int64_t fcs,
+                           const LowRankRhs& lr);
 // Residual into scratch (a second state buffer of the fine level), then
 // restriction of the residual: for 3D, where a coarse node's support is large.
 hipError_t launch_restrict_2stage(const Launch& L, const DevLevel& fine, const void* theta,
                                   void* scratch, const DevLevel& coarse, const void* f,
-                                  int64_t fcs);
+                                  int64_t fcs, const LowRankRhs& lr);
 hipError_t launch_prolong(const Launch& L, const DevLevel& fine, void* theta,
                           const DevLevel& coarse, const void* psi);
 hipError_t launch_coarsest(const Launch& L, const DevLevel& lv0, const void* f0, int64_t fcs,
                            void* theta0, const double* K, const double* Uinv);
+// Low-rank correction after a sweep in direction dir (Alg. 3):
+// theta -= G (B^T theta - Gamma xi) with xi = Gamma^{-1/2} zeta; t receives
+// B^T theta - Gamma xi per chain ([nchains][beta] scratch).  v_out != nullptr
+// (forward sweeps) also receives v = Gamma^{-1} B^T theta' = xi + S^{-1} t.
 hipError_t launch_lowrank(const Launch& L, const DevLevel& lv, void* theta, int dir, uint32_t word,
-                          int beta, const double* gisq, double* xi, double* u);
-hipError_t launch_gather_v(const Launch& L, const DevLevel& lv, const void* theta, int beta,
-                           const double* ginv, double* v);
-hipError_t launch_coarse_rhs_lowrank(const Launch& L, const DevLevel& coarse, const double* v,
-                                     int beta);
+                          int beta, const double* gisq, const double* gam, double* t,
+                          double* v_out);
 hipError_t launch_fill_zero(const Launch& L, void* p, int64_t count);
 hipError_t launch_qoi(const Launch& L, const DevLevel& fine, const void* theta, const double* F,
                       double* partial, int nb, double* qoi, int64_t m0);
