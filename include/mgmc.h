@@ -11,7 +11,7 @@
  * correction of Alg. 3 (omega = 1) on every level when observations are
  * given, Galerkin coarse operators (eq. galerkin_triple_product), transfers
  * R = P^T (Sec. 3.1) and an exact Cholesky sample on the coarsest level
- * (Sec. 3.4).
+ * (Sec. 3.5).
  *
  * A is the finite-difference operator of Sec. 5.1.1 in divergence form,
  *   (A u)_i = s [kappa^2 u_i + h^-2 sum_k a_{i+e_k/2}(u_i - u_{i+e_k})
@@ -184,7 +184,7 @@ mgmc_status mgmc_batch_sample(mgmc_batch* batch, int64_t m0, int64_t nsamples, v
 mgmc_status mgmc_batch_destroy(mgmc_batch* batch);
 
 /* Learned prolongation.  The sampler keeps its target for any full-rank P
- * with Galerkin coarse operators (invariance theorem of Sec. 3, proved for
+ * with Galerkin coarse operators (invariance theorem of Sec. 4.2, proved for
  * general transfers; Sec. 3.1 notes P is not unique), so the finest transfer
  * may be chosen to speed up mixing.  This network maps the coefficient near
  * each coarse node J to the 9 weights of J in problem.prolong_w (2D):
@@ -197,7 +197,7 @@ mgmc_status mgmc_batch_destroy(mgmc_batch* batch);
  *   multilinear P.
  * Training minimises the two-grid loss, the fraction of an error's energy the
  * coarse correction I - P (P^T A P)^{-1} P^T A of the convergence analysis
- * (Sec. 4) leaves behind,
+ * (Sec. 4.3) leaves behind,
  *   L = mean over fields, crops, errors of 1 - g^T Ac^{-1} g / e^T A e,
  *   g = P^T A e, Ac = P^T A P,
  * on 15 x 15 coarse-node crops tiling each field (fine window of 31 x 31

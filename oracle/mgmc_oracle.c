@@ -464,7 +464,7 @@ static double* dense_tilde(const ora_problem* p, int l) {
   return a;
 }
 
-/* Textbook Cholesky At_0 = U^T U with U upper triangular (Sec. 5.1.4). */
+/* Textbook Cholesky At_0 = U^T U with U upper triangular (Sec. 5.1.3). */
 static int coarse_cholesky(ora_problem* p) {
   int64_t n0 = p->lv[0].N;
   double* a = dense_tilde(p, 0);
@@ -872,7 +872,7 @@ static void smooth(ora_problem* p, workspace* ws, int l, int dir, int sigma, uin
   }
 }
 
-/* Exact coarsest sample (Sec. 3.4, Cholesky sampler of Sec. 5.1.4):
+/* Exact coarsest sample (Sec. 3.5, Cholesky sampler of Sec. 5.1.3):
  * U^T g = f_0, then U theta_0 = g + z with z ~ N(0, I); the input is ignored. */
 static void coarse_sample(ora_problem* p, workspace* ws, uint32_t chain, uint32_t m, const double* f,
                           double* theta) {

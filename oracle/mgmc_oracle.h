@@ -10,13 +10,13 @@
  * Revisited: Theory and Bayesian Inference", arXiv 2407.12149):
  *   * the MGMC Markov update of Alg. 1 (V-cycle, gamma = 1) for the target
  *     N(At^{-1} f, At^{-1}), At = A + B Gamma^{-1} B^T (Sec. 2.3, eq.
- *     post-cov; Sec. 5.1.3 "Posterior");
+ *     post-cov; Sec. 5.1.2 "Posterior");
  *   * random Gibbs smoothing with the low-rank correction of Alg. 3 with
- *     omega = 1 (Sec. 3.3, eqs. M_lowrank_gibbs, lowrank_gibbs_two_steps,
+ *     omega = 1 (Sec. 3.4, eqs. M_lowrank_gibbs, lowrank_gibbs_two_steps,
  *     Bellstar_definition), forward before and backward after the coarse
- *     correction (Alg. 4 pairing, Sec. 5.1.4 "MGMC sampler");
- *   * an exact Cholesky sample on the coarsest level (Sec. 3.4 and the
- *     Cholesky-sampler equation of Sec. 5.1.4);
+ *     correction (Alg. 4 pairing, Sec. 5.1.3 "Samplers");
+ *   * an exact Cholesky sample on the coarsest level (Sec. 3.5 and the
+ *     Cholesky-sampler equation of Sec. 5.1.3);
  *   * Galerkin coarse operators A_{l-1} = P^T A_l P, B_{l-1} = P^T B_l
  *     (eqs. A_ell_1_B_ell_1, galerkin_triple_product) with multilinear P
  *     and R = P^T (Sec. 3.1);

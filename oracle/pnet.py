@@ -4,13 +4,13 @@ TEST INFRASTRUCTURE ONLY: used by the test-suite to check the HIP network
 kernels; the product path never imports it.
 
 The transfer operator of MGMC may be any full-rank P with Galerkin coarse
-operators (the invariance theorem of Sec. 3 is proved for general
+operators (the invariance theorem of Sec. 4.2 is proved for general
 prolongations, and Sec. 3.1 notes the intergrid operators are not unique),
 so P only affects efficiency.  Here P on the finest transfer comes from a
 small convolutional network of the local coefficient, trained to reduce the
 two-grid error: for an error e, the coarse-grid correction of the two-grid
 method (the operator T = I - P A_c^{-1} P^T A used in the convergence analysis,
-Sec. 4) removes the A-orthogonal projection of e onto range(P), so the loss
+Sec. 4.3) removes the A-orthogonal projection of e onto range(P), so the loss
 
     L(P) = mean_e ( 1 - g^T A_c^{-1} g / e^T A e ),  g = P^T A e,  A_c = P^T A P
 

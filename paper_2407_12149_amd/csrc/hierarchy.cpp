@@ -3,13 +3,13 @@
 //  * fine operator: s (kappa^2 I - div(a grad)) by finite differences with face
 //    coefficients and zero Dirichlet data (paper Sec. 5.1.1);
 //  * prolongation: column J of P carries w_J(delta) at fine node 2J + delta,
-//    multilinear by default (Sec. 3.1, Sec. 5.1.4 "MGMC sampler");
+//    multilinear by default (Sec. 3.1, Sec. 5.1.3 "Samplers");
 //  * Galerkin coarse operators A_{l-1} = P^T A_l P and B_{l-1} = P^T B_l
 //    (eq. A_ell_1_B_ell_1), assembled stencil-wise;
 //  * low-rank smoother data C = M^{-1} B, S = Gamma + B^T C, G = C S^{-1}
 //    (Alg. 3 with omega = 1, M = D + L in colour order);
 //  * the coarsest exact sampler from the Cholesky factor At_0 = U^T U
-//    (Sec. 3.4 and the Cholesky sampler of Sec. 5.1.4).
+//    (Sec. 3.5 and the Cholesky sampler of Sec. 5.1.3).
 #include "hierarchy.h"
 
 #include <algorithm>

@@ -9,7 +9,7 @@
 //    the restricted residual with R = P^T (Alg. 1, restriction step).
 //  * k_prolong: theta_i += sum_J P_iJ psi_J (Alg. 1, prolongation step).
 //  * k_coarsest: theta_0 = K f_0 + U^{-1} z, an exact draw from
-//    N(At_0^{-1} f_0, At_0^{-1}) (Sec. 3.4).
+//    N(At_0^{-1} f_0, At_0^{-1}) (Sec. 3.5).
 //  * k_lowrank_*: the low-rank correction of Alg. 3 (see k_lowrank_prep).
 //  * k_qoi_*: q = F^T theta per chain, fixed-order reductions.
 #include <algorithm>

@@ -3,7 +3,7 @@
 // training kernels (forward, backward, two-grid loss on crops, Adam).
 //
 // Any full-rank prolongation with Galerkin coarse operators leaves the
-// sampler's target invariant (the invariance theorem of Sec. 3 holds for
+// sampler's target invariant (the invariance theorem of Sec. 4.2 holds for
 // general P; Sec. 3.1 notes the transfers are not unique), so the network
 // only changes the mixing speed.  The loss is the fraction of an error's
 // energy that the two-grid coarse correction misses,

@@ -1,7 +1,7 @@
 """Chain diagnostics: integrated autocorrelation time and effective sample rate.
 
 The integrated autocorrelation time (IACT) follows the paper's normalisation
-tau = 1 + 2 sum_{t>=1} rho(t) (Sec. 4, eq. tau_int_definition), estimated with
+tau = 1 + 2 sum_{t>=1} rho(t) (Sec. 4.3, eq. tau_int_definition), estimated with
 Wolff's automatic windowing (U. Wolff, "Monte Carlo errors with less errors",
 Comput. Phys. Commun. 156 (2004), Sec. 3.3), as the paper does in Sec. 5.3.2.
 Wolff states his estimate as 1/2 + sum rho, i.e. half of the paper's value.

@@ -4,7 +4,7 @@ identities and closed forms of the paper.
 * Smoother: deterministic part equals theta + Mt^{-1}(f - At theta) with
   Mt = D + L + B Gamma^{-1} B^T (eq. M_lowrank_gibbs), and its noise has the
   covariance that leaves N(At^{-1} f, At^{-1}) invariant:
-  J J^T = At^{-1} - S At^{-1} S^T, S = I - Mt^{-1} At (Sec. 3.3 eq.
+  J J^T = At^{-1} - S At^{-1} S^T, S = I - Mt^{-1} At (Sec. 3.4 eq.
   low_rank_smoother_covariance; Appendix proposition on smoother noise).
 * One MGMC update is theta' = X theta + Y f + W with Y = (I - X) At^{-1} and
   Cov(W) = At^{-1} - X At^{-1} X^T (Lemma MG-iteration-rep).
