@@ -165,6 +165,36 @@ def batched(args):
     return out
 
 
+LEARNED_PARAMS = os.path.join(ROOT, "paper_2407_12149_amd", "pnet_learned511.npy")
+
+
+def learned_block(args):
+    """Plain vs learned-prolongation MGMC on held-out fields of the learned
+    prolongation workload (511^2, log-normal a, kappa = 1): IACT and ESS/s of
+    both on the same fields, FP64, with the committed trained parameters."""
+    import torch
+
+    from paper_2407_12149_amd import learned, workloads
+    if not os.path.exists(LEARNED_PARAMS):
+        return {"skipped": "no trained parameters"}
+    cfg = workloads.config("learned511")
+    params = learned.load_params(LEARNED_PARAMS)
+    log(f"[bench] learned: {args.learned_fields} held-out fields")
+    hold = learned.fields(cfg, cfg["train_fields"], args.learned_fields)
+    res = learned.evaluate(cfg, hold, params, nchains=4, nsamples=args.learned_samples, burn=200,
+                           log=log)
+    torch.cuda.synchronize()
+    agg = {}
+    for name in ("multilinear", "learned"):
+        agg[name] = {"iact": float(np.mean([r[name]["iact"] for r in res])),
+                     "ess_per_s": float(np.mean([r[name]["ess_per_s"] for r in res])),
+                     "ms_per_step": float(np.mean([r[name]["ms_per_step"] for r in res]))}
+    better = agg["learned"]["ess_per_s"] > agg["multilinear"]["ess_per_s"]
+    return {"workload": "learned511 held-out fields", "fields": args.learned_fields, "chains": 4,
+            "samples": args.learned_samples, **agg,
+            "selected": "learned" if better else "multilinear (fallback)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,6 +209,10 @@ def main():
     ap.add_argument("--tune-cache", default=None,
                     help="JSON cache of the per-level kernel choices (default: tune afresh)")
     ap.add_argument("--tune", type=int, default=1, help="autotune the sweep kernels before timing")
+    ap.add_argument("--learned", type=int, default=1,
+                    help="also compare learned and multilinear prolongation on held-out fields")
+    ap.add_argument("--learned-fields", type=int, default=4)
+    ap.add_argument("--learned-samples", type=int, default=2000)
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB, 20 times "
                          "(reference for the HBM byte counters)")
@@ -301,6 +335,8 @@ def main():
                      "bytes_per_launch": r64["bytes_launch"]},
     }
     result.update(extra)
+    if args.learned:
+        result["learned"] = learned_block(args)
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
         result["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds, tau)

@@ -195,13 +195,14 @@ mgmc_status mgmc_batch_destroy(mgmc_batch* batch);
  *   rho_J(delta) / sum of rho over the coarse nodes covering i (nodes outside
  *   the grid count 1), and 1 at delta = 0 (FP64).  Equal rho give the
  *   multilinear P.
- * Training minimises the two-grid loss, the fraction of an error's energy the
- * coarse correction I - P (P^T A P)^{-1} P^T A of the convergence analysis
- * (Sec. 4.3) leaves behind,
- *   L = mean over fields, crops, errors of 1 - g^T Ac^{-1} g / e^T A e,
- *   g = P^T A e, Ac = P^T A P,
- * on 15 x 15 coarse-node crops tiling each field (fine window of 31 x 31
- * nodes with zero Dirichlet data outside it; scale s = h^2).
+ * Training minimises the two-grid error reduction of the convergence
+ * analysis (Sec. 4.3: error propagator S_post T S_pre with the coarse
+ * correction T = I - P (P^T A P)^{-1} P^T A, eq. def-Tell),
+ *   L = mean over fields, crops, errors of ||S_b T S_f e||_A^2 / ||e||_A^2,
+ * with S_f / S_b one noise-free forward / backward red-black Gauss-Seidel
+ * sweep (even coordinate sum first / last), on 15 x 15 coarse-node crops
+ * tiling each field (fine window of 31 x 31 nodes with zero Dirichlet data
+ * outside it; scale s = h^2).
  * Parameters: pnet_param_count() floats, [W1 16x24x9][b1 16][W2 16x16x9]
  * [b2 16][W3 9x16x9][b3 9], W[cout][cin][t], t = (dx+1) + 3 (dy+1).
  * Calls are asynchronous on hip_stream unless they return host values. */

@@ -8,14 +8,20 @@ operators (the invariance theorem of Sec. 4.2 is proved for general
 prolongations, and Sec. 3.1 notes the intergrid operators are not unique),
 so P only affects efficiency.  Here P on the finest transfer comes from a
 small convolutional network of the local coefficient, trained to reduce the
-two-grid error: for an error e, the coarse-grid correction of the two-grid
-method (the operator T = I - P A_c^{-1} P^T A used in the convergence analysis,
-Sec. 4.3) removes the A-orthogonal projection of e onto range(P), so the loss
+two-grid error.  The two-grid error propagator of the convergence analysis
+(Sec. 4.3: X = S_post T S_pre with the coarse correction T = I - P A_c^{-1}
+P^T A, eq. def-Tell, and an exact coarse solve) gives the loss
 
-    L(P) = mean_e ( 1 - g^T A_c^{-1} g / e^T A e ),  g = P^T A e,  A_c = P^T A P
+    L(P) = mean_e || S_b T S_f e ||_A^2 / || e ||_A^2,   A_c = P^T A P,
 
-is the fraction of e's energy the coarse space misses.  Its gradient is
-dL/dP = -2 mean_e A (e - P x) x^T / (e^T A e) with x = A_c^{-1} g.
+with S_f, S_b one noise-free forward / backward red-black Gauss-Seidel sweep
+(the smoothers of the sampler's finest level).  With e_s = S_f e,
+x = A_c^{-1} P^T A e_s, r = e_s - P x, W = S_b^T A S_b and y = A_c^{-1} P^T W r,
+
+    dL/dP = -2 mean_e [ (W r - A P y) x^T + (A r) y^T ] / || e ||_A^2.
+
+(Without the smoothers, L reduces to the fraction of e's energy the coarse
+space misses; minimising that alone was found to slow the V-cycle down.)
 
 Network (all arrays on the coarse grid, nc x nc, zero padding):
   input  24 channels: log a on the 12 x-faces and 12 y-faces around the
@@ -187,9 +193,29 @@ def crop_prolongation(w, J0x, J0y, cw):
     return P
 
 
-def crop_loss_grad(faces, n, kappa2, w, errors, crops, cw=15):
+def red_black_masks(ix0, iy0, width):
+    """Sites of the window whose global coordinates have an even (red) or odd
+    (black) coordinate sum; the forward sweep updates red first."""
+    ly, lx = np.divmod(np.arange(width * width), width)
+    red = ((lx + ix0 + ly + iy0) % 2) == 0
+    return red, ~red
+
+
+def gs_sweep(A, e, order):
+    """Noise-free Gauss-Seidel sweep for A u = 0 from u = e, colour by colour
+    (sites of one colour do not couple on the 5-point stencil)."""
+    u = np.array(e, dtype=np.float64)  # a vector, or vectors as columns
+    d = np.diag(A)
+    for mask in order:
+        dm = d[mask] if u.ndim == 1 else d[mask][:, None]
+        u[mask] = u[mask] - (A[mask] @ u) / dm
+    return u
+
+
+def crop_loss_grad(faces, n, kappa2, w, errors, crops, cw=15, smooth=True):
     """Mean two-grid loss over crops x errors and its gradient w.r.t. w.
-    errors: [K][n*n] fine vectors; crops: list of (J0x, J0y) coarse origins."""
+    errors: [K][n*n] fine vectors; crops: list of (J0x, J0y) coarse origins.
+    smooth=False drops both smoothers (S_f = S_b = I)."""
     nc = (n - 1) // 2
     K = len(errors)
     dw = np.zeros_like(w)
@@ -200,14 +226,20 @@ def crop_loss_grad(faces, n, kappa2, w, errors, crops, cw=15):
         A = fine_operator_dense(faces, n, kappa2, ix0, iy0, fw)
         P = crop_prolongation(w, J0x, J0y, cw)
         Ac = P.T @ A @ P
+        red, black = red_black_masks(ix0, iy0, fw)
+        fwd, bwd = ((red, black), (black, red)) if smooth else ((), ())
+        # S_b as a matrix: column j is the sweep of unit vector j
+        Sb = gs_sweep(A, np.eye(fw * fw), bwd)
+        W = Sb.T @ A @ Sb
         for e_full in errors:
             e = np.asarray(e_full, dtype=np.float64).reshape(n, n)[iy0 - 1:iy0 - 1 + fw, ix0 - 1:ix0 - 1 + fw].reshape(-1)
-            Ae = A @ e
-            E = e @ Ae
-            g = P.T @ Ae
-            x = np.linalg.solve(Ac, g)
-            total += 1.0 - (g @ x) / E
-            G = -2.0 * np.outer(A @ (e - P @ x), x) / E  # dL_e/dP
+            E = e @ A @ e
+            es = gs_sweep(A, e, fwd)
+            x = np.linalg.solve(Ac, P.T @ (A @ es))
+            r = es - P @ x
+            total += (r @ W @ r) / E
+            y = np.linalg.solve(Ac, P.T @ (W @ r))
+            G = -2.0 * (np.outer(W @ r - A @ (P @ y), x) + np.outer(A @ r, y)) / E  # dL_e/dP
             for ly in range(cw):
                 for lx in range(cw):
                     for t in range(9):
@@ -248,14 +280,14 @@ def normalize_backward(o, nc, dw):
     return drho * sig
 
 
-def loss_and_grad(theta, faces, n, kappa2, errors, crops, cw=15):
+def loss_and_grad(theta, faces, n, kappa2, errors, crops, cw=15, smooth=True):
     """Loss of the network's prolongation and its gradient w.r.t. theta."""
     nc = (n - 1) // 2
     W1, b1, W2, b2, W3, b3 = unpack(theta)
     X = features(faces, n)
     o, (X, z1, a1, z2, a2) = forward(theta, X)
     w = normalize(o, nc)
-    loss, dw = crop_loss_grad(faces, n, kappa2, w, errors, crops, cw)
+    loss, dw = crop_loss_grad(faces, n, kappa2, w, errors, crops, cw, smooth)
     do = normalize_backward(o, nc, dw)
     da2, dW3, db3 = conv3x3_backward(a2, W3, do)
     dz2 = da2 * (z2 > 0)

@@ -5,11 +5,10 @@
 // Any full-rank prolongation with Galerkin coarse operators leaves the
 // sampler's target invariant (the invariance theorem of Sec. 4.2 holds for
 // general P; Sec. 3.1 notes the transfers are not unique), so the network
-// only changes the mixing speed.  The loss is the fraction of an error's
-// energy that the two-grid coarse correction misses,
-//   L = 1 - g^T A_c^{-1} g / e^T A e,  g = P^T A e,  A_c = P^T A P,
-// averaged over crops and errors; its gradient is
-//   dL/dP = -2 A (e - P x) x^T / (e^T A e),  x = A_c^{-1} g.
+// only changes the mixing speed.  The loss is the two-grid error reduction
+// ||S_b T S_f e||_A^2 / ||e||_A^2 (T = I - P A_c^{-1} P^T A, A_c = P^T A P,
+// S_f / S_b one noise-free red-black Gauss-Seidel sweep), averaged over crops
+// and errors; k_crop_loss derives its gradient.
 //
 // Layout: features and activations [batch][channel][nc][nc] (FP32); network
 // weights [cout][cin][9] + bias, the three layers concatenated; prolongation
@@ -238,8 +237,15 @@ __global__ __launch_bounds__(kB) void k_normalize_bwd(const float* __restrict__ 
 
 // Two-grid loss on one crop of one field: coarse window of cw x cw nodes with
 // origin J0, fine window [2 J0 - 1, 2 (J0 + cw - 1) + 1]^2, the fine operator
-// restricted to the window (zero Dirichlet data outside).  FP64 throughout;
-// the coarse matrix is factored by a banded Cholesky (bandwidth cw + 1).
+// restricted to the window (zero Dirichlet data outside).  For each error e:
+//   e_s = S_f e, x = A_c^{-1} P^T A e_s, r = e_s - P x, u = S_b r,
+//   loss += u^T A u / e^T A e,
+//   W r = S_b^T A u = A u - A M_b^{-T} A u  (S_b = I - M_b^{-1} A),
+//   y = A_c^{-1} P^T W r,
+//   dL/dP += -2 [(W r - A P y) x^T + (A r) y^T] / e^T A e,
+// with S_f / S_b one noise-free red-black Gauss-Seidel sweep (red = even
+// coordinate sum first / last).  FP64 throughout; A_c is factored by a banded
+// Cholesky (bandwidth cw + 1).
 constexpr int kCW = 15, kFW = 2 * kCW + 1, kNF = kFW * kFW, kNCr = kCW * kCW, kBW = kCW + 1;
 
 __global__ __launch_bounds__(kB) void k_crop_loss(const double* __restrict__ faces, int n,
@@ -249,9 +255,9 @@ __global__ __launch_bounds__(kB) void k_crop_loss(const double* __restrict__ fac
                                                   double* __restrict__ loss_out,
                                                   double* __restrict__ dw) {
   __shared__ double sA[5][kNF];   // fine stencil: centre, west, east, south, north
-  __shared__ double sE[kNF], sV[kNF];
+  __shared__ double sB[4][kNF];   // fine work vectors
   __shared__ double sL[kNCr][kBW + 1];  // band of the coarse matrix / its factor
-  __shared__ double sG[kNCr], sX[kNCr], sY[kNCr];
+  __shared__ double sG[kNCr], sX[kNCr], sY[kNCr], sYY[kNCr], sT[kNCr];
   __shared__ double scol[kBW + 1];
   __shared__ double sred[kB];
   const int b = blockIdx.y;
@@ -280,6 +286,46 @@ __global__ __launch_bounds__(kB) void k_crop_loss(const double* __restrict__ fac
   __syncthreads();
   // P entry of crop coarse node (lx, ly) at offset t
   auto pw = [&](int lx, int ly, int t) { return wb[(int64_t(J0y + ly - 1) * nc + (J0x + lx - 1)) * 9 + t]; };
+  // (A v)_r without the diagonal, and with it
+  auto offdiag = [&](const double* v, int r) {
+    const int lx = r % kFW, ly = r / kFW;
+    double a = 0.0;
+    if (lx > 0) a += sA[1][r] * v[r - 1];
+    if (lx < kFW - 1) a += sA[2][r] * v[r + 1];
+    if (ly > 0) a += sA[3][r] * v[r - kFW];
+    if (ly < kFW - 1) a += sA[4][r] * v[r + kFW];
+    return a;
+  };
+  auto Av = [&](const double* v, int r) { return sA[0][r] * v[r] + offdiag(v, r); };
+  auto red = [&](int r) { return ((r % kFW + r / kFW) & 1) == 0; };  // window origin has an even sum
+  // one colour of a noise-free Gauss-Seidel sweep for A u = 0, in place
+  auto gs_colour = [&](double* u, bool want_red) {
+    for (int r = threadIdx.x; r < kNF; r += blockDim.x)
+      if (red(r) == want_red) u[r] = -offdiag(u, r) / sA[0][r];
+    __syncthreads();
+  };
+  // (P^T v)_k for the crop's coarse nodes, into out
+  auto restrict_to = [&](const double* v, double* out) {
+    for (int k = threadIdx.x; k < kNCr; k += blockDim.x) {
+      const int kx = k % kCW, ky = k / kCW;
+      double g = 0.0;
+      for (int t = 0; t < 9; ++t) g += pw(kx, ky, t) * v[(2 * kx + 1 + t % 3 - 1) + kFW * (2 * ky + 1 + t / 3 - 1)];
+      out[k] = g;
+    }
+  };
+  // (P c)_r at fine window site r
+  auto prolong = [&](const double* c, int r) {
+    const int fx = r % kFW, fy = r / kFW;
+    double v = 0.0;
+    for (int my = (fy - 2) / 2; my <= fy / 2; ++my)
+      for (int mx = (fx - 2) / 2; mx <= fx / 2; ++mx) {
+        if (mx < 0 || mx >= kCW || my < 0 || my >= kCW) continue;
+        const int ddx = fx - (2 * mx + 1), ddy = fy - (2 * my + 1);
+        if (ddx < -1 || ddx > 1 || ddy < -1 || ddy > 1) continue;
+        v += pw(mx, my, (ddx + 1) + 3 * (ddy + 1)) * c[mx + kCW * my];
+      }
+    return v;
+  };
   // A_c = P^T A P, 9-point: row of coarse node k, lower band entries
   for (int k = threadIdx.x; k < kNCr; k += blockDim.x) {
     const int kx = k % kCW, ky = k / kCW;
@@ -330,87 +376,88 @@ __global__ __launch_bounds__(kB) void k_crop_loss(const double* __restrict__ fac
     }
     __syncthreads();
   }
+  // out = A_c^{-1} g: column-oriented banded substitutions, one barrier per
+  // unknown (out is the working right-hand side, tmp the forward result)
+  auto solve = [&](const double* g, double* out, double* tmp) {
+    for (int k = threadIdx.x; k < kNCr; k += blockDim.x) out[k] = g[k];
+    __syncthreads();
+    for (int k = 0; k < kNCr; ++k) {
+      const int tid = threadIdx.x;
+      const double yk = out[k] / sL[k][0];
+      if (tid == 0) tmp[k] = yk;
+      if (tid >= 1 && tid <= kBW && k + tid < kNCr) out[k + tid] -= sL[k + tid][tid] * yk;
+      __syncthreads();
+    }
+    for (int k = kNCr - 1; k >= 0; --k) {
+      const int tid = threadIdx.x;
+      const double xk = tmp[k] / sL[k][0];
+      if (tid == 0) out[k] = xk;
+      if (tid >= 1 && tid <= kBW && k - tid >= 0) tmp[k - tid] -= sL[k][tid] * xk;
+      __syncthreads();
+    }
+  };
+  double* B0 = sB[0];
+  double* B1 = sB[1];
+  double* B2 = sB[2];
+  double* B3 = sB[3];
   double crop_loss = 0.0;
   for (int q = 0; q < K; ++q) {
     const double* ef = errors + (int64_t(b) * K + q) * int64_t(n) * n;
     for (int r = threadIdx.x; r < kNF; r += blockDim.x) {
       const int x = ix0 + r % kFW, y = iy0 + r / kFW;
-      sE[r] = ef[int64_t(y - 1) * n + (x - 1)];
+      B0[r] = ef[int64_t(y - 1) * n + (x - 1)];
     }
     __syncthreads();
-    double part = 0.0;  // E = e^T A e, with A e kept in sV
-    for (int r = threadIdx.x; r < kNF; r += blockDim.x) {
-      const int lx = r % kFW, ly = r / kFW;
-      double v = sA[0][r] * sE[r];
-      if (lx > 0) v += sA[1][r] * sE[r - 1];
-      if (lx < kFW - 1) v += sA[2][r] * sE[r + 1];
-      if (ly > 0) v += sA[3][r] * sE[r - kFW];
-      if (ly < kFW - 1) v += sA[4][r] * sE[r + kFW];
-      sV[r] = v;
-      part += sE[r] * v;
-    }
+    double part = 0.0;  // E = e^T A e
+    for (int r = threadIdx.x; r < kNF; r += blockDim.x) part += B0[r] * Av(B0, r);
     const double E = block_reduce(part, sred);
-    for (int k = threadIdx.x; k < kNCr; k += blockDim.x) {  // g = P^T A e
-      const int kx = k % kCW, ky = k / kCW;
-      double g = 0.0;
-      for (int t = 0; t < 9; ++t) g += pw(kx, ky, t) * sV[(2 * kx + 1 + t % 3 - 1) + kFW * (2 * ky + 1 + t / 3 - 1)];
-      sG[k] = g;
-    }
+    gs_colour(B0, true);   // e_s = S_f e
+    gs_colour(B0, false);
+    for (int r = threadIdx.x; r < kNF; r += blockDim.x) B1[r] = Av(B0, r);
     __syncthreads();
-    // x = A_c^{-1} g: column-oriented banded substitutions, one barrier per
-    // unknown (sX is the working right-hand side, sY the forward result)
-    for (int k = threadIdx.x; k < kNCr; k += blockDim.x) sX[k] = sG[k];
+    restrict_to(B1, sG);   // g = P^T A e_s
     __syncthreads();
-    for (int k = 0; k < kNCr; ++k) {
-      const int tid = threadIdx.x;
-      const double yk = sX[k] / sL[k][0];
-      if (tid == 0) sY[k] = yk;
-      if (tid >= 1 && tid <= kBW && k + tid < kNCr) sX[k + tid] -= sL[k + tid][tid] * yk;
-      __syncthreads();
-    }
-    for (int k = kNCr - 1; k >= 0; --k) {
-      const int tid = threadIdx.x;
-      const double xk = sY[k] / sL[k][0];
-      if (tid == 0) sX[k] = xk;
-      if (tid >= 1 && tid <= kBW && k - tid >= 0) sY[k - tid] -= sL[k][tid] * xk;
-      __syncthreads();
-    }
-    double gx = 0.0;
-    for (int k = threadIdx.x; k < kNCr; k += blockDim.x) gx += sG[k] * sX[k];
-    const double gtx = block_reduce(gx, sred);
-    crop_loss += 1.0 - gtx / E;
-    // residual of the coarse correction: sE <- e - P x, then sV <- A (e - P x)
+    solve(sG, sX, sY);     // x
     for (int r = threadIdx.x; r < kNF; r += blockDim.x) {
-      const int fx = r % kFW, fy = r / kFW;
-      double px = 0.0;
-      for (int my = (fy - 2) / 2; my <= fy / 2; ++my)
-        for (int mx = (fx - 2) / 2; mx <= fx / 2; ++mx) {
-          if (mx < 0 || mx >= kCW || my < 0 || my >= kCW) continue;
-          const int ddx = fx - (2 * mx + 1), ddy = fy - (2 * my + 1);
-          if (ddx < -1 || ddx > 1 || ddy < -1 || ddy > 1) continue;
-          px += pw(mx, my, (ddx + 1) + 3 * (ddy + 1)) * sX[mx + kCW * my];
-        }
-      sV[r] = sE[r] - px;
+      const double rr = B0[r] - prolong(sX, r);  // r = e_s - P x
+      B1[r] = rr;
+      B2[r] = rr;
     }
     __syncthreads();
+    gs_colour(B2, false);  // u = S_b r
+    gs_colour(B2, true);
+    part = 0.0;
     for (int r = threadIdx.x; r < kNF; r += blockDim.x) {
-      const int lx = r % kFW, ly = r / kFW;
-      double v = sA[0][r] * sV[r];
-      if (lx > 0) v += sA[1][r] * sV[r - 1];
-      if (lx < kFW - 1) v += sA[2][r] * sV[r + 1];
-      if (ly > 0) v += sA[3][r] * sV[r - kFW];
-      if (ly < kFW - 1) v += sA[4][r] * sV[r + kFW];
-      sE[r] = v;
+      const double v = Av(B2, r);
+      B3[r] = v;           // v = A u
+      part += B2[r] * v;
     }
+    const double uAu = block_reduce(part, sred);
+    crop_loss += uAu / E;
+    // z = M_b^{-T} v: red sites first (no coupling), then black from red
+    for (int r = threadIdx.x; r < kNF; r += blockDim.x)
+      if (red(r)) B0[r] = B3[r] / sA[0][r];
     __syncthreads();
-    // dL/dw_J(t) = -2 scale [A (e - P x)]_{2J+d} x_J / E
+    for (int r = threadIdx.x; r < kNF; r += blockDim.x)
+      if (!red(r)) B0[r] = (B3[r] - offdiag(B0, r)) / sA[0][r];
+    __syncthreads();
+    for (int r = threadIdx.x; r < kNF; r += blockDim.x) B2[r] = B3[r] - Av(B0, r);  // W r
+    __syncthreads();
+    restrict_to(B2, sT);   // P^T W r
+    __syncthreads();
+    solve(sT, sYY, sY);    // y
+    for (int r = threadIdx.x; r < kNF; r += blockDim.x) B3[r] = prolong(sYY, r);  // P y
+    __syncthreads();
+    for (int r = threadIdx.x; r < kNF; r += blockDim.x) B0[r] = B2[r] - Av(B3, r);  // W r - A P y
+    __syncthreads();
+    for (int r = threadIdx.x; r < kNF; r += blockDim.x) B3[r] = Av(B1, r);  // A r
+    __syncthreads();
     for (int k = threadIdx.x; k < kNCr; k += blockDim.x) {
       const int kx = k % kCW, ky = k / kCW;
       const int64_t base = (int64_t(J0y + ky - 1) * nc + (J0x + kx - 1)) * 9;
       for (int t = 0; t < 9; ++t) {
-        const double r = sE[(2 * kx + 1 + t % 3 - 1) + kFW * (2 * ky + 1 + t / 3 - 1)];
-        const double gval = -2.0 * scale * r * sX[k] / E;
-        dwb[base + t] += gval;
+        const int i = (2 * kx + 1 + t % 3 - 1) + kFW * (2 * ky + 1 + t / 3 - 1);
+        dwb[base + t] += -2.0 * scale * (B0[i] * sX[k] + B3[i] * sYY[k]) / E;
       }
     }
     __syncthreads();

@@ -72,20 +72,61 @@ def crop_problem(seed=3, n=31):
     return faces, errors
 
 
-def test_loss_is_the_missed_energy_fraction():
-    """0 <= L <= 1, and L = 0 for errors in the range of P (exact projector)."""
+def test_coarse_correction_alone_is_the_missed_energy_fraction():
+    """Without smoothers: L = 1 - g^T A_c^{-1} g / e^T A e, in (0, 1), and 0
+    for errors in the range of P (T is the A-orthogonal projector onto the
+    complement of range(P))."""
     n, nc, cw = 31, 15, 15
     faces, errors = crop_problem()
     rng = np.random.default_rng(4)
     w = pnet.normalize(rng.normal(size=(9, nc, nc)), nc)
-    loss, _ = pnet.crop_loss_grad(faces, n, 1.0, w, errors, [(1, 1)], cw)
-    assert 0.0 < loss < 1.0
+    loss, _ = pnet.crop_loss_grad(faces, n, 1.0, w, errors, [(1, 1)], cw, smooth=False)
+    A = pnet.fine_operator_dense(faces, n, 1.0, 1, 1, 2 * cw + 1)
     P = pnet.crop_prolongation(w, 1, 1, cw)
+    want = 0.0
+    for e in errors:
+        g = P.T @ A @ e
+        want += 1.0 - g @ np.linalg.solve(P.T @ A @ P, g) / (e @ A @ e)
+    assert abs(loss - want / len(errors)) <= 1e-12 and 0.0 < loss < 1.0
     v = rng.normal(size=cw * cw)
     e = np.zeros((n, n))
     e[0:2 * cw + 1, 0:2 * cw + 1] = (P @ v).reshape(2 * cw + 1, 2 * cw + 1)
-    l0, _ = pnet.crop_loss_grad(faces, n, 1.0, w, [e.reshape(-1)], [(1, 1)], cw)
+    l0, _ = pnet.crop_loss_grad(faces, n, 1.0, w, [e.reshape(-1)], [(1, 1)], cw, smooth=False)
     assert abs(l0) < 1e-12
+
+
+def test_red_black_sweeps_are_the_gauss_seidel_splitting():
+    """The sweep equals I - M^{-1} A with M the lower triangle of A in
+    red-then-black order (textbook Gauss-Seidel), the backward sweep is the
+    A-adjoint of the forward one, and both contract in the A-norm."""
+    n, cw = 31, 15
+    faces, errors = crop_problem()
+    fw = 2 * cw + 1
+    A = pnet.fine_operator_dense(faces, n, 1.0, 1, 1, fw)
+    red, black = pnet.red_black_masks(1, 1, fw)
+    perm = np.concatenate([np.flatnonzero(red), np.flatnonzero(black)])
+    Ap = A[np.ix_(perm, perm)]
+    M = np.tril(Ap)
+    S_perm = np.eye(fw * fw) - np.linalg.solve(M, Ap)
+    inv = np.argsort(perm)
+    S_ref = S_perm[np.ix_(inv, inv)]
+    Sf = np.column_stack([pnet.gs_sweep(A, np.eye(fw * fw)[:, j], (red, black)) for j in range(fw * fw)])
+    Sb = pnet.gs_sweep(A, np.eye(fw * fw), (black, red))  # all columns at once
+    assert np.allclose(Sf, S_ref, atol=1e-13)
+    assert np.allclose(A @ Sb, Sf.T @ A, atol=1e-12)
+    e = errors[0].reshape(n, n)[:fw, :fw].reshape(-1)
+    assert (Sf @ e) @ A @ (Sf @ e) < e @ A @ e
+
+
+def test_two_grid_loss_is_a_contraction_factor():
+    """0 < ||S_b T S_f e||_A^2 / ||e||_A^2 < 1, and below the loss of the
+    coarse correction alone for the same errors (smoothing only helps)."""
+    n, nc, cw = 31, 15, 15
+    faces, errors = crop_problem()
+    w = pnet.normalize(np.full((9, nc, nc), np.log(np.expm1(1.0))), nc)
+    l2, _ = pnet.crop_loss_grad(faces, n, 1.0, w, errors, [(1, 1)], cw)
+    l1, _ = pnet.crop_loss_grad(faces, n, 1.0, w, errors, [(1, 1)], cw, smooth=False)
+    assert 0.0 < l2 < l1 < 1.0
 
 
 def test_gradient_matches_finite_differences():
