@@ -144,8 +144,17 @@ mgmc_status mgmc_set_graph(mgmc_ctx* ctx, int32_t enabled);
  *     same with 512 threads per block (taller tiles), 3 (default) chooses
  *     per level.
  *   MGMC_OPT_CHAINS_PER_BLOCK: chains processed by one block of the 2D
- *     sweep; 0 (default) chooses from the grid size and precision. */
-enum { MGMC_OPT_TILED_SWEEPS = 1, MGMC_OPT_SWEEP_VARIANT = 2, MGMC_OPT_CHAINS_PER_BLOCK = 3 };
+ *     sweep; 0 (default) chooses from the grid size and precision.
+ *   MGMC_OPT_COARSE_FUSED: 1 runs the levels with at most 63 nodes per axis
+ *     below the finest (2D, one-launch sweeps) as one launch with one
+ *     workgroup per chain and the levels resident in LDS; 0 (default)
+ *     launches them level by level (faster for few chains). */
+enum {
+  MGMC_OPT_TILED_SWEEPS = 1,
+  MGMC_OPT_SWEEP_VARIANT = 2,
+  MGMC_OPT_CHAINS_PER_BLOCK = 3,
+  MGMC_OPT_COARSE_FUSED = 4
+};
 mgmc_status mgmc_set_option(mgmc_ctx* ctx, int32_t option, int64_t value);
 
 /* Per-level form of MGMC_OPT_SWEEP_VARIANT or MGMC_OPT_CHAINS_PER_BLOCK for

@@ -5,8 +5,8 @@ kernel form (LDS tiles, or register-held stencil with 256 or 512 threads per
 block) and the number of chains processed per block, by coordinate descent
 from the finest level down: each level's candidates are timed with the
 library's own update timer while the other levels keep their current best.
-Results are cached in a JSON file keyed by problem shape, precision, chain
-count and device name."""
+It then tries the bottom levels as one launch.  Results are cached in a JSON
+file keyed by problem shape, precision, chain count and device architecture.""" 
 import json
 import os
 
@@ -19,7 +19,8 @@ CANDIDATE_CPB = (0, 1, 2, 4, 8, 16)
 def _key(sampler):
     import torch
     p = sampler.problem
-    dev = torch.cuda.get_device_name(torch.cuda.current_device())
+    props = torch.cuda.get_device_properties(torch.cuda.current_device())
+    dev = f"{getattr(props, 'gcnArchName', '')}:{props.multi_processor_count}"
     return "|".join(str(v) for v in (p["dim"], p["n"], p["levels"], p.get("precision", "fp64"),
                                      sampler.nchains, dev))
 
@@ -73,14 +74,24 @@ def autotune(sampler, cache_path=None, updates=3, verbose=False):
             if choice is not None:
                 levels[l] = choice
             apply(sampler, levels)
-        best = {"levels": levels, "ms": ms_best, "cached": False}
+        # the bottom levels as one launch, if that is faster
+        fused = 0
+        sampler.set_option(mgmc.MGMC_OPT_COARSE_FUSED, 1)
+        ms = _time(sampler, updates)
+        if verbose:
+            print(f"[autotune] {key} fused bottom: {ms:.3f} ms/update", flush=True)
+        if ms < ms_best:
+            ms_best, fused = ms, 1
+        sampler.set_option(mgmc.MGMC_OPT_COARSE_FUSED, fused)
+        best = {"levels": levels, "fused": fused, "ms": ms_best, "cached": False}
         if cache_path:
-            cache[key] = {"levels": levels, "ms": ms_best}
+            cache[key] = {"levels": levels, "fused": fused, "ms": ms_best}
             tmp = cache_path + ".tmp"
             with open(tmp, "w") as fh:
                 json.dump(cache, fh, indent=1, sort_keys=True)
             os.replace(tmp, cache_path)
     sampler.set_option(mgmc.MGMC_OPT_SWEEP_VARIANT, 3)
     sampler.set_option(mgmc.MGMC_OPT_CHAINS_PER_BLOCK, 0)
+    sampler.set_option(mgmc.MGMC_OPT_COARSE_FUSED, int(best.get("fused", 0)))
     apply(sampler, best["levels"])
     return best

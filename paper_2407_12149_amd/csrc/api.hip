@@ -73,6 +73,11 @@ struct mgmc_ctx {
   int sweep_variant = 3;  // 0: LDS-staged tiles, 1/2: segment owners with 256/512 threads, 3: per level
   int sweep_cpb = 0;      // chains per block of the 2D sweeps; 0 picks by size
   std::vector<int> lvl_variant, lvl_cpb;  // per-level overrides, -1 = context-wide setting
+  // levels 0..coarse_lm run as one workgroup per chain (0: not available)
+  bool coarse_fused = false;
+  int coarse_lm = 0;
+  size_t coarse_lds = 0;
+  mgmc::CoarseArgs cargs;
   std::vector<void*> allocs;
   // profiling: a ring of event pairs around finest-level sweep launches
   bool profiling = false;
@@ -390,10 +395,12 @@ mgmc_status enqueue_cycle(mgmc_ctx* c, const void* fL, const double* F, double* 
     }
     return MGMC_OK;
   };
+  // the bottom levels in one launch when available (2D, one-launch sweeps)
+  const int lm = (tiled && c->coarse_fused) ? c->coarse_lm : 0;
   if (top == 0) {
     MGMC_LAUNCH(mgmc::launch_coarsest(L, c->lv[0], fL, 0, state(0), c->K, c->Uinv));
   } else {
-    for (int l = top; l >= 1; --l) {
+    for (int l = top; l >= std::max(1, lm + 1); --l) {
       mgmc::DevLevel& lv = c->lv[l];
       const void* f = (l == top) ? fL : lv.f;
       const int64_t fcs = (l == top) ? 0 : lv.g.Np;
@@ -433,8 +440,16 @@ mgmc_status enqueue_cycle(mgmc_ctx* c, const void* fL, const double* F, double* 
       else
         MGMC_LAUNCH(mgmc::launch_restrict(L, lv, state(l), c->lv[l - 1], f, fcs, lr));
     }
-    MGMC_LAUNCH(mgmc::launch_coarsest(L, c->lv[0], c->lv[0].f, c->lv[0].g.Np, state(0), c->K, c->Uinv));
-    for (int l = 1; l <= top; ++l) {
+    if (lm >= 1) {
+      mgmc::CoarseArgs a = c->cargs;
+      a.f_top = c->lv[lm].f;
+      cur[lm] = 0;
+      a.theta_top = state(lm);
+      MGMC_LAUNCH(mgmc::launch_coarse_vcycle(L, a, c->coarse_lds));
+    } else {
+      MGMC_LAUNCH(mgmc::launch_coarsest(L, c->lv[0], c->lv[0].f, c->lv[0].g.Np, state(0), c->K, c->Uinv));
+    }
+    for (int l = std::max(1, lm + 1); l <= top; ++l) {
       mgmc::DevLevel& lv = c->lv[l];
       const void* f = (l == top) ? fL : lv.f;
       const int64_t fcs = (l == top) ? 0 : lv.g.Np;
@@ -577,6 +592,58 @@ mgmc_status mgmc_setup(const mgmc_problem* problem, const mgmc_obs* obs, void* h
     if ((s = c->alloc(c->t, bc)) != MGMC_OK) return cleanup(s);
     if ((s = c->alloc(c->v, bc)) != MGMC_OK) return cleanup(s);
   }
+  // the bottom of the V-cycle as one launch: the highest level below the
+  // finest with at most 63 nodes per axis, if its levels fit in LDS
+  if (problem->dim == 2 && top >= 2) {
+    int lm = 0;
+    for (int l = 1; l < top && l < mgmc::kMaxCoarseLevels; ++l)
+      if (c->lv[l].g.n <= 63) lm = l;
+    mgmc::CoarseArgs& a = c->cargs;
+    a.C.beta = c->beta;
+    a.C.nu1 = problem->nu1;
+    a.C.nu2 = problem->nu2;
+    a.C.gisq = c->gisq;
+    a.C.gam = c->gam;
+    a.C.K = c->K;
+    a.C.Uinv = c->Uinv;
+    a.C.mcur = c->mcur;
+    a.C.seed = c->L.seed;
+    a.C.chain0 = c->L.chain0;
+    for (int l = 0; l <= lm; ++l) {
+      const mgmc::DevLevel& d = c->lv[l];
+      mgmc::CoarseLevel& cl = a.L[l];
+      cl.g = d.g;
+      cl.coef = d.coef;
+      cl.invd = d.invd;
+      cl.isqd = d.isqd;
+      cl.bptr = d.bptr;
+      cl.bidx = d.bidx;
+      cl.bval = d.bval;
+      for (int dir = 0; dir < 2; ++dir) {
+        cl.nsupp[dir] = d.nsupp[dir];
+        cl.supp[dir] = d.supp[dir];
+        cl.GT[dir] = d.GT[dir];
+      }
+      cl.SinvT = d.SinvT;
+      cl.brow_of = d.brow_of;
+      cl.brptr = d.brptr;
+      cl.brcol = d.brcol;
+      cl.brval = d.brval;
+    }
+    while (lm >= 1) {
+      a.lm = lm;
+      int64_t max_bnnz = 0;
+      for (int l = 1; l <= lm; ++l) max_bnnz = std::max(max_bnnz, c->lv[l].bnnz);
+      const size_t bytes = mgmc::coarse_vcycle_lds(a, c->L.fp32 != 0, max_bnnz);
+      if (bytes <= 160 * 1024 && mgmc::coarse_vcycle_prepare(c->L.fp32 != 0, bytes) == hipSuccess) {
+        c->coarse_lds = bytes;
+        break;
+      }
+      --lm;
+    }
+    c->coarse_lm = lm;
+    (void)hipGetLastError();
+  }
   // keep only what later calls need on the host: the observation columns
   for (int l = 0; l < c->levels; ++l) {
     mgmc::HostLevel& h = c->H.lv[l];
@@ -662,6 +729,9 @@ mgmc_status mgmc_set_option(mgmc_ctx* c, int32_t option, int64_t value) {
     case MGMC_OPT_CHAINS_PER_BLOCK:
       if (value < 0 || value > 65535) return fail(MGMC_EINVAL, "chains per block out of range");
       c->sweep_cpb = int(value);
+      return MGMC_OK;
+    case MGMC_OPT_COARSE_FUSED:
+      c->coarse_fused = value != 0;
       return MGMC_OK;
     default:
       return fail(MGMC_EINVAL, "unknown option");

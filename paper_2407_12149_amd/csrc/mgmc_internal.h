@@ -62,6 +62,48 @@ struct LowRankRhs {
   int beta = 0;
 };
 
+// Arguments of the one-launch bottom of the V-cycle (kernels_coarse.hip):
+// levels 0..lm of a 2D hierarchy, all Galerkin 9-point.
+constexpr int kMaxCoarseLevels = 6;
+struct CoarseLevel {
+  Geom g;
+  const void* coef = nullptr;  // [9][Np], state precision
+  const void* invd = nullptr;
+  const void* isqd = nullptr;
+  const int64_t* bptr = nullptr;  // B_l by columns (padded sites)
+  const int32_t* bidx = nullptr;
+  const double* bval = nullptr;
+  int32_t nsupp[2] = {0, 0};
+  const int32_t* supp[2] = {nullptr, nullptr};
+  const double* GT[2] = {nullptr, nullptr};
+  const double* SinvT = nullptr;
+  const int32_t* brow_of = nullptr;  // B_l by rows (restriction into this level)
+  const int64_t* brptr = nullptr;
+  const int32_t* brcol = nullptr;
+  const double* brval = nullptr;
+};
+struct CoarseCommon {
+  int beta = 0, nu1 = 1, nu2 = 1;
+  const double* gisq = nullptr;
+  const double* gam = nullptr;
+  const double* K = nullptr;
+  const double* Uinv = nullptr;
+  const int64_t* mcur = nullptr;
+  uint32_t seed = 0, chain0 = 0;
+};
+struct CoarseArgs {
+  int lm = 0;
+  CoarseLevel L[kMaxCoarseLevels];
+  CoarseCommon C;
+  const void* f_top = nullptr;  // [nchains][Np of level lm]: right-hand side of level lm
+  void* theta_top = nullptr;    // [nchains][Np of level lm]: its state after the post-sweeps
+};
+// LDS bytes of the launch, the one-time attribute set-up (above 64 KiB) and
+// the launch itself (one workgroup of 512 threads per chain).
+size_t coarse_vcycle_lds(const CoarseArgs& a, bool fp32, int64_t max_bnnz);
+hipError_t coarse_vcycle_prepare(bool fp32, size_t lds_bytes);
+hipError_t launch_coarse_vcycle(const struct Launch& L, const CoarseArgs& a, size_t lds_bytes);
+
 struct Launch {
   hipStream_t stream = nullptr;
   int dim = 2;
@@ -73,7 +115,7 @@ struct Launch {
 };
 
 // Noise counter word 1: level << 8 | sweep << 4 | colour.
-inline uint32_t noise_word(int level, int sigma) { return (uint32_t(level) << 8) | (uint32_t(sigma) << 4); }
+__host__ __device__ inline uint32_t noise_word(int level, int sigma) { return (uint32_t(level) << 8) | (uint32_t(sigma) << 4); }
 
 // One colour pass, in place on theta.
 hipError_t launch_sweep_colour(const Launch& L, const DevLevel& lv, void* theta, const void* f,

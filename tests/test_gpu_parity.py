@@ -77,7 +77,7 @@ def rel_err(got, want):
 
 
 def check_stepwise(prob, obs, nsamples, y=None, rhs=None, F=None, label="", tiled=True,
-                   variant=None, cpb=None, levels=None):
+                   variant=None, cpb=None, levels=None, fused=None):
     from paper_2407_12149_amd import mgmc
     log(f"[parity] {label} dim={prob['dim']} n={prob['n']} levels={prob['levels']} "
         f"beta={0 if obs is None else len(obs[0]) - 1} chains={prob['nchains']} tiled={tiled}")
@@ -92,6 +92,8 @@ def check_stepwise(prob, obs, nsamples, y=None, rhs=None, F=None, label="", tile
     if levels is not None:
         from paper_2407_12149_amd import autotune
         autotune.apply(s, levels)
+    if fused is not None:
+        s.set_option(mgmc.MGMC_OPT_COARSE_FUSED, 1 if fused else 0)
     Fd = None if F is None else torch.tensor(F, device="cuda")
     rhsd = None if rhs is None else torch.tensor(rhs, device="cuda")
     worst = 0.0
@@ -140,6 +142,18 @@ def test_posterior_2d_many_tiles_many_chains(variant, cpb):
     y = workloads.observed_values(5, seed=6)
     check_stepwise(prob, obs, 2, y=y, F=workloads.subcube_qoi(n, 2),
                    label=f"posterior 255^2 variant {variant} cpb {cpb}", variant=variant, cpb=cpb)
+
+
+@pytest.mark.parametrize("fused", [True, False])
+def test_bottom_levels_fused_or_per_level(fused):
+    """The levels up to 63^2 as one launch (one workgroup per chain, LDS
+    resident) or level by level: both follow the oracle; 2 pre- and 3
+    post-sweeps exercise the sweep counts inside the fused bottom."""
+    n = 255
+    face = workloads.face_array(n, 2, workloads.fourier_log_field(2, nmodes=8, seed=5))
+    prob, obs = make_problem(2, n, 6, 30.0, face=face, beta=6, gamma=1e-3, nchains=3, nu1=2, nu2=3)
+    y = workloads.observed_values(6, seed=9)
+    check_stepwise(prob, obs, 2, y=y, label=f"posterior 255^2 fused bottom {fused}", fused=fused)
 
 
 def test_per_level_kernel_forms():
