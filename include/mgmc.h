@@ -148,12 +148,16 @@ mgmc_status mgmc_set_graph(mgmc_ctx* ctx, int32_t enabled);
  *   MGMC_OPT_COARSE_FUSED: 1 runs the levels with at most 63 nodes per axis
  *     below the finest (2D, one-launch sweeps) as one launch with one
  *     workgroup per chain and the levels resident in LDS; 0 (default)
- *     launches them level by level (faster for few chains). */
+ *     launches them level by level (faster for few chains).
+ *   MGMC_OPT_LOWRANK_MFMA: 1 (default) computes the low-rank product G t of
+ *     all chains with FP64 matrix-core instructions (16 chains per tile; used
+ *     for beta <= 512); 0 with vector FMA, 8 chains per pass over G. */
 enum {
   MGMC_OPT_TILED_SWEEPS = 1,
   MGMC_OPT_SWEEP_VARIANT = 2,
   MGMC_OPT_CHAINS_PER_BLOCK = 3,
-  MGMC_OPT_COARSE_FUSED = 4
+  MGMC_OPT_COARSE_FUSED = 4,
+  MGMC_OPT_LOWRANK_MFMA = 5
 };
 mgmc_status mgmc_set_option(mgmc_ctx* ctx, int32_t option, int64_t value);
 

@@ -560,6 +560,7 @@ mgmc_status mgmc_setup(const mgmc_problem* problem, const mgmc_obs* obs, void* h
   c->L.nchains = problem->nchains;
   c->L.seed = uint32_t(problem->seed);
   c->L.chain0 = uint32_t(problem->chain_offset);
+  c->L.lowrank_mfma = 1;
   std::string err;
   s = mgmc::build_hierarchy(*problem, obs, c->H, err);
   if (s != MGMC_OK) {
@@ -732,6 +733,9 @@ mgmc_status mgmc_set_option(mgmc_ctx* c, int32_t option, int64_t value) {
       return MGMC_OK;
     case MGMC_OPT_COARSE_FUSED:
       c->coarse_fused = value != 0;
+      return MGMC_OK;
+    case MGMC_OPT_LOWRANK_MFMA:
+      c->L.lowrank_mfma = value != 0;
       return MGMC_OK;
     default:
       return fail(MGMC_EINVAL, "unknown option");

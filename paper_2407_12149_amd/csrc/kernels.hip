@@ -613,6 +613,60 @@ hipError_t launch_coarsest(const Launch& L, const DevLevel& lv0, const void* f0,
   return hipGetLastError();
 }
 
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
+// The same product on the matrix cores: a block updates 64 support rows x 16
+// chains (four wavefronts of 16 rows), accumulating G (rows x beta) times
+// T (beta x chains, staged in LDS) with the FP64 16x16x4 MFMA.  Operand
+// layout of that instruction: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16] and receives D[l / 16 + 4 v][l % 16] in register v.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_lowrank_apply_mfma(T* __restrict__ theta, int64_t Np,
+                                                               int beta, int nsupp,
+                                                               const int32_t* __restrict__ supp,
+                                                               const double* __restrict__ GT,
+                                                               const double* __restrict__ t,
+                                                               int nchains) {
+  extern __shared__ double sT[];  // [beta][16], zero past the last chain
+  const int c0 = blockIdx.y * 16;
+  for (int e = threadIdx.x; e < beta * 16; e += blockDim.x) {
+    const int j = e >> 4, cc = e & 15;
+    sT[e] = c0 + cc < nchains ? t[int64_t(c0 + cc) * beta + j] : 0.0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = blockIdx.x * 64 + wave * 16;
+  const int ri = lane & 15, kk = lane >> 4;
+  const int r = r0 + ri;
+  mfma_d4 acc = {0.0, 0.0, 0.0, 0.0};
+  // chunks of 64 columns: the 16 loads of a chunk are issued together
+  for (int kc = 0; kc < beta; kc += 64) {
+    double av[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int k = kc + 4 * u + kk;
+      av[u] = (r < nsupp && k < beta) ? GT[int64_t(k) * nsupp + r] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int k = kc + 4 * u + kk;
+      const double b = k < beta ? sT[k * 16 + ri] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], b, acc, 0, 0, 0);
+    }
+  }
+  const int cc = lane & 15;
+  if (c0 + cc >= nchains) return;
+  T* th = theta + int64_t(c0 + cc) * Np;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int rr = r0 + (lane >> 4) + 4 * v;
+    if (rr < nsupp) {
+      const int64_t at = supp[rr];
+      th[at] = T(double(th[at]) - acc[v]);
+    }
+  }
+}
+
 hipError_t launch_lowrank(const Launch& L, const DevLevel& lv, void* theta, int dir, uint32_t word,
                           int beta, const double* gisq, const double* gam, double* t,
                           double* v_out) {
@@ -625,6 +679,15 @@ hipError_t launch_lowrank(const Launch& L, const DevLevel& lv, void* theta, int 
     k_lowrank_prep<double><<<L.nchains, kBlock, pshm, L.stream>>>((const double*)theta, lv.g.Np, beta, gisq, gam, lv.bptr, lv.bidx, lv.bval, lv.SinvT, t, v_out, word, L.mcur, L.seed, L.chain0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || lv.nsupp[dir] == 0) return e;
+  if (L.lowrank_mfma && beta <= 512) {  // LDS: beta x 16 doubles <= 64 KiB
+    const size_t mshm = size_t(beta) * 16 * sizeof(double);
+    dim3 mgrid(unsigned((lv.nsupp[dir] + 63) / 64), unsigned((L.nchains + 15) / 16));
+    if (L.fp32)
+      k_lowrank_apply_mfma<float><<<mgrid, kBlock, mshm, L.stream>>>((float*)theta, lv.g.Np, beta, lv.nsupp[dir], lv.supp[dir], lv.GT[dir], t, L.nchains);
+    else
+      k_lowrank_apply_mfma<double><<<mgrid, kBlock, mshm, L.stream>>>((double*)theta, lv.g.Np, beta, lv.nsupp[dir], lv.supp[dir], lv.GT[dir], t, L.nchains);
+    return hipGetLastError();
+  }
   // chain groups of 8 share each G entry; LDS holds t of the group and the
   // partial sums (<= 64 KiB)
   const int cb = beta <= 768 ? 8 : 1;

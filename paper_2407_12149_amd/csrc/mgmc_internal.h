@@ -112,6 +112,7 @@ struct Launch {
   uint32_t seed = 0;
   uint32_t chain0 = 0;
   const int64_t* mcur = nullptr;  // device: current sample index
+  int lowrank_mfma = 0;           // low-rank G t product on the matrix cores
 };
 
 // Noise counter word 1: level << 8 | sweep << 4 | colour.

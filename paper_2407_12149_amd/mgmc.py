@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libmgmc.so")
 MGMC_OK, MGMC_EINVAL, MGMC_ENOMEM, MGMC_EDEVICE, MGMC_ENOTSPD, MGMC_EUNSUPPORTED, MGMC_ESTATE = range(7)
 MGMC_FP64, MGMC_FP32 = 0, 1
 MGMC_OPT_TILED_SWEEPS, MGMC_OPT_SWEEP_VARIANT, MGMC_OPT_CHAINS_PER_BLOCK = 1, 2, 3
-MGMC_OPT_COARSE_FUSED = 4
+MGMC_OPT_COARSE_FUSED, MGMC_OPT_LOWRANK_MFMA = 4, 5
 
 EXPORTED = [
     "mgmc_setup", "mgmc_sample", "mgmc_posterior_sample", "mgmc_levels", "mgmc_level_sites",

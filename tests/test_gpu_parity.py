@@ -77,7 +77,7 @@ def rel_err(got, want):
 
 
 def check_stepwise(prob, obs, nsamples, y=None, rhs=None, F=None, label="", tiled=True,
-                   variant=None, cpb=None, levels=None, fused=None):
+                   variant=None, cpb=None, levels=None, fused=None, options=None):
     from paper_2407_12149_amd import mgmc
     log(f"[parity] {label} dim={prob['dim']} n={prob['n']} levels={prob['levels']} "
         f"beta={0 if obs is None else len(obs[0]) - 1} chains={prob['nchains']} tiled={tiled}")
@@ -94,6 +94,8 @@ def check_stepwise(prob, obs, nsamples, y=None, rhs=None, F=None, label="", tile
         autotune.apply(s, levels)
     if fused is not None:
         s.set_option(mgmc.MGMC_OPT_COARSE_FUSED, 1 if fused else 0)
+    for opt, val in (options or {}).items():
+        s.set_option(opt, val)
     Fd = None if F is None else torch.tensor(F, device="cuda")
     rhsd = None if rhs is None else torch.tensor(rhs, device="cuda")
     worst = 0.0
@@ -154,6 +156,19 @@ def test_bottom_levels_fused_or_per_level(fused):
     prob, obs = make_problem(2, n, 6, 30.0, face=face, beta=6, gamma=1e-3, nchains=3, nu1=2, nu2=3)
     y = workloads.observed_values(6, seed=9)
     check_stepwise(prob, obs, 2, y=y, label=f"posterior 255^2 fused bottom {fused}", fused=fused)
+
+
+@pytest.mark.parametrize("mfma", [True, False])
+def test_low_rank_product_on_matrix_cores_or_vector(mfma):
+    """The low-rank G t product with the FP64 MFMA (ragged 16-chain tile with
+    19 chains, beta not a multiple of 4) or with vector FMA."""
+    n = 127
+    face = workloads.face_array(n, 2, workloads.fourier_log_field(2, nmodes=8, seed=6))
+    prob, obs = make_problem(2, n, 4, 30.0, face=face, beta=7, gamma=1e-3, nchains=19)
+    y = workloads.observed_values(7, seed=10)
+    from paper_2407_12149_amd import mgmc
+    check_stepwise(prob, obs, 2, y=y, label=f"posterior 127^2 x 19 mfma {mfma}",
+                   options={mgmc.MGMC_OPT_LOWRANK_MFMA: int(mfma)})
 
 
 def test_per_level_kernel_forms():
