@@ -94,13 +94,13 @@ __global__ __launch_bounds__(kBlock) void k_sweep_parity3d(const T* __restrict__
                                                            const T* __restrict__ f, int64_t fcs,
                                                            Geom g, int parity, uint32_t word,
                                                            const int64_t* __restrict__ mcur,
-                                                           uint32_t seed, uint32_t chain0) {
+                                                           uint32_t seed, uint32_t chain0, int cpb,
+                                                           int nchains) {
   const int n = g.n;
   const int qmax = ((n + 1) / 2 + 1) / 2;  // pairs per row for the odd x-sublattice
   const int64_t total = int64_t(qmax) * n * n;
   const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (gid >= total) return;
-  const int c = blockIdx.y;
   const int q = int(gid % qmax);
   const int64_t row = gid / qmax;
   const int i2 = 1 + int(row % n), i3 = 1 + int(row / n);
@@ -112,15 +112,43 @@ __global__ __launch_bounds__(kBlock) void k_sweep_parity3d(const T* __restrict__
   const int m2 = (i2 & 1) ? (n + 1) / 2 : (n - 1) / 2;
   const int s2 = (i2 - 1) >> 1, s3 = (i3 - 1) >> 1;
   const uint32_t pair = uint32_t(q) + uint32_t(qx) * (uint32_t(s2) + uint32_t(m2) * uint32_t(s3));
-  const Block4 blk = philox10(pair, word | uint32_t(colour), uint32_t(*mcur), 0u, seed, chain0 + c);
-  T z0, z1;
-  Gauss<T>::pair(blk, z0, z1);
-  T* th = theta + int64_t(c) * g.Np;
-  const T* fc = f ? f + int64_t(c) * fcs : nullptr;
+  const uint32_t m = uint32_t(*mcur);
   const int i1 = 4 * q + (xpar ? 1 : 2);
+  const bool two = 2 * q + 1 < m1;
+  // the stencil of the pair's two sites, kept in registers for every chain
+  // of the block's group: axis neighbours in ascending index order
   const int64_t ia = pidx(g, i1, i2, i3);
-  gs_update<T, 3, true>(coef, invd, isqd, th, fc, g, ia, z0);
-  if (2 * q + 1 < m1) gs_update<T, 3, true>(coef, invd, isqd, th, fc, g, ia + 2, z1);
+  const int64_t off[6] = {-int64_t(g.px) * g.py, -int64_t(g.px), -1, 1, int64_t(g.px),
+                          int64_t(g.px) * g.py};
+  const int tix[6] = {4, 10, 12, 14, 16, 22};
+  T cf[2][6], ivd[2], isd[2], rhs[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int64_t i = ia + 2 * k;
+    const bool in = k == 0 || two;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) cf[k][e] = in ? coef[int64_t(tix[e]) * g.Np + i] : T(0);
+    ivd[k] = in ? invd[i] : T(0);
+    isd[k] = in ? isqd[i] : T(0);
+    rhs[k] = (in && f && fcs == 0) ? f[i] : T(0);
+  }
+  const int cb = int(blockIdx.y) * cpb;
+  const int ce = min(nchains, cb + cpb);
+  for (int c = cb; c < ce; ++c) {
+    const Block4 blk = philox10(pair, word | uint32_t(colour), m, 0u, seed, chain0 + c);
+    T z[2];
+    Gauss<T>::pair(blk, z[0], z[1]);
+    T* th = theta + int64_t(c) * g.Np;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      if (k == 1 && !two) break;
+      const int64_t i = ia + 2 * k;
+      T s = (f && fcs != 0) ? f[int64_t(c) * fcs + i] : rhs[k];
+#pragma unroll
+      for (int e = 0; e < 6; ++e) s -= cf[k][e] * th[i + off[e]];
+      th[i] = s * ivd[k] + z[k] * isd[k];
+    }
+  }
 }
 
 template <typename T, int DIM, bool CROSS, bool USERP>
@@ -540,11 +568,15 @@ hipError_t launch_sweep_parity3d(const Launch& L, const DevLevel& lv, void* thet
   if (L.mcur == nullptr || L.dim != 3 || !lv.cross) return hipErrorInvalidValue;
   const int n = lv.g.n;
   const int64_t total = int64_t(((n + 1) / 2 + 1) / 2) * n * n;
-  dim3 grid(blocks_for(total), L.nchains);
+  // chain groups share the stencil registers; keep at least ~2048 blocks
+  const int64_t blocks = blocks_for(total);
+  int cpb = 1;
+  while (cpb < 8 && cpb < L.nchains && blocks * ((L.nchains + 2 * cpb - 1) / (2 * cpb)) >= 2048) cpb *= 2;
+  dim3 grid(unsigned(blocks), unsigned((L.nchains + cpb - 1) / cpb));
   if (L.fp32)
-    k_sweep_parity3d<float><<<grid, kBlock, 0, L.stream>>>((const float*)lv.coef, (const float*)lv.invd, (const float*)lv.isqd, (float*)theta, (const float*)f, fcs, lv.g, parity, word, L.mcur, L.seed, L.chain0);
+    k_sweep_parity3d<float><<<grid, kBlock, 0, L.stream>>>((const float*)lv.coef, (const float*)lv.invd, (const float*)lv.isqd, (float*)theta, (const float*)f, fcs, lv.g, parity, word, L.mcur, L.seed, L.chain0, cpb, L.nchains);
   else
-    k_sweep_parity3d<double><<<grid, kBlock, 0, L.stream>>>((const double*)lv.coef, (const double*)lv.invd, (const double*)lv.isqd, (double*)theta, (const double*)f, fcs, lv.g, parity, word, L.mcur, L.seed, L.chain0);
+    k_sweep_parity3d<double><<<grid, kBlock, 0, L.stream>>>((const double*)lv.coef, (const double*)lv.invd, (const double*)lv.isqd, (double*)theta, (const double*)f, fcs, lv.g, parity, word, L.mcur, L.seed, L.chain0, cpb, L.nchains);
   return hipGetLastError();
 }
 
