@@ -55,7 +55,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const T* __restrict__ coef,
                                                   const T* __restrict__ f, int64_t fcs, Geom g,
                                                   int colour, uint32_t word,
                                                   const int64_t* __restrict__ mcur, uint32_t seed,
-                                                  uint32_t chain0) {
+                                                  uint32_t chain0, int cpb, int nchains) {
+  constexpr int S = DIM == 2 ? 9 : 27;
+  constexpr int NB = CROSS ? 2 * DIM : S - 1;  // neighbours per site
   const int p1 = colour & 1, p2 = (colour >> 1) & 1, p3 = (colour >> 2) & 1;
   const int n = g.n;
   const int m1 = p1 ? (n + 1) / 2 : (n - 1) / 2;
@@ -65,7 +67,6 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const T* __restrict__ coef,
   const int64_t total = int64_t(qx) * m2 * m3;
   const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (gid >= total) return;
-  const int c = blockIdx.y;
   const int q = int(gid % qx);
   const int64_t rest = gid / qx;
   const int s2 = int(rest % m2), s3 = int(rest / m2);
@@ -73,14 +74,50 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const T* __restrict__ coef,
   const int i2 = 2 * s2 + (p2 ? 1 : 2);
   const int i3 = DIM == 3 ? 2 * s3 + (p3 ? 1 : 2) : 0;
   const uint32_t pair = uint32_t(q) + uint32_t(qx) * (uint32_t(s2) + uint32_t(m2) * uint32_t(s3));
-  const Block4 blk = philox10(pair, word | uint32_t(colour), uint32_t(*mcur), 0u, seed, chain0 + c);
-  T z0, z1;
-  Gauss<T>::pair(blk, z0, z1);
-  T* th = theta + int64_t(c) * g.Np;
-  const T* fc = f ? f + int64_t(c) * fcs : nullptr;
+  const uint32_t m = uint32_t(*mcur);
+  const bool two = 2 * q + 1 < m1;
   const int64_t ia = pidx(g, i1, i2, i3);
-  gs_update<T, DIM, CROSS>(coef, invd, isqd, th, fc, g, ia, z0);
-  if (2 * q + 1 < m1) gs_update<T, DIM, CROSS>(coef, invd, isqd, th, fc, g, ia + 2, z1);
+  // the stencil of the pair's two sites, in registers for the chain group
+  // (neighbours in ascending index order)
+  T cf[2][NB], ivd[2], isd[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const bool in = k == 0 || two;
+    int b = 0;
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+      const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = DIM == 3 ? t / 9 - 1 : 0;
+      const int nz = (dx != 0) + (dy != 0) + (dz != 0);
+      if (nz == 0 || (CROSS && nz != 1)) continue;
+      cf[k][b++] = in ? coef[int64_t(t) * g.Np + ia + 2 * k] : T(0);
+    }
+    ivd[k] = in ? invd[ia + 2 * k] : T(0);
+    isd[k] = in ? isqd[ia + 2 * k] : T(0);
+  }
+  const int cb = int(blockIdx.y) * cpb;
+  const int ce = min(nchains, cb + cpb);
+  for (int c = cb; c < ce; ++c) {
+    const Block4 blk = philox10(pair, word | uint32_t(colour), m, 0u, seed, chain0 + c);
+    T z[2];
+    Gauss<T>::pair(blk, z[0], z[1]);
+    T* th = theta + int64_t(c) * g.Np;
+    const T* fc = f ? f + int64_t(c) * fcs : nullptr;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      if (k == 1 && !two) break;
+      const int64_t i = ia + 2 * k;
+      T s = fc ? fc[i] : T(0);
+      int b = 0;
+#pragma unroll
+      for (int t = 0; t < S; ++t) {
+        const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = DIM == 3 ? t / 9 - 1 : 0;
+        const int nz = (dx != 0) + (dy != 0) + (dz != 0);
+        if (nz == 0 || (CROSS && nz != 1)) continue;
+        s -= cf[k][b++] * th[i + poff(g, dx, dy, dz)];
+      }
+      th[i] = s * ivd[k] + z[k] * isd[k];
+    }
+  }
 }
 
 // Parity pass of a 3D 7-point sweep: all colours with parity sum `parity`
@@ -193,24 +230,39 @@ template <typename T, int DIM, bool CROSS>
 __global__ __launch_bounds__(kBlock) void k_residual(const T* __restrict__ coef,
                                                      const T* __restrict__ theta,
                                                      const T* __restrict__ f, int64_t fcs, Geom g,
-                                                     int64_t N, T* __restrict__ r) {
+                                                     int64_t N, T* __restrict__ r, int cpb,
+                                                     int nchains) {
   constexpr int S = DIM == 2 ? 9 : 27;
+  constexpr int NS = CROSS ? 2 * DIM + 1 : S;  // stencil entries used
   const int64_t lin = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (lin >= N) return;
-  const int c = blockIdx.y;
   int i1, i2, i3;
   unflatten<DIM>(lin, g.n, i1, i2, i3);
   const int64_t ii = pidx(g, i1, i2, i3);
-  const T* th = theta + int64_t(c) * g.Np;
-  T acc = f ? f[int64_t(c) * fcs + ii] : T(0);
+  T cf[NS];
+  int b = 0;
 #pragma unroll
   for (int t = 0; t < S; ++t) {
     const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = DIM == 3 ? t / 9 - 1 : 0;
     const int nz = (dx != 0) + (dy != 0) + (dz != 0);
     if (CROSS && nz > 1) continue;
-    acc -= coef[int64_t(t) * g.Np + ii] * th[ii + poff(g, dx, dy, dz)];
+    cf[b++] = coef[int64_t(t) * g.Np + ii];
   }
-  r[int64_t(c) * g.Np + ii] = acc;
+  const int cb = int(blockIdx.y) * cpb;
+  const int ce = min(nchains, cb + cpb);
+  for (int c = cb; c < ce; ++c) {
+    const T* th = theta + int64_t(c) * g.Np;
+    T acc = f ? f[int64_t(c) * fcs + ii] : T(0);
+    b = 0;
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+      const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = DIM == 3 ? t / 9 - 1 : 0;
+      const int nz = (dx != 0) + (dy != 0) + (dz != 0);
+      if (CROSS && nz > 1) continue;
+      acc -= cf[b++] * th[ii + poff(g, dx, dy, dz)];
+    }
+    r[int64_t(c) * g.Np + ii] = acc;
+  }
 }
 
 template <typename T, int DIM, bool USERP>
@@ -249,33 +301,46 @@ __global__ __launch_bounds__(kBlock) void k_prolong(T* __restrict__ theta, Geom 
   const int c = blockIdx.y;
   int i[3];
   unflatten<DIM>(gid, nf, i[0], i[1], i[2]);
-  // coarse nodes covering i along each axis, ascending: (J, delta) with i = 2J + delta
-  int J[3][2], D[3][2], cnt[3];
+  // per axis the covering coarse nodes J0 = i >> 1 (offset i & 1) and, for
+  // odd i, J1 = (i + 1) >> 1 (offset -1); for even i J1 = J0 with weight 0,
+  // so every site sums the same terms in the same order
+  int J[3][2], D[3][2];
+  T h[3][2];
+#pragma unroll
   for (int k = 0; k < 3; ++k) {
-    if (k >= DIM) {
-      J[k][0] = 0; D[k][0] = 0; cnt[k] = 1;
-    } else if ((i[k] & 1) == 0) {
-      J[k][0] = i[k] / 2; D[k][0] = 0; cnt[k] = 1;
-    } else {
-      J[k][0] = (i[k] - 1) / 2; D[k][0] = 1;
-      J[k][1] = (i[k] + 1) / 2; D[k][1] = -1;
-      cnt[k] = 2;
-    }
+    const int ik = k < DIM ? i[k] : 0, odd = ik & 1;
+    J[k][0] = ik >> 1;
+    J[k][1] = (ik + 1) >> 1;
+    D[k][0] = odd;
+    D[k][1] = -1;
+    h[k][0] = odd ? T(0.5) : T(1);
+    h[k][1] = odd ? T(0.5) : T(0);
   }
   const T* ps = psi + int64_t(c) * gc.Np;
   T s = T(0);
-  for (int a3 = 0; a3 < cnt[2]; ++a3)
-    for (int a2 = 0; a2 < cnt[1]; ++a2)
-      for (int a1 = 0; a1 < cnt[0]; ++a1) {
+  bool first = true;
+#pragma unroll
+  for (int a3 = 0; a3 < (DIM == 3 ? 2 : 1); ++a3)
+#pragma unroll
+    for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+      for (int a1 = 0; a1 < 2; ++a1) {
         const int64_t jc = pidx(gc, J[0][a1], J[1][a2], J[2][a3]);
         T w;
         if (USERP) {
+          const bool on = (a1 == 0 || (i[0] & 1)) && (a2 == 0 || (i[1] & 1)) &&
+                          (DIM == 2 || a3 == 0 || (i[2] & 1));
           const int t = (D[0][a1] + 1) + 3 * (D[1][a2] + 1) + (DIM == 3 ? 9 * (D[2][a3] + 1) : 0);
-          w = T(wP[int64_t(t) * gc.Np + jc]);
+          w = on ? T(wP[int64_t(t) * gc.Np + jc]) : T(0);
         } else {
-          w = T(multilinear(D[0][a1], D[1][a2], D[2][a3]));
+          w = h[0][a1] * h[1][a2] * (DIM == 3 ? h[2][a3] : T(1));
         }
-        s += w * ps[jc];
+        if (first) {
+          s = w * ps[jc];
+          first = false;
+        } else {
+          s += w * ps[jc];
+        }
       }
   theta[int64_t(c) * gf.Np + pidx(gf, i[0], i[1], i[2])] += s;
 }
@@ -457,9 +522,11 @@ __global__ __launch_bounds__(kBlock) void k_qoi_partial(const T* __restrict__ th
   const int64_t lo = int64_t(b) * chunk, hi = lo + chunk < N ? lo + chunk : N;
   const T* th = theta + int64_t(c) * g.Np;
   double acc = 0.0;
+  const int n = g.n;
   for (int64_t lin = lo + threadIdx.x; lin < hi; lin += blockDim.x) {
-    int i1, i2, i3;
-    unflatten<DIM>(lin, g.n, i1, i2, i3);
+    const int l32 = int(lin);  // N < 2^31 (checked at set-up)
+    const int i1 = 1 + l32 % n, r = l32 / n;
+    const int i2 = 1 + (DIM == 3 ? r % n : r), i3 = DIM == 3 ? 1 + r / n : 0;
     acc += F[lin] * double(th[pidx(g, i1, i2, i3)]);
   }
   const double s = block_sum(acc, sh);
@@ -515,6 +582,14 @@ __global__ void k_advance_m(int64_t* mcur) { *mcur += 1; }
 
 inline unsigned blocks_for(int64_t count) { return unsigned((count + kBlock - 1) / kBlock); }
 
+// Chains per thread for kernels that keep a site's stencil in registers
+// across chains: up to 8, halved while fewer than ~2048 blocks would remain.
+inline int chain_group(int64_t blocks, int nchains) {
+  int cpb = 1;
+  while (cpb < 8 && cpb < nchains && blocks * ((nchains + 2 * cpb - 1) / (2 * cpb)) >= 2048) cpb *= 2;
+  return cpb;
+}
+
 }  // namespace
 
 #define MGMC_DISPATCH(L, ...)  \
@@ -549,16 +624,17 @@ hipError_t launch_sweep_colour(const Launch& L, const DevLevel& lv, void* theta,
   const int m3 = L.dim == 3 ? ext((colour >> 2) & 1) : 1;
   const int64_t total = int64_t((m1 + 1) / 2) * m2 * m3;
   if (total == 0) return hipSuccess;
-  dim3 grid(blocks_for(total), L.nchains);
+  const int cpb = chain_group(blocks_for(total), L.nchains);
+  dim3 grid(blocks_for(total), unsigned((L.nchains + cpb - 1) / cpb));
   MGMC_DISPATCH(L, {
     if (lv.cross)
       k_sweep<T, DIM, true><<<grid, kBlock, 0, L.stream>>>(
           (const T*)lv.coef, (const T*)lv.invd, (const T*)lv.isqd, (T*)theta, (const T*)f, fcs,
-          lv.g, colour, word, L.mcur, L.seed, L.chain0);
+          lv.g, colour, word, L.mcur, L.seed, L.chain0, cpb, L.nchains);
     else
       k_sweep<T, DIM, false><<<grid, kBlock, 0, L.stream>>>(
           (const T*)lv.coef, (const T*)lv.invd, (const T*)lv.isqd, (T*)theta, (const T*)f, fcs,
-          lv.g, colour, word, L.mcur, L.seed, L.chain0);
+          lv.g, colour, word, L.mcur, L.seed, L.chain0, cpb, L.nchains);
   });
   return hipGetLastError();
 }
@@ -568,10 +644,8 @@ hipError_t launch_sweep_parity3d(const Launch& L, const DevLevel& lv, void* thet
   if (L.mcur == nullptr || L.dim != 3 || !lv.cross) return hipErrorInvalidValue;
   const int n = lv.g.n;
   const int64_t total = int64_t(((n + 1) / 2 + 1) / 2) * n * n;
-  // chain groups share the stencil registers; keep at least ~2048 blocks
   const int64_t blocks = blocks_for(total);
-  int cpb = 1;
-  while (cpb < 8 && cpb < L.nchains && blocks * ((L.nchains + 2 * cpb - 1) / (2 * cpb)) >= 2048) cpb *= 2;
+  const int cpb = chain_group(blocks, L.nchains);
   dim3 grid(unsigned(blocks), unsigned((L.nchains + cpb - 1) / cpb));
   if (L.fp32)
     k_sweep_parity3d<float><<<grid, kBlock, 0, L.stream>>>((const float*)lv.coef, (const float*)lv.invd, (const float*)lv.isqd, (float*)theta, (const float*)f, fcs, lv.g, parity, word, L.mcur, L.seed, L.chain0, cpb, L.nchains);
@@ -607,12 +681,13 @@ hipError_t launch_restrict_2stage(const Launch& L, const DevLevel& fine, const v
                                   void* scratch, const DevLevel& coarse, const void* f,
                                   int64_t fcs, const LowRankRhs& lr) {
   if (scratch == nullptr || scratch == theta) return hipErrorInvalidValue;
-  dim3 g1(blocks_for(fine.N), L.nchains), g2(blocks_for(coarse.N), L.nchains);
+  const int rcpb = chain_group(blocks_for(fine.N), L.nchains);
+  dim3 g1(blocks_for(fine.N), unsigned((L.nchains + rcpb - 1) / rcpb)), g2(blocks_for(coarse.N), L.nchains);
   MGMC_DISPATCH(L, {
     if (fine.cross)
-      k_residual<T, DIM, true><<<g1, kBlock, 0, L.stream>>>((const T*)fine.coef, (const T*)theta, (const T*)f, fcs, fine.g, fine.N, (T*)scratch);
+      k_residual<T, DIM, true><<<g1, kBlock, 0, L.stream>>>((const T*)fine.coef, (const T*)theta, (const T*)f, fcs, fine.g, fine.N, (T*)scratch, rcpb, L.nchains);
     else
-      k_residual<T, DIM, false><<<g1, kBlock, 0, L.stream>>>((const T*)fine.coef, (const T*)theta, (const T*)f, fcs, fine.g, fine.N, (T*)scratch);
+      k_residual<T, DIM, false><<<g1, kBlock, 0, L.stream>>>((const T*)fine.coef, (const T*)theta, (const T*)f, fcs, fine.g, fine.N, (T*)scratch, rcpb, L.nchains);
     if (fine.wP)
       k_restrict_residual<T, DIM, true><<<g2, kBlock, 0, L.stream>>>((const T*)scratch, fine.g, (T*)coarse.f, coarse.g, fine.wP, lr);
     else
