@@ -3,7 +3,8 @@
 //
 // One Philox block gives two normals: u1 from words (x0, x1), u2 from (x2, x3)
 // as the top 53 bits plus half an ulp scaled by 2^-53; z = sqrt(-2 ln u1)
-// (cos, sin)(2 pi u2).  The single-precision variant takes the top 24 bits of
+// (cos, sin)(2 pi u2).  The double-precision logarithm and sine/cosine are
+// short series written out here (few live registers inside the sweeps).  The single-precision variant takes the top 24 bits of
 // x0 and x2, so its normals track the double ones to ~1e-7 from the same
 // counters.
 #pragma once
@@ -39,6 +40,68 @@ __device__ __forceinline__ Block4 philox10(uint32_t c0, uint32_t c1, uint32_t c2
 template <typename T>
 struct Gauss;
 
+// Natural logarithm of u in (0, 1), a normal double.  u = f 2^k with f in
+// [1/sqrt 2, sqrt 2); with s = (f - 1) / (f + 1), log f = 2 atanh s =
+// 2 s sum_j s^(2j) / (2j + 1), and |s| <= 0.1716 makes ten terms accurate to
+// 3e-17 relative.  Horner form keeps few values live.
+__device__ __forceinline__ double log_unit(double u) {
+  int k;
+  double f = frexp(u, &k);  // f in [0.5, 1)
+  if (f < 0.70710678118654752440) {
+    f *= 2.0;
+    k -= 1;
+  }
+  const double s = (f - 1.0) / (f + 1.0);
+  const double s2 = s * s;
+  double p = 1.0 / 19.0;
+  p = fma(p, s2, 1.0 / 17.0);
+  p = fma(p, s2, 1.0 / 15.0);
+  p = fma(p, s2, 1.0 / 13.0);
+  p = fma(p, s2, 1.0 / 11.0);
+  p = fma(p, s2, 1.0 / 9.0);
+  p = fma(p, s2, 1.0 / 7.0);
+  p = fma(p, s2, 1.0 / 5.0);
+  p = fma(p, s2, 1.0 / 3.0);
+  p = fma(p, s2, 1.0);
+  return fma(double(k), 0.69314718055994530942, 2.0 * s * p);
+}
+
+// sin and cos of 2 pi u for u in [0, 1).  t = 4u is exact; with q the
+// nearest integer and r = t - q (exact, |r| <= 1/2) the angle is
+// q pi/2 + x, x = r pi/2 in [-pi/4, pi/4], where Taylor series of nine
+// (sin) and ten (cos) terms are accurate to 1e-19 and 3e-21.
+__device__ __forceinline__ void sincos_2pi(double u, double& sn, double& cs) {
+  const double t = 4.0 * u;
+  const double qd = rint(t);
+  const double x = (t - qd) * 1.57079632679489661923;
+  const double x2 = x * x;
+  double ps = 1.0 / 355687428096000.0;  // 1/17!
+  ps = fma(ps, x2, -1.0 / 1307674368000.0);
+  ps = fma(ps, x2, 1.0 / 6227020800.0);
+  ps = fma(ps, x2, -1.0 / 39916800.0);
+  ps = fma(ps, x2, 1.0 / 362880.0);
+  ps = fma(ps, x2, -1.0 / 5040.0);
+  ps = fma(ps, x2, 1.0 / 120.0);
+  ps = fma(ps, x2, -1.0 / 6.0);
+  ps = fma(ps, x2, 1.0);
+  const double sx = x * ps;
+  double pc = 1.0 / 6402373705728000.0;  // 1/18!
+  pc = fma(pc, x2, -1.0 / 20922789888000.0);
+  pc = fma(pc, x2, 1.0 / 87178291200.0);
+  pc = fma(pc, x2, -1.0 / 479001600.0);
+  pc = fma(pc, x2, 1.0 / 3628800.0);
+  pc = fma(pc, x2, -1.0 / 40320.0);
+  pc = fma(pc, x2, 1.0 / 720.0);
+  pc = fma(pc, x2, -1.0 / 24.0);
+  pc = fma(pc, x2, 0.5);
+  const double cx = fma(-x2, pc, 1.0);
+  const int q = int(qd) & 3;
+  const double a = (q & 1) ? cx : sx;  // sin of the angle up to sign
+  const double b = (q & 1) ? sx : cx;  // cos of the angle up to sign
+  sn = (q & 2) ? -a : a;
+  cs = (q == 1 || q == 2) ? -b : b;
+}
+
 template <>
 struct Gauss<double> {
   static __device__ __forceinline__ void pair(const Block4& x, double& z0, double& z1) {
@@ -46,10 +109,9 @@ struct Gauss<double> {
     const uint64_t w2 = (uint64_t(x.x2) << 32) | uint64_t(x.x3);
     const double u1 = (double(w1 >> 11) + 0.5) * 0x1p-53;
     const double u2 = (double(w2 >> 11) + 0.5) * 0x1p-53;
-    const double rad = sqrt(-2.0 * log(u1));
-    // (sin, cos)(2 pi u2) via the pi-scaled forms: exact argument reduction
+    const double rad = sqrt(-2.0 * log_unit(u1));
     double sn, cs;
-    sincospi(2.0 * u2, &sn, &cs);
+    sincos_2pi(u2, sn, cs);
     z0 = rad * cs;
     z1 = rad * sn;
   }

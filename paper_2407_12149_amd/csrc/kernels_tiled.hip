@@ -271,11 +271,11 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
       const int dx = t % 3 - 1, dy = t / 3 - 1;
       if (dx == 0 && dy == 0) continue;
       if (CROSS && dx != 0 && dy != 0) continue;
-      cf[k][b++] = in ? coef[int64_t(t) * g.Np + gi] : T(0);
+      cf[k][b++] = coef[int64_t(t) * g.Np + gi];
     }
-    ivd[k] = in ? invd[gi] : T(0);
-    isd[k] = in ? isqd[gi] : T(0);
-    rhs[k] = (in && f && fcs == 0) ? f[gi] : T(0);
+    ivd[k] = invd[gi];
+    isd[k] = isqd[gi];
+    rhs[k] = (f && fcs == 0) ? f[gi] : T(0);
   }
   // The passes this thread updates sites in ("slots"): on red-black levels
   // both passes (each row holds both colours), on four-colour levels the
@@ -309,11 +309,16 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
   for (int c = cb; c < ce; ++c) {
     const T* thi = theta_in + int64_t(c) * g.Np;
     T* tho = theta_out + int64_t(c) * g.Np;
+    // Every load below is issued unconditionally: positions outside the grid
+    // (or all of them when the input is zero) read offset 0 of the field,
+    // which is padding and stays zero.  Without per-load branches the loaded
+    // registers need no copies, so nothing waits for the loads before the
+    // noise below is drawn.
     if (f && fcs != 0) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int x = 4 * q + 1 + k;
-        rhs[k] = (row_in && x >= 1 && x <= n) ? f[int64_t(c) * fcs + pidx(g, x, y, 0)] : T(0);
+        rhs[k] = f[int64_t(c) * fcs + ((row_in && x >= 1 && x <= n) ? pidx(g, x, y, 0) : 0)];
       }
     }
     // issue the tile loads (and those of the coarse patch) into registers ...
@@ -323,18 +328,16 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
     for (int k = 0; k < KP; ++k) {
       const int e = int(threadIdx.x) + k * NT;
       const int Jx = jx0 + e % CRX, Jy = jy0 + e / CRX;
-      pv[k] = (e < CRX * CRY && Jx >= 1 && Jx <= gc.n && Jy >= 1 && Jy <= gc.n)
-                  ? psi[int64_t(c) * gc.Np + pidx(gc, Jx, Jy, 0)]
-                  : T(0);
+      const bool ok = e < CRX * CRY && Jx >= 1 && Jx <= gc.n && Jy >= 1 && Jy <= gc.n;
+      pv[k] = psi[int64_t(c) * gc.Np + (ok ? pidx(gc, Jx, Jy, 0) : 0)];
     }
     T fv[KF];
 #pragma unroll
     for (int k = 0; k < KF; ++k) {
       const int idx = int(threadIdx.x) + k * NT;
       const int xx = ox + idx % RX, yy = oy + idx / RX;
-      fv[k] = (!zero_in && idx < RX * RY && xx >= 1 && xx <= n && yy >= 1 && yy <= n)
-                  ? thi[pidx(g, xx, yy, 0)]
-                  : T(0);
+      const bool ok = !zero_in && idx < RX * RY && xx >= 1 && xx <= n && yy >= 1 && yy <= n;
+      fv[k] = thi[ok ? pidx(g, xx, yy, 0) : 0];
     }
     // ... and draw this chain's noise while they are in flight (except where
     // registers are scarce: FP64 four-colour levels with the prolongation)
