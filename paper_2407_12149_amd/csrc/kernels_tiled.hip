@@ -13,9 +13,9 @@
 // theta += P psi (Alg. 1, prolongation step) is applied while the tile is
 // loaded, fusing it into the post-smoother.
 //
-// k_restrict2d_tiled computes f_{l-1} = P^T (f_l - A_l theta) (Alg. 1,
+// k_restrict2d_reg computes f_{l-1} = P^T (f_l - A_l theta) (Alg. 1,
 // restriction step) for a tile of coarse nodes from fine residuals staged
-// in LDS.
+// in LDS, with the residual's operator held in registers across chains.
 #include "device_common.h"
 #include "device_rng.h"
 #include "mgmc_internal.h"
@@ -424,68 +424,133 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
   }
 }
 
-template <typename T, bool CROSS, bool USERP, int CTX, int CTY>
-__global__ __launch_bounds__(kBlock) void k_restrict2d_tiled(
+
+// The same restriction with the residual's operator held in registers across
+// the chains of a block.  A block covers CTX x CTY coarse nodes; thread t
+// owns the fine residual nodes t, t + NT, ... of the (2 CTX + 1) x (2 CTY + 1)
+// residual region and keeps their stencil (and a chain-shared right-hand
+// side) in registers.  Per chain: the theta region (one more ring) goes from
+// registers to LDS, each thread forms its residuals into LDS, and thread J
+// sums the nine weighted residuals of coarse node J.  The next chain's theta
+// (and right-hand side) loads are issued before the current chain's
+// residuals, and every load is branch-free: positions outside the grid read
+// offset 0 of the field, which is padding and stays zero.
+template <typename T, bool CROSS, bool USERP, int CTY, int NT>
+__global__ __launch_bounds__(NT) void k_restrict2d_reg(
     const T* __restrict__ coef, const T* __restrict__ theta, const T* __restrict__ f, int64_t fcs,
     Geom gf, T* __restrict__ fcoarse, Geom gc, const double* __restrict__ wP, int tiles_x, int cpb,
     int nchains, LowRankRhs lr) {
-  constexpr int RXr = 2 * CTX + 1, RYr = 2 * CTY + 1;  // fine residual region
-  constexpr int RXt = RXr + 2, RYt = RYr + 2;          // theta region (one more ring)
+  constexpr int CTX = 32;
+  constexpr int RXr = 2 * CTX + 1, RYr = 2 * CTY + 1;  // residual region
+  constexpr int RXt = RXr + 2, RYt = RYr + 2;          // theta region
+  constexpr int KR = (RXr * RYr + NT - 1) / NT;        // residual nodes per thread
+  constexpr int KT = (RXt * RYt + NT - 1) / NT;        // theta entries per thread
+  constexpr int NS = CROSS ? 5 : 9;
+  static_assert(CTX * CTY <= NT, "one coarse node per thread");
   __shared__ T sth[RYt * RXt];
   __shared__ T sr[RYr * RXr];
   const int nf = gf.n, nc = gc.n;
   const int cx0 = int(blockIdx.x % tiles_x) * CTX + 1;
   const int cy0 = int(blockIdx.x / tiles_x) * CTY + 1;
-  const int rx0 = 2 * cx0 - 1, ry0 = 2 * cy0 - 1;  // residual region origin
-  const int tx0 = rx0 - 1, ty0 = ry0 - 1;          // theta region origin
+  const int rx0 = 2 * cx0 - 1, ry0 = 2 * cy0 - 1;
+  const int tx0 = rx0 - 1, ty0 = ry0 - 1;
+  const int tid = int(threadIdx.x);
+  // stencil of the owned residual nodes (zero outside the grid)
+  int64_t gr[KR];
+  T cr[KR][NS], fr[KR];
+#pragma unroll
+  for (int k = 0; k < KR; ++k) {
+    const int idx = tid + k * NT;
+    const int x = rx0 + idx % RXr, y = ry0 + idx / RXr;
+    const bool in = idx < RXr * RYr && x >= 1 && x <= nf && y >= 1 && y <= nf;
+    gr[k] = in ? pidx(gf, x, y, 0) : 0;
+    int b = 0;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int dx = t % 3 - 1, dy = t / 3 - 1;
+      if (CROSS && dx != 0 && dy != 0) continue;
+      cr[k][b++] = coef[int64_t(t) * gf.Np + gr[k]];
+    }
+    fr[k] = (f && fcs == 0) ? f[gr[k]] : T(0);
+  }
+  // this thread's coarse node
+  const int J1 = cx0 + tid % CTX, J2 = cy0 + tid / CTX;
+  const bool own = tid < CTX * CTY && J1 <= nc && J2 <= nc;
+  const int64_t iJ = own ? pidx(gc, J1, J2, 0) : 0;
+  const int rowJ = (own && lr.row_of) ? lr.row_of[iJ] : -1;
+  T wJ[9];
+#pragma unroll
+  for (int t1 = 0; t1 < 9; ++t1) {
+    const int ex = t1 % 3 - 1, ey = t1 / 3 - 1;
+    wJ[t1] = USERP ? T(wP[int64_t(t1) * gc.Np + iJ]) : T(multilinear(ex, ey, 0));
+  }
   const int cb = int(blockIdx.y) * cpb;
   const int ce = min(nchains, cb + cpb);
-  for (int c = cb; c < ce; ++c) {
+  T tv[KT], fn[KR];
+  auto issue = [&](int c) {
     const T* th = theta + int64_t(c) * gf.Np;
-    const T* fc = f ? f + int64_t(c) * fcs : nullptr;
-    for (int idx = threadIdx.x; idx < RXt * RYt; idx += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+      const int idx = tid + k * NT;
       const int x = tx0 + idx % RXt, y = ty0 + idx / RXt;
-      sth[idx] = (x >= 1 && x <= nf && y >= 1 && y <= nf) ? th[pidx(gf, x, y, 0)] : T(0);
+      const bool ok = idx < RXt * RYt && x >= 1 && x <= nf && y >= 1 && y <= nf;
+      tv[k] = th[ok ? pidx(gf, x, y, 0) : 0];
+    }
+    if (f && fcs != 0) {
+#pragma unroll
+      for (int k = 0; k < KR; ++k) fn[k] = f[int64_t(c) * fcs + gr[k]];
+    }
+  };
+  if (cb < ce) issue(cb);
+  for (int c = cb; c < ce; ++c) {
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+      const int idx = tid + k * NT;
+      if (idx < RXt * RYt) sth[idx] = tv[k];
+    }
+    if (f && fcs != 0) {
+#pragma unroll
+      for (int k = 0; k < KR; ++k) fr[k] = fn[k];
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < RXr * RYr; idx += blockDim.x) {
-      const int lx = idx % RXr, ly = idx / RXr;
-      const int x = rx0 + lx, y = ry0 + ly;
-      T r = T(0);
-      if (x >= 1 && x <= nf && y >= 1 && y <= nf) {
-        const int64_t gi = pidx(gf, x, y, 0);
-        const int li = (ly + 1) * RXt + (lx + 1);
-        r = fc ? fc[gi] : T(0);
+    if (c + 1 < ce) issue(c + 1);
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-          const int dx = t % 3 - 1, dy = t / 3 - 1;
-          if (CROSS && dx != 0 && dy != 0) continue;
-          r -= coef[int64_t(t) * gf.Np + gi] * sth[li + dy * RXt + dx];
-        }
+    for (int k = 0; k < KR; ++k) {
+      const int idx = tid + k * NT;
+      if (idx >= RXr * RYr) continue;
+      const int lx = idx % RXr, ly = idx / RXr;
+      const int li = (ly + 1) * RXt + (lx + 1);
+      T r = fr[k];
+      int b = 0;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const int dx = t % 3 - 1, dy = t / 3 - 1;
+        if (CROSS && dx != 0 && dy != 0) continue;
+        r -= cr[k][b++] * sth[li + dy * RXt + dx];
       }
       sr[idx] = r;
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < CTX * CTY; idx += blockDim.x) {
-      const int J1 = cx0 + idx % CTX, J2 = cy0 + idx / CTX;
-      if (J1 > nc || J2 > nc) continue;
-      const int64_t iJ = pidx(gc, J1, J2, 0);
-      const int lx = 2 * (J1 - cx0) + 1, ly = 2 * (J2 - cy0) + 1;  // residual-region coords of 2J
+    if (own) {
+      const int lx = 2 * (J1 - cx0) + 1, ly = 2 * (J2 - cy0) + 1;
       T acc = T(0);
 #pragma unroll
       for (int t1 = 0; t1 < 9; ++t1) {
         const int ex = t1 % 3 - 1, ey = t1 / 3 - 1;
-        const T w = USERP ? T(wP[int64_t(t1) * gc.Np + iJ]) : T(multilinear(ex, ey, 0));
-        acc += w * sr[(ly + ey) * RXr + (lx + ex)];
+        acc += wJ[t1] * sr[(ly + ey) * RXr + (lx + ex)];
       }
-      fcoarse[int64_t(c) * gc.Np + iJ] = T(double(acc) - lowrank_rhs(lr, c, iJ));
+      double lrv = 0.0;
+      if (rowJ >= 0) {
+        for (int64_t e = lr.ptr[rowJ]; e < lr.ptr[rowJ + 1]; ++e)
+          lrv += lr.val[e] * lr.v[int64_t(c) * lr.beta + lr.col[e]];
+      }
+      fcoarse[int64_t(c) * gc.Np + iJ] = T(double(acc) - lrv);
     }
     __syncthreads();
   }
 }
 
 constexpr int kTX = 64, kTY = 32;  // sweep tile
-constexpr int kCTX = 32, kCTY = 16;  // restriction tile (coarse nodes)
 
 int chains_per_block(int nchains, int64_t tiles) {
   // enough blocks to cover the 256 compute units several times over, while
@@ -583,23 +648,30 @@ hipError_t launch_restrict_tiled(const Launch& L, const DevLevel& fine, const vo
                                  const DevLevel& coarse, const void* f, int64_t fcs,
                                  const LowRankRhs& lr) {
   if (L.dim != 2) return hipErrorInvalidValue;
+  constexpr int CTX = 32, CTY = 8;
   const int nc = coarse.g.n;
-  const int tiles_x = (nc + kCTX - 1) / kCTX, tiles_y = (nc + kCTY - 1) / kCTY;
+  const int tiles_x = (nc + CTX - 1) / CTX, tiles_y = (nc + CTY - 1) / CTY;
   const int64_t tiles = int64_t(tiles_x) * tiles_y;
-  const int cpb = chains_per_block(L.nchains, tiles);
+  // as many chains per block as keep >= 1024 blocks (the operator is read
+  // from memory once per chain group)
+  int cpb = L.nchains;
+  while (cpb > 1 && tiles * ((L.nchains + cpb - 1) / cpb) < 1024) cpb = (cpb + 1) / 2;
   dim3 grid(unsigned(tiles), unsigned((L.nchains + cpb - 1) / cpb));
   const bool userp = fine.wP != nullptr;
-#define MGMC_RESTRICT_T(T, CR, UP)                                                              \
-  k_restrict2d_tiled<T, CR, UP, kCTX, kCTY><<<grid, kBlock, 0, L.stream>>>(                     \
+#define MGMC_RESTRICT_T(T, CR, UP, NT)                                                          \
+  k_restrict2d_reg<T, CR, UP, CTY, NT><<<grid, NT, 0, L.stream>>>(                               \
       (const T*)fine.coef, (const T*)theta, (const T*)f, fcs, fine.g, (T*)coarse.f, coarse.g,       \
       fine.wP, tiles_x, cpb, L.nchains, lr)
-  if (L.fp32) {
-    if (fine.cross) { if (userp) MGMC_RESTRICT_T(float, true, true); else MGMC_RESTRICT_T(float, true, false); }
-    else { if (userp) MGMC_RESTRICT_T(float, false, true); else MGMC_RESTRICT_T(float, false, false); }
-  } else {
-    if (fine.cross) { if (userp) MGMC_RESTRICT_T(double, true, true); else MGMC_RESTRICT_T(double, true, false); }
-    else { if (userp) MGMC_RESTRICT_T(double, false, true); else MGMC_RESTRICT_T(double, false, false); }
-  }
+#define MGMC_RESTRICT_P(T)                                                                      \
+  do {                                                                                          \
+    if (fine.cross) {                                                                           \
+      if (userp) MGMC_RESTRICT_T(T, true, true, 256); else MGMC_RESTRICT_T(T, true, false, 256);  \
+    } else {                                                                                    \
+      if (userp) MGMC_RESTRICT_T(T, false, true, 512); else MGMC_RESTRICT_T(T, false, false, 512); \
+    }                                                                                           \
+  } while (0)
+  if (L.fp32) MGMC_RESTRICT_P(float); else MGMC_RESTRICT_P(double);
+#undef MGMC_RESTRICT_P
 #undef MGMC_RESTRICT_T
   return hipGetLastError();
 }
