@@ -134,7 +134,9 @@ int64_t mgmc_level_sites(const mgmc_ctx* ctx, int32_t level);
  * kernels one by one (0, default).  Results are identical either way. */
 mgmc_status mgmc_set_graph(mgmc_ctx* ctx, int32_t enabled);
 
-/* Kernel variants; results are identical for every setting.
+/* Kernel variants; results agree to rounding for every setting (the one-launch
+ * 2D sweeps of double-precision contexts draw their normals with a
+ * table-driven Box-Muller transform, the other kernels with series).
  *   MGMC_OPT_TILED_SWEEPS: 1 (default) runs each 2D sweep as one launch with
  *     the prolongation fused into the post-smoother; 0 launches one kernel
  *     per colour (the form used for 3D).
@@ -151,7 +153,11 @@ mgmc_status mgmc_set_graph(mgmc_ctx* ctx, int32_t enabled);
  *     launches them level by level (faster for few chains).
  *   MGMC_OPT_LOWRANK_MFMA: 1 (default) computes the low-rank product G t of
  *     all chains with FP64 matrix-core instructions (16 chains per tile; used
- *     for beta <= 512); 0 with vector FMA, 8 chains per pass over G. */
+ *     for beta <= 512), and on 2D levels with one-launch sweeps the sweep
+ *     kernel also copies its values at the observation sites, so that
+ *     B^T theta, the noise xi and the product take one launch; 2 uses the
+ *     matrix cores with a separate launch for B^T theta and xi; 0 uses
+ *     vector FMA, 8 chains per pass over G.  Results agree to rounding. */
 enum {
   MGMC_OPT_TILED_SWEEPS = 1,
   MGMC_OPT_SWEEP_VARIANT = 2,
@@ -163,7 +169,7 @@ mgmc_status mgmc_set_option(mgmc_ctx* ctx, int32_t option, int64_t value);
 
 /* Per-level form of MGMC_OPT_SWEEP_VARIANT or MGMC_OPT_CHAINS_PER_BLOCK for
  * level `level` (0 = coarsest); -1 returns the level to the context-wide
- * setting.  Results are identical for every setting.  Errors: EINVAL. */
+ * setting.  Results agree to rounding for every setting.  Errors: EINVAL. */
 mgmc_status mgmc_set_level_option(mgmc_ctx* ctx, int32_t level, int32_t option, int64_t value);
 
 /* Kernel timing of the finest-level smoother sweeps (the hot loop of the

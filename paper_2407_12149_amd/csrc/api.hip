@@ -248,6 +248,28 @@ mgmc_status upload_level(mgmc_ctx* c, int l) {
     if ((s = c->upload(d.bptr, bptr)) != MGMC_OK) return s;
     if ((s = c->upload(d.bidx, bidx)) != MGMC_OK) return s;
     if ((s = c->upload(d.bval, bval)) != MGMC_OK) return s;
+    if (c->prob.dim == 2 && l >= 1 && d.bnnz > 0) {
+      // entries of B grouped by the 64 x TY tile holding their site, for
+      // each tile height of the 2D sweep forms
+      const int tiles_x = (h.n + 63) / 64;
+      for (int gi = 0; gi < 3; ++gi) {
+        const int ty = mgmc::kSnapTY[d.cross ? 1 : 0][gi];
+        const int tiles = tiles_x * ((h.n + ty - 1) / ty);
+        std::vector<int32_t> tptr(size_t(tiles) + 1, 0), tent(size_t(d.bnnz));
+        std::vector<int32_t> tile_of(size_t(d.bnnz));
+        for (int64_t e = 0; e < d.bnnz; ++e) {
+          const int x = bidx[e] % d.g.px - 3, y = bidx[e] / d.g.px;
+          tile_of[e] = ((y - 1) / ty) * tiles_x + (x - 1) / 64;
+          ++tptr[size_t(tile_of[e]) + 1];
+        }
+        for (int t = 0; t < tiles; ++t) tptr[t + 1] += tptr[t];
+        std::vector<int32_t> fill(tptr.begin(), tptr.end() - 1);
+        for (int64_t e = 0; e < d.bnnz; ++e) tent[size_t(fill[tile_of[e]]++)] = int32_t(e);
+        if ((s = c->upload(d.bt_ptr[gi], tptr)) != MGMC_OK) return s;
+        if ((s = c->upload(d.bt_ent[gi], tent)) != MGMC_OK) return s;
+      }
+      if ((s = c->alloc(d.bsnap, size_t(nch) * d.bnnz)) != MGMC_OK) return s;
+    }
     std::vector<int32_t> brow, brcol;
     std::vector<int64_t> brptr(1, 0);
     std::vector<double> brval;
@@ -334,11 +356,12 @@ mgmc_status timed(mgmc_ctx* c, bool finest, F&& body) {
 // One 2D sweep from theta_in into theta_out in the selected kernel form.
 hipError_t sweep2d(mgmc_ctx* c, int l, const void* in, void* out, int zero_in, const void* f,
                    int64_t fcs, uint32_t word, int backward, const mgmc::DevLevel* coarse,
-                   const void* psi) {
+                   const void* psi, bool snap) {
   const mgmc::DevLevel& lv = c->lv[l];
   const int sv = c->lvl_variant[l] >= 0 ? c->lvl_variant[l] : c->sweep_variant;
   if (sv == 0)
-    return mgmc::launch_sweep_tiled(c->L, lv, in, out, zero_in, f, fcs, word, backward, coarse, psi);
+    return mgmc::launch_sweep_tiled(c->L, lv, in, out, zero_in, f, fcs, word, backward, coarse, psi,
+                                    snap);
   // 512-thread blocks (taller tiles, less redundant halo work) or 256-thread
   // blocks; the automatic choice takes 512 threads for FP64 four-colour
   // sweeps with the fused prolongation (register pressure), else 256
@@ -358,7 +381,13 @@ hipError_t sweep2d(mgmc_ctx* c, int l, const void* in, void* out, int zero_in, c
     cpb = (nch + groups - 1) / groups;  // balance the groups
   }
   return mgmc::launch_sweep_seg(c->L, lv, in, out, zero_in, f, fcs, word, backward, coarse, psi,
-                                variant, cpb);
+                                variant, cpb, snap);
+}
+
+// Whether the low-rank step of level l runs as one launch fed by the sweep's
+// snapshot of B's sites (2D one-launch sweeps, matrix-core product).
+bool fused_lowrank(const mgmc_ctx* c, const mgmc::DevLevel& lv) {
+  return c->beta > 0 && c->beta <= 512 && c->L.lowrank_mfma == 1 && lv.bsnap != nullptr;
 }
 
 // One MGMC update of every chain (Alg. 1), enqueued on the context stream.
@@ -408,20 +437,26 @@ mgmc_status enqueue_cycle(mgmc_ctx* c, const void* fL, const double* F, double* 
       if (zero_start && !tiled) MGMC_LAUNCH(mgmc::launch_fill_zero(L, state(l), int64_t(nch) * lv.g.Np));
       for (int j = 0; j < nu1; ++j) {
         const uint32_t word = mgmc::noise_word(l, j);
+        double* v_out = j == nu1 - 1 ? c->v : nullptr;
         if (tiled) {
           const int zin = (zero_start && j == 0) ? 1 : 0;
+          const bool snap = fused_lowrank(c, lv);
           mgmc_status st = timed(c, l == top, [&] {
-            return sweep2d(c, l, state(l), lv.buf[1 - cur[l]], zin, f, fcs, word, 0, nullptr, nullptr);
+            return sweep2d(c, l, state(l), lv.buf[1 - cur[l]], zin, f, fcs, word, 0, nullptr, nullptr,
+                           snap);
           });
           if (st != MGMC_OK) return st;
           cur[l] ^= 1;
+          if (snap) {
+            MGMC_LAUNCH(mgmc::launch_lowrank_fused(L, lv, state(l), 0, word, beta, c->gisq, c->gam, v_out));
+            continue;
+          }
         } else {
           mgmc_status st = in_place_sweep(l, f, fcs, word, false);
           if (st != MGMC_OK) return st;
         }
         if (beta)
-          MGMC_LAUNCH(mgmc::launch_lowrank(L, lv, state(l), 0, word, beta, c->gisq, c->gam, c->t,
-                                           j == nu1 - 1 ? c->v : nullptr));
+          MGMC_LAUNCH(mgmc::launch_lowrank(L, lv, state(l), 0, word, beta, c->gisq, c->gam, c->t, v_out));
       }
       mgmc::LowRankRhs lr;
       if (beta) {
@@ -459,11 +494,17 @@ mgmc_status enqueue_cycle(mgmc_ctx* c, const void* fL, const double* F, double* 
         const bool last_in_place = l == top && ((nu1 + nu2) & 1) && j == nu2 - 1;
         if (tiled && !last_in_place) {
           const mgmc::DevLevel* coarse = (j == 0) ? &c->lv[l - 1] : nullptr;
+          const bool snap = fused_lowrank(c, lv);
           mgmc_status st = timed(c, l == top, [&] {
-            return sweep2d(c, l, state(l), lv.buf[1 - cur[l]], 0, f, fcs, word, 1, coarse, coarse ? psi : nullptr);
+            return sweep2d(c, l, state(l), lv.buf[1 - cur[l]], 0, f, fcs, word, 1, coarse,
+                           coarse ? psi : nullptr, snap);
           });
           if (st != MGMC_OK) return st;
           cur[l] ^= 1;
+          if (snap) {
+            MGMC_LAUNCH(mgmc::launch_lowrank_fused(L, lv, state(l), 1, word, beta, c->gisq, c->gam, nullptr));
+            continue;
+          }
         } else {
           if (j == 0) MGMC_LAUNCH(mgmc::launch_prolong(L, lv, state(l), c->lv[l - 1], psi));
           mgmc_status st = in_place_sweep(l, f, fcs, word, true);
@@ -475,8 +516,11 @@ mgmc_status enqueue_cycle(mgmc_ctx* c, const void* fL, const double* F, double* 
     }
   }
   if (cur[top] != 0) return fail(MGMC_EDEVICE, "internal: finest state left in the second buffer");
-  if (qoi) MGMC_LAUNCH(mgmc::launch_qoi(L, c->lv[top], state(top), F, c->qpart, c->qnb, qoi, m0));
-  MGMC_LAUNCH(mgmc::launch_advance_m(c->stream, c->mcur));
+  // the QoI reduction also advances the sample index
+  if (qoi)
+    MGMC_LAUNCH(mgmc::launch_qoi(L, c->lv[top], state(top), F, c->qpart, c->qnb, qoi, m0));
+  else
+    MGMC_LAUNCH(mgmc::launch_advance_m(c->stream, c->mcur));
   return MGMC_OK;
 }
 
@@ -579,6 +623,13 @@ mgmc_status mgmc_setup(const mgmc_problem* problem, const mgmc_obs* obs, void* h
   if ((s = c->upload(c->Uinv, c->H.Uinv)) != MGMC_OK) return cleanup(s);
   if ((s = c->alloc(c->mcur, 1)) != MGMC_OK) return cleanup(s);
   c->L.mcur = c->mcur;
+  {
+    std::vector<double> tab(mgmc::kBmTable);
+    mgmc::fill_bm_table(tab.data());
+    double* d = nullptr;
+    if ((s = c->upload(d, tab)) != MGMC_OK) return cleanup(s);
+    c->L.bm_table = d;
+  }
   const int top = c->levels - 1;
   c->qnb = int(std::min<int64_t>(256, (c->lv[top].N + 4095) / 4096));
   if (c->qnb < 1) c->qnb = 1;
@@ -735,7 +786,8 @@ mgmc_status mgmc_set_option(mgmc_ctx* c, int32_t option, int64_t value) {
       c->coarse_fused = value != 0;
       return MGMC_OK;
     case MGMC_OPT_LOWRANK_MFMA:
-      c->L.lowrank_mfma = value != 0;
+      if (value < 0 || value > 2) return fail(MGMC_EINVAL, "MGMC_OPT_LOWRANK_MFMA takes 0, 1 or 2");
+      c->L.lowrank_mfma = int(value);
       return MGMC_OK;
     default:
       return fail(MGMC_EINVAL, "unknown option");

@@ -102,6 +102,64 @@ __device__ __forceinline__ void sincos_2pi(double u, double& sn, double& cs) {
   cs = (q == 1 || q == 2) ? -b : b;
 }
 
+// Table-driven double-precision Box-Muller for kernels that stage the table
+// in LDS.  Layout (kBmTable = 770 doubles, filled by fill_bm_table on the
+// host):
+//   [0, 128)     log c_i,  c_i = 45/64 + (i + 1/2) 45/8192, the midpoints of
+//                128 equal cells covering [45/64, 45/32)
+//   [128, 256)   1 / c_i
+//   [256, 513)   sin(2 pi k / 256), k = 0..256
+//   [513, 770)   cos(2 pi k / 256)
+// log u: u = f 2^e with f in [45/64, 45/32); with c the midpoint of f's cell,
+// r = (f - c) / c has |r| <= 1/256 and log u = e ln 2 + log c + log1p r,
+// log1p r to seven terms (error < r^8 / 8).  sin/cos(2 pi u): t = 256 u
+// (exact), k = nearest integer, x = (t - k) 2 pi / 256 with |x| <= pi/256,
+// short series for sin x and cos x, and the angle-sum formulas with the
+// tabulated sin and cos of 2 pi k / 256.
+__device__ __forceinline__ void gauss_pair_tab(const Block4& x, const double* __restrict__ tab,
+                                               double& z0, double& z1) {
+  const uint64_t w1 = (uint64_t(x.x0) << 32) | uint64_t(x.x1);
+  const uint64_t w2 = (uint64_t(x.x2) << 32) | uint64_t(x.x3);
+  const double u1 = (double(w1 >> 11) + 0.5) * 0x1p-53;
+  const double u2 = (double(w2 >> 11) + 0.5) * 0x1p-53;
+  int e;
+  double f = frexp(u1, &e);  // [0.5, 1)
+  if (f < 0.703125) {
+    f *= 2.0;
+    e -= 1;
+  }
+  const int i = min(int((f - 0.703125) * (8192.0 / 45.0)), 127);
+  const double c = 0.703125 + (double(i) + 0.5) * (45.0 / 8192.0);
+  const double r = (f - c) * tab[128 + i];
+  double p = 1.0 / 7.0;
+  p = fma(p, r, -1.0 / 6.0);
+  p = fma(p, r, 1.0 / 5.0);
+  p = fma(p, r, -0.25);
+  p = fma(p, r, 1.0 / 3.0);
+  p = fma(p, r, -0.5);
+  p = fma(p, r, 1.0);
+  const double lg = fma(double(e), 0.69314718055994530942, fma(r, p, tab[i]));
+  const double rad = sqrt(-2.0 * lg);
+  const double t = u2 * 256.0;
+  const double kd = rint(t);
+  const int k = int(kd);
+  const double xa = (t - kd) * 0.024543692606170259675;  // 2 pi / 256
+  const double x2 = xa * xa;
+  double ps = -1.0 / 5040.0;
+  ps = fma(ps, x2, 1.0 / 120.0);
+  ps = fma(ps, x2, -1.0 / 6.0);
+  const double sx = fma(xa * x2, ps, xa);
+  double pc = -1.0 / 720.0;
+  pc = fma(pc, x2, 1.0 / 24.0);
+  pc = fma(pc, x2, -0.5);
+  const double cx = fma(x2, pc, 1.0);
+  const double sk = tab[256 + k], ck = tab[513 + k];
+  const double sn = fma(sk, cx, ck * sx);
+  const double cs = fma(ck, cx, -(sk * sx));
+  z0 = rad * cs;
+  z1 = rad * sn;
+}
+
 template <>
 struct Gauss<double> {
   static __device__ __forceinline__ void pair(const Block4& x, double& z0, double& z1) {

@@ -415,8 +415,22 @@ __global__ __launch_bounds__(kBlock) void k_lowrank_prep(
   const int c = blockIdx.x;
   const T* th = theta + int64_t(c) * Np;
   const int64_t nnz = bptr[beta];
-  // every entry of B^T theta at once: one load chain per entry, no serial walk
-  for (int64_t e = threadIdx.x; e < nnz; e += blockDim.x) prod[e] = bval[e] * double(th[bidx[e]]);
+  // every entry of B^T theta at once: one load chain per entry, no serial
+  // walk; four entries per thread are in flight together (branch-free loads
+  // of a clamped entry, masked stores)
+  for (int64_t e0 = 0; e0 < nnz; e0 += 4 * int64_t(blockDim.x)) {
+    double pv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t e = min(e0 + threadIdx.x + int64_t(u) * blockDim.x, nnz - 1);
+      pv[u] = bval[e] * double(th[bidx[e]]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t e = e0 + threadIdx.x + int64_t(u) * blockDim.x;
+      if (e < nnz) prod[e] = pv[u];
+    }
+  }
   const uint32_t m = uint32_t(*mcur);
   for (int p = threadIdx.x; 2 * p < beta; p += blockDim.x) {
     const Block4 blk = philox10(uint32_t(p), word, m, 1u, seed, chain0 + c);
@@ -533,16 +547,23 @@ __global__ __launch_bounds__(kBlock) void k_qoi_partial(const T* __restrict__ th
   if (threadIdx.x == 0) partial[int64_t(c) * nb + b] = s;
 }
 
+// One block: wavefront w sums the partials of chains w, w + 4, ... in a
+// fixed order, then the sample index advances (the last kernel of an
+// update, so no other kernel of this update reads it afterwards).
 __global__ __launch_bounds__(kBlock) void k_qoi_final(const double* __restrict__ partial, int nb,
                                                       double* __restrict__ qoi,
-                                                      const int64_t* __restrict__ mcur, int64_t m0,
+                                                      int64_t* __restrict__ mcur, int64_t m0,
                                                       int nchains) {
-  __shared__ double sh[kBlock];
-  const int c = blockIdx.x;
-  double acc = 0.0;
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += partial[int64_t(c) * nb + b];
-  const double s = block_sum(acc, sh);
-  if (threadIdx.x == 0) qoi[(*mcur - m0) * nchains + c] = s;
+  const int64_t m = *mcur;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int c = wave; c < nchains; c += kBlock / 64) {
+    double acc = 0.0;
+    for (int b = lane; b < nb; b += 64) acc += partial[int64_t(c) * nb + b];
+    const double s = wave_sum(acc);
+    if (lane == 0) qoi[(m - m0) * nchains + c] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *mcur = m + 1;
 }
 
 template <typename T, int DIM>
@@ -722,37 +743,74 @@ hipError_t launch_coarsest(const Launch& L, const DevLevel& lv0, const void* f0,
 
 typedef double mfma_d4 __attribute__((ext_vector_type(4)));
 
-// The same product on the matrix cores: a block updates 64 support rows x 16
-// chains (four wavefronts of 16 rows), accumulating G (rows x beta) times
-// T (beta x chains, staged in LDS) with the FP64 16x16x4 MFMA.  Operand
-// layout of that instruction: lane l supplies A[l % 16][l / 16] and
-// B[l / 16][l % 16] and receives D[l / 16 + 4 v][l % 16] in register v.
+// theta_r -= sum_j G_rj t_j for the block's 64 support rows and chains
+// c0 .. c0 + 15 on the matrix cores, with t staged in LDS as sT[beta][16]
+// (zero past the last chain).  Four wavefronts of 16 rows each accumulate
+// G (rows x beta) times T (beta x 16) with the FP64 16x16x4 MFMA: lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16] and receives
+// D[l / 16 + 4 v][l % 16] in register v.  G is read at clamped (valid)
+// indices without branches; rows past nsupp are computed but not stored,
+// and columns past beta meet zeros of T.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_lowrank_apply_mfma(T* __restrict__ theta, int64_t Np,
-                                                               int beta, int nsupp,
-                                                               const int32_t* __restrict__ supp,
-                                                               const double* __restrict__ GT,
-                                                               const double* __restrict__ t,
-                                                               int nchains) {
-  extern __shared__ double sT[];  // [beta][16], zero past the last chain
-  const int c0 = blockIdx.y * 16;
-  for (int e = threadIdx.x; e < beta * 16; e += blockDim.x) {
-    const int j = e >> 4, cc = e & 15;
-    sT[e] = c0 + cc < nchains ? t[int64_t(c0 + cc) * beta + j] : 0.0;
-  }
-  __syncthreads();
+struct MfmaRowsPrefetch {
+  double av[16];  // G^T entries of the first 64 columns
+  double th[4];   // this lane's theta values at its four result rows
+};
+
+// Issue the loads that do not depend on t (the first column chunk of G and
+// the theta values that lowrank_mfma_rows updates), so they are in flight
+// while t is being formed.
+template <typename T>
+__device__ __forceinline__ void lowrank_mfma_prefetch(MfmaRowsPrefetch<T>& pf,
+                                                      const T* __restrict__ theta, int64_t Np,
+                                                      int beta, int nsupp,
+                                                      const int32_t* __restrict__ supp,
+                                                      const double* __restrict__ GT, int c0,
+                                                      int nchains) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r0 = blockIdx.x * 64 + wave * 16;
   const int ri = lane & 15, kk = lane >> 4;
-  const int r = r0 + ri;
+  const int rc = min(r0 + ri, nsupp - 1);
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int k = min(4 * u + kk, beta - 1);
+    pf.av[u] = GT[int64_t(k) * nsupp + rc];
+  }
+  const T* th = theta + int64_t(min(c0 + (lane & 15), nchains - 1)) * Np;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int rr = min(r0 + (lane >> 4) + 4 * v, nsupp - 1);
+    pf.th[v] = double(th[supp[rr]]);
+  }
+}
+
+// theta_r -= sum_j G_rj t_j for the block's 64 support rows and chains
+// c0 .. c0 + 15 on the matrix cores, with t staged in LDS as sT[beta][16]
+// (zero past the last chain) and the loads of lowrank_mfma_prefetch done.
+// Four wavefronts of 16 rows each accumulate G (rows x beta) times
+// T (beta x 16) with the FP64 16x16x4 MFMA: lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16] and receives D[l / 16 + 4 v][l % 16] in register v.
+// G is read at clamped (valid) indices without branches; rows past nsupp are
+// computed but not stored, and columns past beta meet zeros of T.
+template <typename T>
+__device__ __forceinline__ void lowrank_mfma_rows(const MfmaRowsPrefetch<T>& pf,
+                                                  T* __restrict__ theta, int64_t Np, int beta,
+                                                  int nsupp, const int32_t* __restrict__ supp,
+                                                  const double* __restrict__ GT,
+                                                  const double* __restrict__ sT, int c0,
+                                                  int nchains) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = blockIdx.x * 64 + wave * 16;
+  const int ri = lane & 15, kk = lane >> 4;
+  const int rc = min(r0 + ri, nsupp - 1);
   mfma_d4 acc = {0.0, 0.0, 0.0, 0.0};
   // chunks of 64 columns: the 16 loads of a chunk are issued together
   for (int kc = 0; kc < beta; kc += 64) {
     double av[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const int k = kc + 4 * u + kk;
-      av[u] = (r < nsupp && k < beta) ? GT[int64_t(k) * nsupp + r] : 0.0;
+      const int k = min(kc + 4 * u + kk, beta - 1);
+      av[u] = kc == 0 ? pf.av[u] : GT[int64_t(k) * nsupp + rc];
     }
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
@@ -767,11 +825,121 @@ __global__ __launch_bounds__(kBlock) void k_lowrank_apply_mfma(T* __restrict__ t
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int rr = r0 + (lane >> 4) + 4 * v;
-    if (rr < nsupp) {
-      const int64_t at = supp[rr];
-      th[at] = T(double(th[at]) - acc[v]);
+    if (rr < nsupp) th[supp[rr]] = T(pf.th[v] - acc[v]);
+  }
+}
+
+// The low-rank correction (Alg. 3) in one launch after a 2D sweep that wrote
+// its snapshot of B's sites (bsnap, [nchains][bnnz]).  Every block forms
+// xi = Gamma^{-1/2} zeta and t = B^T theta* - Gamma xi for its group of up to
+// 16 chains from the snapshot, which the correction does not modify, so the
+// blocks need no ordering among themselves.  Blocks x < nrt then apply
+// theta -= G t on their 64 support rows (lowrank_mfma_rows); with v_out,
+// blocks x >= nrt instead write 64 rows each of v = xi + S^{-1} t for the
+// coarse right-hand side.  The noise and the products per entry are those of
+// k_lowrank_prep; each row sum runs over its entries in order, eight loads
+// in flight at a time.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_lowrank_fused_mfma(
+    T* __restrict__ theta, int64_t Np, int beta, int nsupp, const int32_t* __restrict__ supp,
+    const double* __restrict__ GT, const int64_t* __restrict__ bptr,
+    const double* __restrict__ bval, const double* __restrict__ bsnap, int64_t bnnz,
+    const double* __restrict__ gisq, const double* __restrict__ gam,
+    const double* __restrict__ SinvT, double* __restrict__ v_out, int nrt, uint32_t word,
+    const int64_t* __restrict__ mcur, uint32_t seed, uint32_t chain0, int nchains) {
+  extern __shared__ double sT[];  // [beta][16] t, then [beta][16] xi in the v blocks
+  double* sX = sT + beta * 16;
+  const int c0 = blockIdx.y * 16;
+  const int nc = min(16, nchains - c0);
+  const bool vblock = int(blockIdx.x) >= nrt;
+  const uint32_t m = uint32_t(*mcur);
+  MfmaRowsPrefetch<T> pf;
+  if (!vblock) lowrank_mfma_prefetch<T>(pf, theta, Np, beta, nsupp, supp, GT, c0, nchains);
+  const int npairs = (beta + 1) / 2;
+  for (int task = threadIdx.x; task < npairs * 16; task += blockDim.x) {
+    const int p = task % npairs, cc = task / npairs;
+    double tv[2] = {0.0, 0.0}, xv[2] = {0.0, 0.0};
+    if (cc < nc) {
+      const int c = c0 + cc;
+      const Block4 blk = philox10(uint32_t(p), word, m, 1u, seed, chain0 + c);
+      double z[2];
+      Gauss<double>::pair(blk, z[0], z[1]);
+      const double* sn = bsnap + int64_t(c) * bnnz;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int j = min(2 * p + h, beta - 1);
+        const int64_t e0 = bptr[j], e1 = bptr[j + 1];
+        double w = 0.0;
+        for (int64_t e = e0; e < e1; e += 8) {
+          double pr[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int64_t ec = min(e + u, e1 - 1);
+            pr[u] = bval[ec] * sn[ec];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (e + u < e1) w += pr[u];
+        }
+        xv[h] = z[h] * gisq[j];
+        tv[h] = w - gam[j] * xv[h];
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int j = 2 * p + h;
+      if (j < beta) {
+        sT[j * 16 + cc] = tv[h];
+        if (vblock) sX[j * 16 + cc] = xv[h];
+      }
     }
   }
+  __syncthreads();
+  if (vblock) {
+    const int j0 = (int(blockIdx.x) - nrt) * 64;
+    for (int task = threadIdx.x; task < 64 * nc; task += blockDim.x) {
+      const int j = j0 + task % 64, cc = task / 64;
+      if (j >= beta) continue;
+      double a = 0.0;
+#pragma unroll 8
+      for (int k = 0; k < beta; ++k) a += SinvT[int64_t(k) * beta + j] * sT[k * 16 + cc];
+      v_out[int64_t(c0 + cc) * beta + j] = sX[j * 16 + cc] + a;
+    }
+    return;
+  }
+  lowrank_mfma_rows<T>(pf, theta, Np, beta, nsupp, supp, GT, sT, c0, nchains);
+}
+
+// The same product on the matrix cores (lowrank_mfma_rows): a block updates
+// 64 support rows x 16 chains, with t of the chain group staged in LDS.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_lowrank_apply_mfma(T* __restrict__ theta, int64_t Np,
+                                                               int beta, int nsupp,
+                                                               const int32_t* __restrict__ supp,
+                                                               const double* __restrict__ GT,
+                                                               const double* __restrict__ t,
+                                                               int nchains) {
+  extern __shared__ double sT[];  // [beta][16], zero past the last chain
+  const int c0 = blockIdx.y * 16;
+  MfmaRowsPrefetch<T> pf;
+  lowrank_mfma_prefetch<T>(pf, theta, Np, beta, nsupp, supp, GT, c0, nchains);
+  // staged four entries per thread at a time with branch-free loads
+  for (int e0 = 0; e0 < beta * 16; e0 += 4 * int(blockDim.x)) {
+    double tv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = min(e0 + int(threadIdx.x) + u * int(blockDim.x), beta * 16 - 1);
+      const int j = e >> 4, cc = min(c0 + (e & 15), nchains - 1);
+      tv[u] = t[int64_t(cc) * beta + j];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + int(threadIdx.x) + u * int(blockDim.x);
+      if (e < beta * 16) sT[e] = c0 + (e & 15) < nchains ? tv[u] : 0.0;
+    }
+  }
+  __syncthreads();
+  lowrank_mfma_rows<T>(pf, theta, Np, beta, nsupp, supp, GT, sT, c0, nchains);
 }
 
 hipError_t launch_lowrank(const Launch& L, const DevLevel& lv, void* theta, int dir, uint32_t word,
@@ -812,6 +980,29 @@ hipError_t launch_lowrank(const Launch& L, const DevLevel& lv, void* theta, int 
   return hipGetLastError();
 }
 
+hipError_t launch_lowrank_fused(const Launch& L, const DevLevel& lv, void* theta, int dir,
+                                uint32_t word, int beta, const double* gisq, const double* gam,
+                                double* v_out) {
+  if (L.mcur == nullptr || lv.bsnap == nullptr || beta < 1 || beta > 512) return hipErrorInvalidValue;
+  if (v_out != nullptr && lv.SinvT == nullptr) return hipErrorInvalidValue;
+  const int nsupp = lv.nsupp[dir];
+  const int nrt = (nsupp + 63) / 64;             // blocks of 64 support rows
+  const int nvb = v_out ? (beta + 63) / 64 : 0;  // blocks of 64 rows of v
+  if (nrt + nvb == 0) return hipSuccess;
+  // LDS: t (and xi) of 16 chains, <= 128 KiB
+  const size_t shm = size_t(beta) * 16 * sizeof(double) * (v_out ? 2 : 1);
+  dim3 grid(unsigned(nrt + nvb), unsigned((L.nchains + 15) / 16));
+  if (L.fp32)
+    k_lowrank_fused_mfma<float><<<grid, kBlock, shm, L.stream>>>(
+        (float*)theta, lv.g.Np, beta, nsupp, lv.supp[dir], lv.GT[dir], lv.bptr, lv.bval, lv.bsnap,
+        lv.bnnz, gisq, gam, lv.SinvT, v_out, nrt, word, L.mcur, L.seed, L.chain0, L.nchains);
+  else
+    k_lowrank_fused_mfma<double><<<grid, kBlock, shm, L.stream>>>(
+        (double*)theta, lv.g.Np, beta, nsupp, lv.supp[dir], lv.GT[dir], lv.bptr, lv.bval, lv.bsnap,
+        lv.bnnz, gisq, gam, lv.SinvT, v_out, nrt, word, L.mcur, L.seed, L.chain0, L.nchains);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_zero(const Launch& L, void* p, int64_t count) {
   if (count == 0) return hipSuccess;
   if (L.fp32)
@@ -828,7 +1019,8 @@ hipError_t launch_qoi(const Launch& L, const DevLevel& fine, const void* theta, 
   MGMC_DISPATCH(L, { k_qoi_partial<T, DIM><<<grid, kBlock, 0, L.stream>>>((const T*)theta, fine.g, fine.N, F, partial, nb); });
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_qoi_final<<<L.nchains, kBlock, 0, L.stream>>>(partial, nb, qoi, L.mcur, m0, L.nchains);
+  k_qoi_final<<<1, kBlock, 0, L.stream>>>(partial, nb, qoi, const_cast<int64_t*>(L.mcur), m0,
+                                           L.nchains);
   return hipGetLastError();
 }
 

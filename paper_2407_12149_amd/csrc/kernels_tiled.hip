@@ -16,6 +16,8 @@
 // k_restrict2d_reg computes f_{l-1} = P^T (f_l - A_l theta) (Alg. 1,
 // restriction step) for a tile of coarse nodes from fine residuals staged
 // in LDS, with the residual's operator held in registers across chains.
+#include <cmath>
+
 #include "device_common.h"
 #include "device_rng.h"
 #include "mgmc_internal.h"
@@ -90,6 +92,21 @@ struct Swz {
   static __device__ __forceinline__ int west(int s) { return s > 0 ? -W : 3 * W - 1; }
 };
 
+// Copy the swept values of chain c at B's sites inside tile `tile` into the
+// snapshot (B^T theta is then formed from it without another pass over
+// theta).  at(lx, ly) reads the LDS tile at region coordinates.
+template <class At>
+__device__ __forceinline__ void snap_sites(const BSnap& bs, const Geom& g, int tile, int c, int ox,
+                                           int oy, int nt, At at) {
+  const int b0 = bs.ptr[tile], b1 = bs.ptr[tile + 1];
+  for (int i = b0 + int(threadIdx.x); i < b1; i += nt) {
+    const int e = bs.ent[i];
+    const int site = bs.idx[e];
+    const int x = site % g.px - 3, y = site / g.px;
+    bs.snap[int64_t(c) * bs.nnz + e] = at(x - ox, y - oy);
+  }
+}
+
 template <typename T, int NPASS, bool PROLONG, bool USERP, int TX, int TY>
 __global__ __launch_bounds__(kBlock) void k_sweep2d_tiled(
     const T* __restrict__ coef, const T* __restrict__ invd, const T* __restrict__ isqd,
@@ -97,7 +114,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d_tiled(
     const T* __restrict__ f, int64_t fcs, Geom g,
     const T* __restrict__ psi, Geom gc, const double* __restrict__ wP, int backward,
     uint32_t word, const int64_t* __restrict__ mcur, uint32_t seed, uint32_t chain0, int tiles_x,
-    int cpb, int nchains) {
+    int cpb, int nchains, BSnap bs) {
   constexpr bool CROSS = (NPASS == 2);
   constexpr int H = NPASS, RX = TX + 2 * H, RY = TY + 2 * H;
   constexpr int Q = RX / 4 + 2;  // pair slots per row
@@ -114,14 +131,32 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d_tiled(
     const T* thi = theta_in + int64_t(c) * g.Np;
     T* tho = theta_out + int64_t(c) * g.Np;
     const T* fc = f ? f + int64_t(c) * fcs : nullptr;
-    for (int idx = threadIdx.x; idx < RX * RY; idx += blockDim.x) {
-      const int x = ox + idx % RX, y = oy + idx / RX;
-      T v = T(0);
-      if (x >= 1 && x <= n && y >= 1 && y <= n) {
-        if (!zero_in) v = thi[pidx(g, x, y, 0)];
-        if (PROLONG) v += prolong_at<T, USERP>(psi + int64_t(c) * gc.Np, gc, wP, x, y);
+    // Tile load in chunks of KB entries per thread: the loads of a chunk are
+    // branch-free (positions outside the grid read offset 0 of the field,
+    // which is padding and stays zero; the prolongation reads clamped nodes
+    // and is masked), so they are all in flight before the LDS writes.
+    constexpr int KF = (RX * RY + kBlock - 1) / kBlock, KB = PROLONG ? 2 : 4;
+#pragma unroll 1
+    for (int k0 = 0; k0 < KF; k0 += KB) {
+      T v[KB];
+#pragma unroll
+      for (int u = 0; u < KB; ++u) {
+        const int idx = min(int(threadIdx.x) + (k0 + u) * kBlock, RX * RY - 1);
+        const int x = ox + idx % RX, y = oy + idx / RX;
+        const bool in = x >= 1 && x <= n && y >= 1 && y <= n;
+        T a = thi[(in && !zero_in) ? pidx(g, x, y, 0) : 0];
+        if (PROLONG) {
+          const int xc = min(max(x, 1), n), yc = min(max(y, 1), n);
+          const T pr = prolong_at<T, USERP>(psi + int64_t(c) * gc.Np, gc, wP, xc, yc);
+          a += in ? pr : T(0);
+        }
+        v[u] = a;
       }
-      sh[Z::pos(idx % RX, idx / RX)] = v;
+#pragma unroll
+      for (int u = 0; u < KB; ++u) {
+        const int idx = int(threadIdx.x) + (k0 + u) * kBlock;
+        if (idx < RX * RY) sh[Z::pos(idx % RX, idx / RX)] = v[u];
+      }
     }
     __syncthreads();
     for (int p = 0; p < NPASS; ++p) {
@@ -203,6 +238,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d_tiled(
       }
       __syncthreads();
     }
+    if (bs.snap) snap_sites(bs, g, int(blockIdx.x), c, ox, oy, int(blockDim.x),
+                            [&](int lx, int ly) { return double(sh[Z::pos(lx, ly)]); });
     for (int idx = threadIdx.x; idx < TX * TY; idx += blockDim.x) {
       const int x = tx0 + idx % TX, y = ty0 + idx / TX;
       if (x <= n && y <= n) tho[pidx(g, x, y, 0)] = sh[Z::pos(x - ox, y - oy)];
@@ -218,14 +255,14 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d_tiled(
 // contiguous loads, and reuses them for every colour pass and every chain of
 // the block; only the states go through LDS.  Rows cover the tile plus
 // NPASS-1 halo rows, segments the tile plus one segment either side.
-template <typename T, int NPASS, bool PROLONG, bool USERP, int TYS, int NT>
+template <typename T, int NPASS, bool PROLONG, bool USERP, int TYS, int NT, int MC>
 __global__ __launch_bounds__(NT) void k_sweep2d_seg(
     const T* __restrict__ coef, const T* __restrict__ invd, const T* __restrict__ isqd,
     const T* __restrict__ theta_in, T* __restrict__ theta_out, int zero_in,
     const T* __restrict__ f, int64_t fcs, Geom g,
     const T* __restrict__ psi, Geom gc, const double* __restrict__ wP, int backward,
     uint32_t word, const int64_t* __restrict__ mcur, uint32_t seed, uint32_t chain0, int tiles_x,
-    int cpb, int nchains) {
+    int cpb, int nchains, const double* __restrict__ bmtab, BSnap bs) {
   constexpr bool CROSS = (NPASS == 2);
   constexpr int TX = 64, SX = TX / 4 + 2;       // segments per row (tile + one each side)
   constexpr int SY = TYS + 2 * (NPASS - 1);     // rows with owners
@@ -233,14 +270,24 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
   constexpr int GA = (HALF * SX + 63) / 64 * 64;  // threads of the first parity group
   constexpr int H = NPASS, RX = TX + 2 * H, RY = TYS + 2 * H;
   constexpr int NB = CROSS ? 4 : 8;
+  // right-hand side: shared by all chains (or absent) on the 5-point finest
+  // level, one per chain on the 9-point coarse levels
+  constexpr bool RHSC = !CROSS;
   static_assert(SY % 2 == 0, "owner rows must split evenly by parity");
   static_assert(GA + HALF * SX <= NT, "block too small for the segment grid");
   using Z = Swz<RX>;
-  __shared__ T sh[RY * Z::RS];
+  __shared__ T sh[MC][RY * Z::RS];
   // coarse patch under the tile region for the fused prolongation
   constexpr int CRX = RX / 2 + 2, CRY = RY / 2 + 2;
   constexpr int KP = PROLONG ? (CRX * CRY + NT - 1) / NT : 0;
-  __shared__ T spsi[PROLONG ? CRY * CRX : 1];
+  __shared__ T spsi[MC][PROLONG ? CRY * CRX : 1];
+  // double precision draws its normals with the table-driven Box-Muller
+  constexpr bool TAB = sizeof(T) == 8;
+  __shared__ double stab[TAB ? kBmTable : 1];
+  if (TAB) {
+    for (int i = int(threadIdx.x); i < kBmTable; i += NT) stab[i] = bmtab[i];
+    __syncthreads();
+  }
   const int n = g.n;
   const int tx0 = int(blockIdx.x % tiles_x) * TX + 1;
   const int ty0 = int(blockIdx.x / tiles_x) * TYS + 1;
@@ -259,7 +306,7 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
   const int y = y0 + r;
   const bool row_in = owner && y >= 1 && y <= n;
   // stencil of the four sites in registers (zero outside the grid)
-  T cf[4][NB], ivd[4], isd[4], rhs[4];
+  T cf[4][NB], ivd[4], isd[4], rhs[RHSC ? 1 : 4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int x = 4 * q + 1 + k;
@@ -275,7 +322,7 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
     }
     ivd[k] = invd[gi];
     isd[k] = isqd[gi];
-    rhs[k] = (f && fcs == 0) ? f[gi] : T(0);
+    if (!RHSC) rhs[k] = f ? f[gi] : T(0);
   }
   // The passes this thread updates sites in ("slots"): on red-black levels
   // both passes (each row holds both colours), on four-colour levels the
@@ -306,73 +353,94 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
   constexpr bool HOIST = CROSS || !PROLONG || sizeof(T) == 4;
   const int cb = int(blockIdx.y) * cpb;
   const int ce = min(nchains, cb + cpb);
-  for (int c = cb; c < ce; ++c) {
-    const T* thi = theta_in + int64_t(c) * g.Np;
-    T* tho = theta_out + int64_t(c) * g.Np;
+  const int jx0 = ox >> 1, jy0 = oy >> 1;  // first coarse node under the region
+  auto draw = [&](int c, int p, T& z0, T& z1) {
+    const int colour = pass_colour(p);
+    const int xpar = colour & 1;
+    const int m1 = xpar ? (n + 1) / 2 : (n - 1) / 2;
+    const int qx = (m1 + 1) / 2;
+    const uint32_t pair = uint32_t(q) + uint32_t(qx) * uint32_t((y - 1) >> 1);
+    const Block4 blk = philox10(pair, word | uint32_t(colour), m, 0u, seed, chain0 + c);
+    if constexpr (TAB) {
+      double a0, a1;
+      gauss_pair_tab(blk, stab, a0, a1);
+      z0 = T(a0);
+      z1 = T(a1);
+    } else {
+      Gauss<T>::pair(blk, z0, z1);
+    }
+  };
+  // MC chains per step: their tiles sit side by side in LDS and every pass
+  // updates all of them between two barriers.  A step past the last chain
+  // works on the last chain's data and stores nothing.
+  for (int c0 = cb; c0 < ce; c0 += MC) {
     // Every load below is issued unconditionally: positions outside the grid
     // (or all of them when the input is zero) read offset 0 of the field,
     // which is padding and stays zero.  Without per-load branches the loaded
     // registers need no copies, so nothing waits for the loads before the
     // noise below is drawn.
-    if (f && fcs != 0) {
+    T rc[RHSC ? MC : 1][4], pv[MC][KP > 0 ? KP : 1], fv[MC][KF];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int x = 4 * q + 1 + k;
-        rhs[k] = f[int64_t(c) * fcs + ((row_in && x >= 1 && x <= n) ? pidx(g, x, y, 0) : 0)];
+    for (int mi = 0; mi < MC; ++mi) {
+      const int c = min(c0 + mi, ce - 1);
+      if (RHSC) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int x = 4 * q + 1 + k;
+          rc[mi][k] = f[int64_t(c) * fcs + ((row_in && x >= 1 && x <= n) ? pidx(g, x, y, 0) : 0)];
+        }
       }
-    }
-    // issue the tile loads (and those of the coarse patch) into registers ...
-    const int jx0 = ox >> 1, jy0 = oy >> 1;  // first coarse node under the region
-    T pv[KP > 0 ? KP : 1];
-#pragma unroll
-    for (int k = 0; k < KP; ++k) {
-      const int e = int(threadIdx.x) + k * NT;
-      const int Jx = jx0 + e % CRX, Jy = jy0 + e / CRX;
-      const bool ok = e < CRX * CRY && Jx >= 1 && Jx <= gc.n && Jy >= 1 && Jy <= gc.n;
-      pv[k] = psi[int64_t(c) * gc.Np + (ok ? pidx(gc, Jx, Jy, 0) : 0)];
-    }
-    T fv[KF];
-#pragma unroll
-    for (int k = 0; k < KF; ++k) {
-      const int idx = int(threadIdx.x) + k * NT;
-      const int xx = ox + idx % RX, yy = oy + idx / RX;
-      const bool ok = !zero_in && idx < RX * RY && xx >= 1 && xx <= n && yy >= 1 && yy <= n;
-      fv[k] = thi[ok ? pidx(g, xx, yy, 0) : 0];
-    }
-    // ... and draw this chain's noise while they are in flight (except where
-    // registers are scarce: FP64 four-colour levels with the prolongation)
-    auto draw = [&](int p, T& z0, T& z1) {
-      const int colour = pass_colour(p);
-      const int xpar = colour & 1;
-      const int m1 = xpar ? (n + 1) / 2 : (n - 1) / 2;
-      const int qx = (m1 + 1) / 2;
-      const uint32_t pair = uint32_t(q) + uint32_t(qx) * uint32_t((y - 1) >> 1);
-      const Block4 blk = philox10(pair, word | uint32_t(colour), m, 0u, seed, chain0 + c);
-      Gauss<T>::pair(blk, z0, z1);
-    };
-    T zz[2][2];
-#pragma unroll
-    for (int sl = 0; sl < 2; ++sl) {
-      zz[sl][0] = zz[sl][1] = T(0);
-      if (HOIST && pass_active(pslot[sl])) draw(pslot[sl], zz[sl][0], zz[sl][1]);
-    }
-    if (PROLONG) {
 #pragma unroll
       for (int k = 0; k < KP; ++k) {
         const int e = int(threadIdx.x) + k * NT;
-        if (e < CRX * CRY) spsi[e] = pv[k];
+        const int Jx = jx0 + e % CRX, Jy = jy0 + e / CRX;
+        const bool ok = e < CRX * CRY && Jx >= 1 && Jx <= gc.n && Jy >= 1 && Jy <= gc.n;
+        pv[mi][k] = psi[int64_t(c) * gc.Np + (ok ? pidx(gc, Jx, Jy, 0) : 0)];
+      }
+      const T* thi = theta_in + int64_t(c) * g.Np;
+#pragma unroll
+      for (int k = 0; k < KF; ++k) {
+        const int idx = int(threadIdx.x) + k * NT;
+        const int xx = ox + idx % RX, yy = oy + idx / RX;
+        const bool ok = !zero_in && idx < RX * RY && xx >= 1 && xx <= n && yy >= 1 && yy <= n;
+        fv[mi][k] = thi[ok ? pidx(g, xx, yy, 0) : 0];
+      }
+    }
+    // ... and draw the noise while they are in flight (except where
+    // registers are scarce: FP64 four-colour levels with the prolongation)
+    T zz[MC][2][2];
+#pragma unroll
+    for (int mi = 0; mi < MC; ++mi) {
+#pragma unroll
+      for (int sl = 0; sl < 2; ++sl) {
+        zz[mi][sl][0] = zz[mi][sl][1] = T(0);
+        if (HOIST && c0 + mi < ce && pass_active(pslot[sl]))
+          draw(c0 + mi, pslot[sl], zz[mi][sl][0], zz[mi][sl][1]);
+      }
+    }
+    if (PROLONG) {
+#pragma unroll
+      for (int mi = 0; mi < MC; ++mi) {
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+          const int e = int(threadIdx.x) + k * NT;
+          if (e < CRX * CRY) spsi[mi][e] = pv[mi][k];
+        }
       }
       __syncthreads();
     }
 #pragma unroll
-    for (int k = 0; k < KF; ++k) {
-      const int idx = int(threadIdx.x) + k * NT;
-      if (idx >= RX * RY) continue;
-      const int xx = ox + idx % RX, yy = oy + idx / RX;
-      T v = fv[k];
-      if (PROLONG && xx >= 1 && xx <= n && yy >= 1 && yy <= n)
-        v += prolong_lds<T, USERP>(spsi, CRX, jx0, jy0, gc, wP, xx, yy);
-      sh[Z::pos(idx % RX, idx / RX)] = v;
+    for (int mi = 0; mi < MC; ++mi) {
+#pragma unroll
+      for (int k = 0; k < KF; ++k) {
+        const int idx = int(threadIdx.x) + k * NT;
+        if (idx >= RX * RY) continue;
+        const int xx = ox + idx % RX, yy = oy + idx / RX;
+        T v = fv[mi][k];
+        if (PROLONG && xx >= 1 && xx <= n && yy >= 1 && yy <= n)
+          v += prolong_lds<T, USERP>(spsi[mi], CRX, jx0, jy0, gc, wP, xx, yy);
+        sh[mi][Z::pos(idx % RX, idx / RX)] = v;
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -382,42 +450,54 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
         const int colour = pass_colour(p);
         const int xpar = colour & 1;
         const int k0 = xpar ? 0 : 1;  // offset of the colour's first site in the segment
-        T z[2] = {p == pslot[0] ? zz[0][0] : zz[1][0], p == pslot[0] ? zz[0][1] : zz[1][1]};
-        if (!HOIST) draw(p, z[0], z[1]);
         const int xlo = max(1, tx0 - hp), xhi = min(n, tx0 + TX - 1 + hp);
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int mi = 0; mi < MC; ++mi) {
+          T z[2] = {p == pslot[0] ? zz[mi][0][0] : zz[mi][1][0],
+                    p == pslot[0] ? zz[mi][0][1] : zz[mi][1][1]};
+          if (!HOIST) draw(min(c0 + mi, ce - 1), p, z[0], z[1]);
 #pragma unroll
-          for (int kk = 0; kk < 2; ++kk) {  // resolve the site index at compile time
-            if (kk != k0) continue;
-            const int k = kk + 2 * j;
-            const int x = 4 * q + 1 + k;
-            if (x < xlo || x > xhi) continue;
-            const int lx = x - ox;
-            const int li = Z::pos(lx, y - oy);
-            const int sxm = lx & 3;
-            const int oe = Z::east(sxm), ow = Z::west(sxm);
-            T s = rhs[k];
-            int b = 0;
+          for (int j = 0; j < 2; ++j) {
 #pragma unroll
-            for (int t = 0; t < 9; ++t) {
-              const int dx = t % 3 - 1, dy = t / 3 - 1;
-              if (dx == 0 && dy == 0) continue;
-              if (CROSS && dx != 0 && dy != 0) continue;
-              const int o = dy * Z::RS + (dx < 0 ? ow : (dx > 0 ? oe : 0));
-              s -= cf[k][b++] * sh[li + o];
+            for (int kk = 0; kk < 2; ++kk) {  // resolve the site index at compile time
+              if (kk != k0) continue;
+              const int k = kk + 2 * j;
+              const int x = 4 * q + 1 + k;
+              if (x < xlo || x > xhi) continue;
+              const int lx = x - ox;
+              const int li = Z::pos(lx, y - oy);
+              const int sxm = lx & 3;
+              const int oe = Z::east(sxm), ow = Z::west(sxm);
+              T s = RHSC ? rc[RHSC ? mi : 0][k] : rhs[RHSC ? 0 : k];
+              int b = 0;
+#pragma unroll
+              for (int t = 0; t < 9; ++t) {
+                const int dx = t % 3 - 1, dy = t / 3 - 1;
+                if (dx == 0 && dy == 0) continue;
+                if (CROSS && dx != 0 && dy != 0) continue;
+                const int o = dy * Z::RS + (dx < 0 ? ow : (dx > 0 ? oe : 0));
+                s -= cf[k][b++] * sh[mi][li + o];
+              }
+              sh[mi][li] = s * ivd[k] + z[j] * isd[k];
             }
-            sh[li] = s * ivd[k] + z[j] * isd[k];
           }
         }
       }
       __syncthreads();
     }
-    if (row_in && sx >= 1 && sx <= TX / 4 && y >= ty0 && y <= ty0 + TYS - 1) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int x = 4 * q + 1 + k;
-        if (x <= n) tho[pidx(g, x, y, 0)] = sh[Z::pos(x - ox, y - oy)];
+    for (int mi = 0; mi < MC; ++mi) {
+      const int c = c0 + mi;
+      if (c >= ce) break;
+      if (bs.snap) snap_sites(bs, g, int(blockIdx.x), c, ox, oy, NT,
+                              [&](int lx, int ly) { return double(sh[mi][Z::pos(lx, ly)]); });
+      if (row_in && sx >= 1 && sx <= TX / 4 && y >= ty0 && y <= ty0 + TYS - 1) {
+        T* tho = theta_out + int64_t(c) * g.Np;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int x = 4 * q + 1 + k;
+          if (x <= n) tho[pidx(g, x, y, 0)] = sh[mi][Z::pos(x - ox, y - oy)];
+        }
       }
     }
     __syncthreads();
@@ -563,11 +643,46 @@ int chains_per_block(int nchains, int64_t tiles) {
 
 }  // namespace
 
+void fill_bm_table(double* t) {
+  const long double two_pi = 6.283185307179586476925286766559005768L;
+  for (int i = 0; i < 128; ++i) {
+    const long double c = 45.0L / 64.0L + (i + 0.5L) * (45.0L / 8192.0L);
+    t[i] = double(std::log(c));
+    t[128 + i] = double(1.0L / c);
+  }
+  for (int k = 0; k <= 256; ++k) {
+    long double sn = std::sin(two_pi * k / 256.0L), cs = std::cos(two_pi * k / 256.0L);
+    if (k % 64 == 0) {  // exact on the axes
+      const int q = k / 64;
+      sn = (q == 1) ? 1.0L : (q == 3 ? -1.0L : 0.0L);
+      cs = (q == 0 || q == 4) ? 1.0L : (q == 2 ? -1.0L : 0.0L);
+    }
+    t[256 + k] = double(sn);
+    t[513 + k] = double(cs);
+  }
+}
+
+// The snapshot of B's sites for the fused low-rank step, in the entry
+// lists of tile height index gi.
+static BSnap make_snap(const DevLevel& lv, int gi, bool snap) {
+  BSnap bs;
+  if (!snap) return bs;
+  bs.ptr = lv.bt_ptr[gi];
+  bs.ent = lv.bt_ent[gi];
+  bs.idx = lv.bidx;
+  bs.snap = lv.bsnap;
+  bs.nnz = lv.bnnz;
+  return bs;
+}
+
 hipError_t launch_sweep_tiled(const Launch& L, const DevLevel& lv, const void* theta_in,
                               void* theta_out, int zero_in, const void* f, int64_t fcs,
-                              uint32_t word, int backward, const DevLevel* coarse, const void* psi) {
+                              uint32_t word, int backward, const DevLevel* coarse, const void* psi,
+                              bool snap) {
   if (L.mcur == nullptr || L.dim != 2 || theta_in == theta_out) return hipErrorInvalidValue;
   if (coarse != nullptr && psi == nullptr) return hipErrorInvalidValue;
+  if (snap && (lv.bsnap == nullptr || lv.bt_ptr[0] == nullptr)) return hipErrorInvalidValue;
+  const BSnap bs = make_snap(lv, 0, snap);
   const int n = lv.g.n;
   const int tiles_x = (n + kTX - 1) / kTX, tiles_y = (n + kTY - 1) / kTY;
   const int64_t tiles = int64_t(tiles_x) * tiles_y;
@@ -581,7 +696,7 @@ hipError_t launch_sweep_tiled(const Launch& L, const DevLevel& lv, const void* t
       (const T*)lv.coef, (const T*)lv.invd, (const T*)lv.isqd, (const T*)theta_in, (T*)theta_out,     \
       zero_in, (const T*)f, fcs, lv.g, (const T*)psi, gc, userp ? lv.wP : nullptr, backward, word,     \
       L.mcur,                                                                                          \
-      L.seed, L.chain0, tiles_x, cpb, L.nchains)
+      L.seed, L.chain0, tiles_x, cpb, L.nchains, bs)
 #define MGMC_SWEEP_NP(T, NP)                      \
   do {                                            \
     if (!pro) MGMC_SWEEP_T(T, NP, false, false);  \
@@ -601,11 +716,17 @@ hipError_t launch_sweep_tiled(const Launch& L, const DevLevel& lv, const void* t
 hipError_t launch_sweep_seg(const Launch& L, const DevLevel& lv, const void* theta_in,
                             void* theta_out, int zero_in, const void* f, int64_t fcs,
                             uint32_t word, int backward, const DevLevel* coarse, const void* psi,
-                            int variant, int cpb_override) {
+                            int variant, int cpb_override, bool snap) {
   if (L.mcur == nullptr || L.dim != 2 || theta_in == theta_out) return hipErrorInvalidValue;
   if (coarse != nullptr && psi == nullptr) return hipErrorInvalidValue;
+  if (!L.fp32 && L.bm_table == nullptr) return hipErrorInvalidValue;
+  // the kernel takes a shared right-hand side on the 5-point level and one
+  // per chain on 9-point levels
+  if (lv.cross ? fcs != 0 : (f == nullptr || fcs == 0)) return hipErrorInvalidValue;
   const int n = lv.g.n;
   const bool big = variant == 1;
+  if (snap && (lv.bsnap == nullptr || lv.bt_ptr[big ? 2 : 1] == nullptr)) return hipErrorInvalidValue;
+  const BSnap bs = make_snap(lv, big ? 2 : 1, snap);
   const int tys = lv.cross ? (big ? 26 : 12) : (big ? 22 : 8);
   const int nt = big ? 512 : 256;
   const int tiles_x = (n + 63) / 64, tiles_y = (n + tys - 1) / tys;
@@ -617,10 +738,10 @@ hipError_t launch_sweep_seg(const Launch& L, const DevLevel& lv, const void* the
   const bool userp = pro && lv.wP != nullptr;
   const Geom gc = pro ? coarse->g : Geom{};
 #define MGMC_SEG_T(T, NP, PR, UP, TYS, NT)                                                           \
-  k_sweep2d_seg<T, NP, PR, UP, TYS, NT><<<grid, NT, 0, L.stream>>>(                                 \
+  k_sweep2d_seg<T, NP, PR, UP, TYS, NT, 1><<<grid, NT, 0, L.stream>>>(                              \
       (const T*)lv.coef, (const T*)lv.invd, (const T*)lv.isqd, (const T*)theta_in, (T*)theta_out,     \
       zero_in, (const T*)f, fcs, lv.g, (const T*)psi, gc, userp ? lv.wP : nullptr, backward, word,     \
-      L.mcur, L.seed, L.chain0, tiles_x, cpb, L.nchains)
+      L.mcur, L.seed, L.chain0, tiles_x, cpb, L.nchains, L.bm_table, bs)
 #define MGMC_SEG_NP(T, NP, TYS, NT)                             \
   do {                                                          \
     if (!pro) MGMC_SEG_T(T, NP, false, false, TYS, NT);         \

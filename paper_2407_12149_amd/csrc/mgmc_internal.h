@@ -49,6 +49,28 @@ struct DevLevel {
   int32_t* supp[2] = {nullptr, nullptr};   // padded sites
   double* GT[2] = {nullptr, nullptr};      // [beta][nsupp], G = C S^{-1}
   double* SinvT = nullptr;                 // [beta][beta], S^{-1} of the forward sweep, transposed
+  // B^T theta without a separate pass over theta (2D one-launch sweeps): the
+  // sweep kernels copy the swept values at B's sites into bsnap
+  // ([nchains][bnnz], entry order of bidx); bt_ptr / bt_ent list the entries
+  // whose site lies in each 64 x TY tile, for the tile heights of the three
+  // 2D sweep forms (kSnapTY).
+  int32_t* bt_ptr[3] = {nullptr, nullptr, nullptr};  // [tiles + 1]
+  int32_t* bt_ent[3] = {nullptr, nullptr, nullptr};  // [bnnz]
+  double* bsnap = nullptr;
+};
+
+// Tile heights of the 2D sweep forms, as indexed by DevLevel::bt_ptr: the
+// LDS-tiled sweep, and the segment sweep with 256 and 512 threads, for
+// 5-point (cross) and 9-point levels.
+constexpr int kSnapTY[2][3] = {{32, 8, 22}, {32, 12, 26}};
+
+// Kernel argument: where a 2D sweep writes the snapshot of B's sites.
+struct BSnap {
+  const int32_t* ptr = nullptr;  // bt_ptr of the sweep's tile height
+  const int32_t* ent = nullptr;
+  const int32_t* idx = nullptr;  // bidx
+  double* snap = nullptr;        // null: no snapshot
+  int64_t nnz = 0;
 };
 
 // The low-rank part of the restricted residual, B_{l-1} v with
@@ -113,7 +135,12 @@ struct Launch {
   uint32_t chain0 = 0;
   const int64_t* mcur = nullptr;  // device: current sample index
   int lowrank_mfma = 0;           // low-rank G t product on the matrix cores
+  const double* bm_table = nullptr;  // device: Box-Muller table (device_rng.h), kBmTable doubles
 };
+
+// Host: fill the Box-Muller table of gauss_pair_tab (device_rng.h).
+constexpr int kBmTable = 770;
+void fill_bm_table(double* t);
 
 // Noise counter word 1: level << 8 | sweep << 4 | colour.
 __host__ __device__ inline uint32_t noise_word(int level, int sigma) { return (uint32_t(level) << 8) | (uint32_t(sigma) << 4); }
@@ -131,14 +158,15 @@ hipError_t launch_sweep_parity3d(const Launch& L, const DevLevel& lv, void* thet
 // loading.
 hipError_t launch_sweep_tiled(const Launch& L, const DevLevel& lv, const void* theta_in,
                               void* theta_out, int zero_in, const void* f, int64_t fcs,
-                              uint32_t word, int backward, const DevLevel* coarse, const void* psi);
+                              uint32_t word, int backward, const DevLevel* coarse, const void* psi,
+                              bool snap = false);
 // Segment form of the tiled sweep (stencil held in registers across passes
 // and chains).  variant 0: 256 threads per block, 1: 512; cpb_override > 0
 // fixes the chains per block.
 hipError_t launch_sweep_seg(const Launch& L, const DevLevel& lv, const void* theta_in,
                             void* theta_out, int zero_in, const void* f, int64_t fcs,
                             uint32_t word, int backward, const DevLevel* coarse, const void* psi,
-                            int variant, int cpb_override);
+                            int variant, int cpb_override, bool snap = false);
 // Restriction f_{l-1} = P^T (f_l - A_l theta) - B_{l-1} v (the last term
 // from lr when lr.row_of is set).
 hipError_t launch_restrict_tiled(const Launch& L, const DevLevel& fine, const void* theta,
@@ -163,7 +191,16 @@ hipError_t launch_coarsest(const Launch& L, const DevLevel& lv0, const void* f0,
 hipError_t launch_lowrank(const Launch& L, const DevLevel& lv, void* theta, int dir, uint32_t word,
                           int beta, const double* gisq, const double* gam, double* t,
                           double* v_out);
+// The same correction for a level whose sweep just wrote its snapshot of B's
+// sites (lv.bsnap): one launch forms t = B^T theta - Gamma xi from the
+// snapshot in every block and applies theta -= G t on the matrix cores
+// (beta <= 512); with v_out it also writes v = xi + S^{-1} t.
+hipError_t launch_lowrank_fused(const Launch& L, const DevLevel& lv, void* theta, int dir,
+                                uint32_t word, int beta, const double* gisq, const double* gam,
+                                double* v_out);
 hipError_t launch_fill_zero(const Launch& L, void* p, int64_t count);
+// q = F^T theta per chain into qoi[m - m0][chain], then m += 1 (the last
+// launch of an update).
 hipError_t launch_qoi(const Launch& L, const DevLevel& fine, const void* theta, const double* F,
                       double* partial, int nb, double* qoi, int64_t m0);
 hipError_t launch_unpack(const Launch& L, const DevLevel& lv, const void* user, void* theta);
