@@ -153,9 +153,9 @@ mgmc_status mgmc_set_graph(mgmc_ctx* ctx, int32_t enabled);
  *     launches them level by level (faster for few chains).
  *   MGMC_OPT_LOWRANK_MFMA: 1 (default) computes the low-rank product G t of
  *     all chains with FP64 matrix-core instructions (16 chains per tile; used
- *     for beta <= 512), and on 2D levels with one-launch sweeps the sweep
- *     kernel also copies its values at the observation sites, so that
- *     B^T theta, the noise xi and the product take one launch; 2 uses the
+ *     for beta <= 512), and on 2D levels with one-launch sweeps (beta <= 128)
+ *     the sweep kernel also copies its values at the observation sites, so
+ *     that B^T theta, the noise xi and the product take one launch; 2 uses the
  *     matrix cores with a separate launch for B^T theta and xi; 0 uses
  *     vector FMA, 8 chains per pass over G.  Results agree to rounding. */
 enum {

@@ -387,7 +387,7 @@ hipError_t sweep2d(mgmc_ctx* c, int l, const void* in, void* out, int zero_in, c
 // Whether the low-rank step of level l runs as one launch fed by the sweep's
 // snapshot of B's sites (2D one-launch sweeps, matrix-core product).
 bool fused_lowrank(const mgmc_ctx* c, const mgmc::DevLevel& lv) {
-  return c->beta > 0 && c->beta <= 512 && c->L.lowrank_mfma == 1 && lv.bsnap != nullptr;
+  return c->beta > 0 && c->beta <= 128 && c->L.lowrank_mfma == 1 && lv.bsnap != nullptr;
 }
 
 // One MGMC update of every chain (Alg. 1), enqueued on the context stream.

@@ -847,7 +847,7 @@ __global__ __launch_bounds__(kBlock) void k_lowrank_fused_mfma(
     const double* __restrict__ gisq, const double* __restrict__ gam,
     const double* __restrict__ SinvT, double* __restrict__ v_out, int nrt, uint32_t word,
     const int64_t* __restrict__ mcur, uint32_t seed, uint32_t chain0, int nchains) {
-  extern __shared__ double sT[];  // [beta][16] t, then [beta][16] xi in the v blocks
+  extern __shared__ double sT[];  // [beta][16] t; with v: [beta][16] xi, [64][64] S^{-1}
   double* sX = sT + beta * 16;
   const int c0 = blockIdx.y * 16;
   const int nc = min(16, nchains - c0);
@@ -896,14 +896,35 @@ __global__ __launch_bounds__(kBlock) void k_lowrank_fused_mfma(
   }
   __syncthreads();
   if (vblock) {
+    // rows j0 .. j0 + 63 of S^{-1} t, S^{-1} staged through LDS in 64 x 64
+    // chunks (all loads of a chunk in flight together)
+    double* sS = sX + beta * 16;  // [64][64]
     const int j0 = (int(blockIdx.x) - nrt) * 64;
-    for (int task = threadIdx.x; task < 64 * nc; task += blockDim.x) {
-      const int j = j0 + task % 64, cc = task / 64;
-      if (j >= beta) continue;
-      double a = 0.0;
-#pragma unroll 8
-      for (int k = 0; k < beta; ++k) a += SinvT[int64_t(k) * beta + j] * sT[k * 16 + cc];
-      v_out[int64_t(c0 + cc) * beta + j] = sX[j * 16 + cc] + a;
+    double a[4] = {0.0, 0.0, 0.0, 0.0};  // tasks tid, tid + 256, ... of (row, chain)
+    for (int k0 = 0; k0 < beta; k0 += 64) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = int(threadIdx.x) + u * kBlock;
+        const int kk = e >> 6, jj = e & 63;
+        const int k = min(k0 + kk, beta - 1), j = min(j0 + jj, beta - 1);
+        sS[e] = SinvT[int64_t(k) * beta + j];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int task = int(threadIdx.x) + u * kBlock;
+        const int jj = task & 63, cc = task >> 6;
+        if (cc >= nc) continue;
+        const int kn = min(64, beta - k0);
+        for (int kk = 0; kk < kn; ++kk) a[u] += sS[kk * 64 + jj] * sT[(k0 + kk) * 16 + cc];
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int task = int(threadIdx.x) + u * kBlock;
+      const int j = j0 + (task & 63), cc = task >> 6;
+      if (cc < nc && j < beta) v_out[int64_t(c0 + cc) * beta + j] = sX[j * 16 + cc] + a[u];
     }
     return;
   }
@@ -983,14 +1004,15 @@ hipError_t launch_lowrank(const Launch& L, const DevLevel& lv, void* theta, int 
 hipError_t launch_lowrank_fused(const Launch& L, const DevLevel& lv, void* theta, int dir,
                                 uint32_t word, int beta, const double* gisq, const double* gam,
                                 double* v_out) {
-  if (L.mcur == nullptr || lv.bsnap == nullptr || beta < 1 || beta > 512) return hipErrorInvalidValue;
+  if (L.mcur == nullptr || lv.bsnap == nullptr || beta < 1 || beta > 128) return hipErrorInvalidValue;
   if (v_out != nullptr && lv.SinvT == nullptr) return hipErrorInvalidValue;
   const int nsupp = lv.nsupp[dir];
   const int nrt = (nsupp + 63) / 64;             // blocks of 64 support rows
   const int nvb = v_out ? (beta + 63) / 64 : 0;  // blocks of 64 rows of v
   if (nrt + nvb == 0) return hipSuccess;
-  // LDS: t (and xi) of 16 chains, <= 128 KiB
-  const size_t shm = size_t(beta) * 16 * sizeof(double) * (v_out ? 2 : 1);
+  // LDS: t of 16 chains, with v also their xi and a 64 x 64 chunk of S^{-1}
+  // (<= 64 KiB for beta <= 128)
+  const size_t shm = (size_t(beta) * 16 * (v_out ? 2 : 1) + (v_out ? 64 * 64 : 0)) * sizeof(double);
   dim3 grid(unsigned(nrt + nvb), unsigned((L.nchains + 15) / 16));
   if (L.fp32)
     k_lowrank_fused_mfma<float><<<grid, kBlock, shm, L.stream>>>(

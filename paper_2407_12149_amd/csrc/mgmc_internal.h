@@ -194,7 +194,7 @@ hipError_t launch_lowrank(const Launch& L, const DevLevel& lv, void* theta, int 
 // The same correction for a level whose sweep just wrote its snapshot of B's
 // sites (lv.bsnap): one launch forms t = B^T theta - Gamma xi from the
 // snapshot in every block and applies theta -= G t on the matrix cores
-// (beta <= 512); with v_out it also writes v = xi + S^{-1} t.
+// (beta <= 128); with v_out it also writes v = xi + S^{-1} t.
 hipError_t launch_lowrank_fused(const Launch& L, const DevLevel& lv, void* theta, int dir,
                                 uint32_t word, int beta, const double* gisq, const double* gam,
                                 double* v_out);
