@@ -158,17 +158,30 @@ def test_bottom_levels_fused_or_per_level(fused):
     check_stepwise(prob, obs, 2, y=y, label=f"posterior 255^2 fused bottom {fused}", fused=fused)
 
 
-@pytest.mark.parametrize("mfma", [True, False])
-def test_low_rank_product_on_matrix_cores_or_vector(mfma):
-    """The low-rank G t product with the FP64 MFMA (ragged 16-chain tile with
-    19 chains, beta not a multiple of 4) or with vector FMA."""
+@pytest.mark.parametrize("form", [1, 2, 0])
+def test_low_rank_step_forms(form):
+    """The low-rank step (ragged 16-chain tile with 19 chains, beta not a
+    multiple of 4): 1 = one launch from the sweep's snapshot of the
+    observation sites with the FP64 MFMA product, 2 = separate B^T theta
+    launch and MFMA product, 0 = vector FMA product."""
     n = 127
     face = workloads.face_array(n, 2, workloads.fourier_log_field(2, nmodes=8, seed=6))
     prob, obs = make_problem(2, n, 4, 30.0, face=face, beta=7, gamma=1e-3, nchains=19)
     y = workloads.observed_values(7, seed=10)
     from paper_2407_12149_amd import mgmc
-    check_stepwise(prob, obs, 2, y=y, label=f"posterior 127^2 x 19 mfma {mfma}",
-                   options={mgmc.MGMC_OPT_LOWRANK_MFMA: int(mfma)})
+    check_stepwise(prob, obs, 2, y=y, label=f"posterior 127^2 x 19 low-rank form {form}",
+                   options={mgmc.MGMC_OPT_LOWRANK_MFMA: form})
+
+
+def test_low_rank_snapshot_with_lds_tiled_sweeps():
+    """The snapshot of the observation sites written by the LDS-tiled sweep
+    form (tile height 32) on every level, 70 observations across tiles."""
+    n = 255
+    face = workloads.face_array(n, 2, workloads.fourier_log_field(2, nmodes=8, seed=7))
+    prob, obs = make_problem(2, n, 5, 30.0, face=face, beta=70, gamma=1e-3, nchains=3)
+    y = workloads.observed_values(70, seed=11)
+    check_stepwise(prob, obs, 2, y=y, label="posterior 255^2 beta 70 tiled sweeps",
+                   levels=[None, [0, 0], [0, 0], [0, 0], [0, 0]])
 
 
 def test_per_level_kernel_forms():
