@@ -97,26 +97,29 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const T* __restrict__ coef,
   const int cb = int(blockIdx.y) * cpb;
   const int ce = min(nchains, cb + cpb);
   for (int c = cb; c < ce; ++c) {
-    const Block4 blk = philox10(pair, word | uint32_t(colour), m, 0u, seed, chain0 + c);
-    T z[2];
-    Gauss<T>::pair(blk, z[0], z[1]);
     T* th = theta + int64_t(c) * g.Np;
-    const T* fc = f ? f + int64_t(c) * fcs : nullptr;
+    // Both sites' neighbour loads are issued before the noise is drawn and
+    // without branches: a missing second site (past the row end) reads
+    // padding and ghost entries, which stay in bounds, and is not stored.
+    T s[2];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      if (k == 1 && !two) break;
       const int64_t i = ia + 2 * k;
-      T s = fc ? fc[i] : T(0);
+      s[k] = f ? f[int64_t(c) * fcs + i] : T(0);
       int b = 0;
 #pragma unroll
       for (int t = 0; t < S; ++t) {
         const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = DIM == 3 ? t / 9 - 1 : 0;
         const int nz = (dx != 0) + (dy != 0) + (dz != 0);
         if (nz == 0 || (CROSS && nz != 1)) continue;
-        s -= cf[k][b++] * th[i + poff(g, dx, dy, dz)];
+        s[k] -= cf[k][b++] * th[i + poff(g, dx, dy, dz)];
       }
-      th[i] = s * ivd[k] + z[k] * isd[k];
     }
+    const Block4 blk = philox10(pair, word | uint32_t(colour), m, 0u, seed, chain0 + c);
+    T z[2];
+    Gauss<T>::pair(blk, z[0], z[1]);
+    th[ia] = s[0] * ivd[0] + z[0] * isd[0];
+    if (two) th[ia + 2] = s[1] * ivd[1] + z[1] * isd[1];
   }
 }
 
@@ -172,19 +175,22 @@ __global__ __launch_bounds__(kBlock) void k_sweep_parity3d(const T* __restrict__
   const int cb = int(blockIdx.y) * cpb;
   const int ce = min(nchains, cb + cpb);
   for (int c = cb; c < ce; ++c) {
+    T* th = theta + int64_t(c) * g.Np;
+    // neighbour loads first and branch-free (a missing second site reads
+    // padding and ghost entries and is not stored), then the noise
+    T s[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int64_t i = ia + 2 * k;
+      s[k] = (f && fcs != 0) ? f[int64_t(c) * fcs + i] : rhs[k];
+#pragma unroll
+      for (int e = 0; e < 6; ++e) s[k] -= cf[k][e] * th[i + off[e]];
+    }
     const Block4 blk = philox10(pair, word | uint32_t(colour), m, 0u, seed, chain0 + c);
     T z[2];
     Gauss<T>::pair(blk, z[0], z[1]);
-    T* th = theta + int64_t(c) * g.Np;
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      if (k == 1 && !two) break;
-      const int64_t i = ia + 2 * k;
-      T s = (f && fcs != 0) ? f[int64_t(c) * fcs + i] : rhs[k];
-#pragma unroll
-      for (int e = 0; e < 6; ++e) s -= cf[k][e] * th[i + off[e]];
-      th[i] = s * ivd[k] + z[k] * isd[k];
-    }
+    th[ia] = s[0] * ivd[0] + z[0] * isd[0];
+    if (two) th[ia + 2] = s[1] * ivd[1] + z[1] * isd[1];
   }
 }
 
@@ -250,6 +256,8 @@ __global__ __launch_bounds__(kBlock) void k_residual(const T* __restrict__ coef,
   }
   const int cb = int(blockIdx.y) * cpb;
   const int ce = min(nchains, cb + cpb);
+  // two chains per trip, so the loads of the second overlap the first
+#pragma unroll 2
   for (int c = cb; c < ce; ++c) {
     const T* th = theta + int64_t(c) * g.Np;
     T acc = f ? f[int64_t(c) * fcs + ii] : T(0);
