@@ -612,10 +612,10 @@ __global__ void k_advance_m(int64_t* mcur) { *mcur += 1; }
 inline unsigned blocks_for(int64_t count) { return unsigned((count + kBlock - 1) / kBlock); }
 
 // Chains per thread for kernels that keep a site's stencil in registers
-// across chains: up to 8, halved while fewer than ~2048 blocks would remain.
+// across chains: up to 16, halved while fewer than ~2048 blocks would remain.
 inline int chain_group(int64_t blocks, int nchains) {
   int cpb = 1;
-  while (cpb < 8 && cpb < nchains && blocks * ((nchains + 2 * cpb - 1) / (2 * cpb)) >= 2048) cpb *= 2;
+  while (cpb < 16 && cpb < nchains && blocks * ((nchains + 2 * cpb - 1) / (2 * cpb)) >= 2048) cpb *= 2;
   return cpb;
 }
 

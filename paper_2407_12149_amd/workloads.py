@@ -127,6 +127,35 @@ def lognormal_faces_fft(n, dim, corr_len, variance, seed):
     return out
 
 
+def lognormal_faces_fft3(n, corr_len, variance, seed, box=1.5):
+    """3D face coefficients a = exp(g) of a stationary Gaussian field g with
+    squared-exponential covariance variance * exp(-|r|^2 / (2 corr_len^2)),
+    synthesised spectrally at the nodes (spacing h, periodic box of side
+    `box` > 1 + a few correlation lengths), with the face value between two
+    nodes exp((g_i + g_j) / 2).  Face arrays as in face_midpoints."""
+    import scipy.fft
+    h = 1.0 / (n + 1)
+    m = int(np.ceil(box / h))
+    rng = np.random.default_rng(seed)
+    k = np.fft.fftfreq(m, d=h) * 2.0 * np.pi
+    k2 = k[:, None, None] ** 2 + k[None, :, None] ** 2 + k[None, None, :] ** 2
+    # spectral density of the squared-exponential covariance in 3D
+    spec = variance * (2.0 * np.pi * corr_len ** 2) ** 1.5 * np.exp(-0.5 * corr_len ** 2 * k2)
+    del k2
+    side = m * h
+    amp = np.sqrt(spec / side ** 3) * float(m) ** 3
+    del spec
+    noise = rng.normal(size=(m, m, m)) + 1j * rng.normal(size=(m, m, m))
+    g = np.real(scipy.fft.ifftn(amp * noise, workers=8))[: n + 2, : n + 2, : n + 2]
+    del noise, amp
+    g = np.ascontiguousarray(g.transpose(2, 1, 0))  # index [z][y][x], node i at i h
+    inner = slice(1, n + 1)
+    ax = np.exp(0.5 * (g[inner, inner, : n + 1] + g[inner, inner, 1 : n + 2]))  # [z][y][x face]
+    ay = np.exp(0.5 * (g[inner, : n + 1, inner] + g[inner, 1 : n + 2, inner]))  # [z][y face][x]
+    az = np.exp(0.5 * (g[: n + 1, inner, inner] + g[1 : n + 2, inner, inner]))  # [z face][y][x]
+    return np.concatenate([ax.reshape(-1), ay.reshape(-1), az.reshape(-1)])
+
+
 # --------------------------------------------------------------------------
 # observations, data and quantity of interest
 # --------------------------------------------------------------------------
@@ -209,6 +238,17 @@ def config(name):
         return dict(name=name, dim=dim, n=n, levels=7, kappa2=1.0, corr_len=0.05, variance=2.0,
                     train_fields=2000, test_fields=200, field_seed0=1000, nchains=1,
                     nsamples=10000, burn_in=1000, seed=0, F=subcube_qoi(n, dim))
+    if name == "posterior255":
+        # full posterior at scale: 255^3, lognormal a (correlation length 0.1,
+        # variance 1), 256 sensors averaging 3^3 nodes, Gamma = 0.005^2 I,
+        # 64 chains, kappa = 10 as in the 2D posterior
+        n, dim, m = 255, 3, 256
+        face = lognormal_faces_fft3(n, 0.1, 1.0, seed=4)
+        ptr, idx, val = patch_sensors(n, dim, m, seed=5)
+        gamma = np.full(m, 0.005 ** 2)
+        return dict(name=name, dim=dim, n=n, levels=6, kappa2=100.0, face_coef=face,
+                    obs=(ptr, idx, val, gamma), y=observed_values(m, seed=6), nchains=64,
+                    nsamples=5000, seed=0, F=subcube_qoi(n, dim))
     if name == "batched512":
         # 512 prior chains of five shapes, kappa = 5, constant coefficient
         shapes = [(2, 127, 5, 103), (2, 255, 6, 103), (2, 511, 7, 102), (3, 63, 4, 102),
