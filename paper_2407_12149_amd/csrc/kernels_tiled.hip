@@ -307,18 +307,42 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
   const bool row_in = owner && y >= 1 && y <= n;
   // stencil of the four sites in registers (zero outside the grid)
   T cf[4][NB], ivd[4], isd[4], rhs[RHSC ? 1 : 4];
+  if (CROSS) {
+    // The 5-point operator is symmetric entry by entry (east of x is west of
+    // x + 1, north of y is south of y + 1), so only the west and south arrays
+    // are read: five west entries and the south entries of rows y and y + 1.
+    T wv[5], sv[4], nv[4];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const int x = 4 * q + 1 + k;
+      const bool in = row_in && x >= 1 && x <= n;
+      wv[k] = coef[int64_t(3) * g.Np + (in ? pidx(g, x, y, 0) : 0)];
+      if (k < 4) {
+        sv[k] = coef[int64_t(1) * g.Np + (in ? pidx(g, x, y, 0) : 0)];
+        nv[k] = coef[int64_t(1) * g.Np + ((in && y + 1 <= n) ? pidx(g, x, y + 1, 0) : 0)];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      cf[k][0] = sv[k];      // (0, -1)
+      cf[k][1] = wv[k];      // (-1, 0)
+      cf[k][2] = wv[k + 1];  // (+1, 0)
+      cf[k][3] = nv[k];      // (0, +1)
+    }
+  }
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int x = 4 * q + 1 + k;
     const bool in = row_in && x >= 1 && x <= n;
     const int64_t gi = in ? pidx(g, x, y, 0) : 0;
-    int b = 0;
+    if (!CROSS) {
+      int b = 0;
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const int dx = t % 3 - 1, dy = t / 3 - 1;
-      if (dx == 0 && dy == 0) continue;
-      if (CROSS && dx != 0 && dy != 0) continue;
-      cf[k][b++] = coef[int64_t(t) * g.Np + gi];
+      for (int t = 0; t < 9; ++t) {
+        const int dx = t % 3 - 1, dy = t / 3 - 1;
+        if (dx == 0 && dy == 0) continue;
+        cf[k][b++] = coef[int64_t(t) * g.Np + gi];
+      }
     }
     ivd[k] = invd[gi];
     isd[k] = isqd[gi];
@@ -374,6 +398,7 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
   // updates all of them between two barriers.  A step past the last chain
   // works on the last chain's data and stores nothing.
   for (int c0 = cb; c0 < ce; c0 += MC) {
+    const int tid = int(threadIdx.x);
     // Every load below is issued unconditionally: positions outside the grid
     // (or all of them when the input is zero) read offset 0 of the field,
     // which is padding and stays zero.  Without per-load branches the loaded
@@ -392,7 +417,7 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
       }
 #pragma unroll
       for (int k = 0; k < KP; ++k) {
-        const int e = int(threadIdx.x) + k * NT;
+        const int e = tid + k * NT;
         const int Jx = jx0 + e % CRX, Jy = jy0 + e / CRX;
         const bool ok = e < CRX * CRY && Jx >= 1 && Jx <= gc.n && Jy >= 1 && Jy <= gc.n;
         pv[mi][k] = psi[int64_t(c) * gc.Np + (ok ? pidx(gc, Jx, Jy, 0) : 0)];
@@ -400,7 +425,7 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
       const T* thi = theta_in + int64_t(c) * g.Np;
 #pragma unroll
       for (int k = 0; k < KF; ++k) {
-        const int idx = int(threadIdx.x) + k * NT;
+        const int idx = tid + k * NT;
         const int xx = ox + idx % RX, yy = oy + idx / RX;
         const bool ok = !zero_in && idx < RX * RY && xx >= 1 && xx <= n && yy >= 1 && yy <= n;
         fv[mi][k] = thi[ok ? pidx(g, xx, yy, 0) : 0];
@@ -423,7 +448,7 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
       for (int mi = 0; mi < MC; ++mi) {
 #pragma unroll
         for (int k = 0; k < KP; ++k) {
-          const int e = int(threadIdx.x) + k * NT;
+          const int e = tid + k * NT;
           if (e < CRX * CRY) spsi[mi][e] = pv[mi][k];
         }
       }
@@ -433,7 +458,7 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
     for (int mi = 0; mi < MC; ++mi) {
 #pragma unroll
       for (int k = 0; k < KF; ++k) {
-        const int idx = int(threadIdx.x) + k * NT;
+        const int idx = tid + k * NT;
         if (idx >= RX * RY) continue;
         const int xx = ox + idx % RX, yy = oy + idx / RX;
         T v = fv[mi][k];
