@@ -338,7 +338,8 @@ def main():
         "iact": tau,
         "setup_s": setup_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": measured_traffic(),
+                     "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": measured_traffic() if wl == "posterior1023" else None,
                      "kernel": "finest-level smoother sweep",
                      "launches_per_sweep": r64["launches_per_sweep"],
                      "avg_launch_us": r64["per_launch_s"] * 1e6,
