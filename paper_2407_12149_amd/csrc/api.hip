@@ -248,9 +248,25 @@ mgmc_status upload_level(mgmc_ctx* c, int l) {
     if ((s = c->upload(d.bptr, bptr)) != MGMC_OK) return s;
     if ((s = c->upload(d.bidx, bidx)) != MGMC_OK) return s;
     if ((s = c->upload(d.bval, bval)) != MGMC_OK) return s;
-    if (c->prob.dim == 2 && l >= 1 && d.bnnz > 0) {
-      // entries of B grouped by the 64 x TY tile holding their site, for
-      // each tile height of the 2D sweep forms
+    int64_t kmax = 0;
+    for (int j = 0; j < beta; ++j) kmax = std::max(kmax, bptr[j + 1] - bptr[j]);
+    const int bkp = kmax <= 8 ? 8 : kmax <= 16 ? 16 : kmax <= 32 ? 32 : 0;
+    if (c->prob.dim == 2 && l >= 1 && d.bnnz > 0 && bkp > 0) {
+      // fixed-width slots per column of B (zero padded)
+      d.bkp = bkp;
+      d.bslots = int64_t(beta) * bkp;
+      std::vector<int32_t> slot(size_t(d.bnnz)), pidx(size_t(beta) * bkp, 0);
+      std::vector<double> pval(size_t(beta) * bkp, 0.0);
+      for (int j = 0; j < beta; ++j)
+        for (int64_t e = bptr[j]; e < bptr[j + 1]; ++e) {
+          slot[size_t(e)] = int32_t(int64_t(j) * bkp + (e - bptr[j]));
+          pidx[size_t(slot[size_t(e)])] = bidx[size_t(e)];
+          pval[size_t(slot[size_t(e)])] = bval[size_t(e)];
+        }
+      if ((s = c->upload(d.bpidx, pidx)) != MGMC_OK) return s;
+      if ((s = c->upload(d.bpval, pval)) != MGMC_OK) return s;
+      // slots grouped by the 64 x TY tile holding their site, for each tile
+      // height of the 2D sweep forms
       const int tiles_x = (h.n + 63) / 64;
       for (int gi = 0; gi < 3; ++gi) {
         const int ty = mgmc::kSnapTY[d.cross ? 1 : 0][gi];
@@ -264,11 +280,12 @@ mgmc_status upload_level(mgmc_ctx* c, int l) {
         }
         for (int t = 0; t < tiles; ++t) tptr[t + 1] += tptr[t];
         std::vector<int32_t> fill(tptr.begin(), tptr.end() - 1);
-        for (int64_t e = 0; e < d.bnnz; ++e) tent[size_t(fill[tile_of[e]]++)] = int32_t(e);
+        for (int64_t e = 0; e < d.bnnz; ++e) tent[size_t(fill[tile_of[e]]++)] = slot[size_t(e)];
         if ((s = c->upload(d.bt_ptr[gi], tptr)) != MGMC_OK) return s;
         if ((s = c->upload(d.bt_ent[gi], tent)) != MGMC_OK) return s;
       }
-      if ((s = c->alloc(d.bsnap, size_t(nch) * d.bnnz)) != MGMC_OK) return s;
+      // zeroed by alloc; the padding slots are never written
+      if ((s = c->alloc(d.bsnap, size_t(nch) * size_t(d.bslots))) != MGMC_OK) return s;
     }
     std::vector<int32_t> brow, brcol;
     std::vector<int64_t> brptr(1, 0);

@@ -15,6 +15,7 @@
 #include <algorithm>
 
 #include "device_common.h"
+#include "device_lowrank.h"
 #include "device_rng.h"
 #include "mgmc_internal.h"
 
@@ -751,66 +752,33 @@ hipError_t launch_coarsest(const Launch& L, const DevLevel& lv0, const void* f0,
 
 typedef double mfma_d4 __attribute__((ext_vector_type(4)));
 
-// theta_r -= sum_j G_rj t_j for the block's 64 support rows and chains
-// c0 .. c0 + 15 on the matrix cores, with t staged in LDS as sT[beta][16]
-// (zero past the last chain).  Four wavefronts of 16 rows each accumulate
-// G (rows x beta) times T (beta x 16) with the FP64 16x16x4 MFMA: lane l
-// supplies A[l % 16][l / 16] and B[l / 16][l % 16] and receives
-// D[l / 16 + 4 v][l % 16] in register v.  G is read at clamped (valid)
-// indices without branches; rows past nsupp are computed but not stored,
-// and columns past beta meet zeros of T.
-template <typename T>
-struct MfmaRowsPrefetch {
-  double av[16];  // G^T entries of the first 64 columns
-  double th[4];   // this lane's theta values at its four result rows
-};
-
-// Issue the loads that do not depend on t (the first column chunk of G and
-// the theta values that lowrank_mfma_rows updates), so they are in flight
-// while t is being formed.
-template <typename T>
-__device__ __forceinline__ void lowrank_mfma_prefetch(MfmaRowsPrefetch<T>& pf,
-                                                      const T* __restrict__ theta, int64_t Np,
-                                                      int beta, int nsupp,
-                                                      const int32_t* __restrict__ supp,
-                                                      const double* __restrict__ GT, int c0,
-                                                      int nchains) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r0 = blockIdx.x * 64 + wave * 16;
-  const int ri = lane & 15, kk = lane >> 4;
-  const int rc = min(r0 + ri, nsupp - 1);
+// Products A T on the matrix cores for the 16 rows r0 .. r0 + 15 of one
+// wavefront, with A (nrows x beta) stored by columns, A[r][k] = AT[k * lda + r],
+// and T (beta x 16 chains) staged in LDS as sT[beta][16], zero past the last
+// chain.  The FP64 16x16x4 MFMA takes A[l % 16][l / 16] and B[l / 16][l % 16]
+// from lane l and returns D[l / 16 + 4 v][l % 16] in register v.  A is read
+// at clamped (valid) indices without branches: rows past nrows are computed
+// but not used, and columns past beta meet zeros of T.  mfma_cols_prefetch
+// issues the loads of the first 64 columns early, so they can be in flight
+// while T is being formed.
+__device__ __forceinline__ void mfma_cols_prefetch(double (&av)[16], const double* __restrict__ AT,
+                                                   int64_t lda, int nrows, int beta, int r0) {
+  const int lane = threadIdx.x & 63;
+  const int rc = min(r0 + (lane & 15), nrows - 1), kk = lane >> 4;
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int k = min(4 * u + kk, beta - 1);
-    pf.av[u] = GT[int64_t(k) * nsupp + rc];
-  }
-  const T* th = theta + int64_t(min(c0 + (lane & 15), nchains - 1)) * Np;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int rr = min(r0 + (lane >> 4) + 4 * v, nsupp - 1);
-    pf.th[v] = double(th[supp[rr]]);
+    av[u] = AT[int64_t(k) * lda + rc];
   }
 }
 
-// theta_r -= sum_j G_rj t_j for the block's 64 support rows and chains
-// c0 .. c0 + 15 on the matrix cores, with t staged in LDS as sT[beta][16]
-// (zero past the last chain) and the loads of lowrank_mfma_prefetch done.
-// Four wavefronts of 16 rows each accumulate G (rows x beta) times
-// T (beta x 16) with the FP64 16x16x4 MFMA: lane l supplies A[l % 16][l / 16]
-// and B[l / 16][l % 16] and receives D[l / 16 + 4 v][l % 16] in register v.
-// G is read at clamped (valid) indices without branches; rows past nsupp are
-// computed but not stored, and columns past beta meet zeros of T.
-template <typename T>
-__device__ __forceinline__ void lowrank_mfma_rows(const MfmaRowsPrefetch<T>& pf,
-                                                  T* __restrict__ theta, int64_t Np, int beta,
-                                                  int nsupp, const int32_t* __restrict__ supp,
-                                                  const double* __restrict__ GT,
-                                                  const double* __restrict__ sT, int c0,
-                                                  int nchains) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r0 = blockIdx.x * 64 + wave * 16;
+__device__ __forceinline__ mfma_d4 mfma_rows_product(const double (&av0)[16],
+                                                     const double* __restrict__ AT, int64_t lda,
+                                                     int nrows, int beta, int r0,
+                                                     const double* __restrict__ sT) {
+  const int lane = threadIdx.x & 63;
   const int ri = lane & 15, kk = lane >> 4;
-  const int rc = min(r0 + ri, nsupp - 1);
+  const int rc = min(r0 + ri, nrows - 1);
   mfma_d4 acc = {0.0, 0.0, 0.0, 0.0};
   // chunks of 64 columns: the 16 loads of a chunk are issued together
   for (int kc = 0; kc < beta; kc += 64) {
@@ -818,7 +786,7 @@ __device__ __forceinline__ void lowrank_mfma_rows(const MfmaRowsPrefetch<T>& pf,
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int k = min(kc + 4 * u + kk, beta - 1);
-      av[u] = kc == 0 ? pf.av[u] : GT[int64_t(k) * nsupp + rc];
+      av[u] = kc == 0 ? av0[u] : AT[int64_t(k) * lda + rc];
     }
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
@@ -827,6 +795,47 @@ __device__ __forceinline__ void lowrank_mfma_rows(const MfmaRowsPrefetch<T>& pf,
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], b, acc, 0, 0, 0);
     }
   }
+  return acc;
+}
+
+// theta_r -= sum_j G_rj t_j for the 64 support rows of row block rb (16 per
+// wavefront) and chains c0 .. c0 + 15, G given as GT[beta][nsupp].
+template <typename T>
+struct MfmaRowsPrefetch {
+  double av[16];  // G^T entries of the first 64 columns
+  double th[4];   // this lane's theta values at its four result rows
+};
+
+// The loads that do not depend on t: the first column chunk of G and the
+// theta values that lowrank_mfma_rows updates.
+template <typename T>
+__device__ __forceinline__ void lowrank_mfma_prefetch(MfmaRowsPrefetch<T>& pf,
+                                                      const T* __restrict__ theta, int64_t Np,
+                                                      int beta, int nsupp,
+                                                      const int32_t* __restrict__ supp,
+                                                      const double* __restrict__ GT, int c0,
+                                                      int nchains, int rb) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = rb * 64 + wave * 16;
+  mfma_cols_prefetch(pf.av, GT, nsupp, nsupp, beta, r0);
+  const T* th = theta + int64_t(min(c0 + (lane & 15), nchains - 1)) * Np;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int rr = min(r0 + (lane >> 4) + 4 * v, nsupp - 1);
+    pf.th[v] = double(th[supp[rr]]);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void lowrank_mfma_rows(const MfmaRowsPrefetch<T>& pf,
+                                                  T* __restrict__ theta, int64_t Np, int beta,
+                                                  int nsupp, const int32_t* __restrict__ supp,
+                                                  const double* __restrict__ GT,
+                                                  const double* __restrict__ sT, int c0,
+                                                  int nchains, int rb) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = rb * 64 + wave * 16;
+  const mfma_d4 acc = mfma_rows_product(pf.av, GT, nsupp, nsupp, beta, r0, sT);
   const int cc = lane & 15;
   if (c0 + cc >= nchains) return;
   T* th = theta + int64_t(c0 + cc) * Np;
@@ -838,105 +847,54 @@ __device__ __forceinline__ void lowrank_mfma_rows(const MfmaRowsPrefetch<T>& pf,
 }
 
 // The low-rank correction (Alg. 3) in one launch after a 2D sweep that wrote
-// its snapshot of B's sites (bsnap, [nchains][bnnz]).  Every block forms
+// its snapshot of B's sites (bsnap, [nchains][beta][KP] slots, zero padded,
+// with the weights bpval in the same slots).  Every block forms
 // xi = Gamma^{-1/2} zeta and t = B^T theta* - Gamma xi for its group of up to
 // 16 chains from the snapshot, which the correction does not modify, so the
-// blocks need no ordering among themselves.  Blocks x < nrt then apply
-// theta -= G t on their 64 support rows (lowrank_mfma_rows); with v_out,
-// blocks x >= nrt instead write 64 rows each of v = xi + S^{-1} t for the
-// coarse right-hand side.  The noise and the products per entry are those of
-// k_lowrank_prep; each row sum runs over its entries in order, eight loads
-// in flight at a time.
-template <typename T>
+// blocks need no ordering among themselves; each column sum takes its KP
+// slots in order with all loads issued together.  Blocks x < nrt then apply
+// theta -= G t on their 64 support rows; with v_out, blocks x >= nrt instead
+// write 64 rows each of v = xi + S^{-1} t for the coarse right-hand side,
+// the product S^{-1} t also on the matrix cores.  The noise and the products
+// per entry are those of k_lowrank_prep.
+template <typename T, int KP>
 __global__ __launch_bounds__(kBlock) void k_lowrank_fused_mfma(
     T* __restrict__ theta, int64_t Np, int beta, int nsupp, const int32_t* __restrict__ supp,
-    const double* __restrict__ GT, const int64_t* __restrict__ bptr,
-    const double* __restrict__ bval, const double* __restrict__ bsnap, int64_t bnnz,
-    const double* __restrict__ gisq, const double* __restrict__ gam,
-    const double* __restrict__ SinvT, double* __restrict__ v_out, int nrt, uint32_t word,
-    const int64_t* __restrict__ mcur, uint32_t seed, uint32_t chain0, int nchains) {
-  extern __shared__ double sT[];  // [beta][16] t; with v: [beta][16] xi, [64][64] S^{-1}
+    const double* __restrict__ GT, const double* __restrict__ bpval,
+    const double* __restrict__ bsnap, int64_t bslots, const double* __restrict__ gisq,
+    const double* __restrict__ gam, const double* __restrict__ SinvT, double* __restrict__ v_out,
+    int nrt, uint32_t word, const int64_t* __restrict__ mcur, uint32_t seed, uint32_t chain0,
+    int nchains) {
+  extern __shared__ double sT[];  // [beta][16] t; with v also [beta][16] xi
   double* sX = sT + beta * 16;
   const int c0 = blockIdx.y * 16;
   const int nc = min(16, nchains - c0);
   const bool vblock = int(blockIdx.x) >= nrt;
+  const int rv0 = (int(blockIdx.x) - nrt) * 64 + int(threadIdx.x >> 6) * 16;  // v blocks' rows
   const uint32_t m = uint32_t(*mcur);
   MfmaRowsPrefetch<T> pf;
-  if (!vblock) lowrank_mfma_prefetch<T>(pf, theta, Np, beta, nsupp, supp, GT, c0, nchains);
-  const int npairs = (beta + 1) / 2;
-  for (int task = threadIdx.x; task < npairs * 16; task += blockDim.x) {
-    const int p = task % npairs, cc = task / npairs;
-    double tv[2] = {0.0, 0.0}, xv[2] = {0.0, 0.0};
-    if (cc < nc) {
-      const int c = c0 + cc;
-      const Block4 blk = philox10(uint32_t(p), word, m, 1u, seed, chain0 + c);
-      double z[2];
-      Gauss<double>::pair(blk, z[0], z[1]);
-      const double* sn = bsnap + int64_t(c) * bnnz;
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int j = min(2 * p + h, beta - 1);
-        const int64_t e0 = bptr[j], e1 = bptr[j + 1];
-        double w = 0.0;
-        for (int64_t e = e0; e < e1; e += 8) {
-          double pr[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int64_t ec = min(e + u, e1 - 1);
-            pr[u] = bval[ec] * sn[ec];
-          }
-#pragma unroll
-          for (int u = 0; u < 8; ++u)
-            if (e + u < e1) w += pr[u];
-        }
-        xv[h] = z[h] * gisq[j];
-        tv[h] = w - gam[j] * xv[h];
-      }
-    }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int j = 2 * p + h;
-      if (j < beta) {
-        sT[j * 16 + cc] = tv[h];
-        if (vblock) sX[j * 16 + cc] = xv[h];
-      }
-    }
-  }
+  if (vblock)
+    mfma_cols_prefetch(pf.av, SinvT, beta, beta, beta, rv0);
+  else
+    lowrank_mfma_prefetch<T>(pf, theta, Np, beta, nsupp, supp, GT, c0, nchains, blockIdx.x);
+  lowrank_t_xi<KP>(bpval, bsnap, bslots, beta, gisq, gam, word, m, seed, chain0, c0, nc, 16,
+                   [&](int j, int cc, double t, double xi) {
+                     sT[j * 16 + cc] = t;
+                     if (vblock) sX[j * 16 + cc] = xi;
+                   });
   __syncthreads();
   if (vblock) {
-    // rows j0 .. j0 + 63 of S^{-1} t, S^{-1} staged through LDS in 64 x 64
-    // chunks (all loads of a chunk in flight together)
-    double* sS = sX + beta * 16;  // [64][64]
-    const int j0 = (int(blockIdx.x) - nrt) * 64;
-    double a[4] = {0.0, 0.0, 0.0, 0.0};  // tasks tid, tid + 256, ... of (row, chain)
-    for (int k0 = 0; k0 < beta; k0 += 64) {
+    const mfma_d4 acc = mfma_rows_product(pf.av, SinvT, beta, beta, beta, rv0, sT);
+    const int lane = threadIdx.x & 63, cc = lane & 15;
+    if (cc >= nc) return;
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int e = int(threadIdx.x) + u * kBlock;
-        const int kk = e >> 6, jj = e & 63;
-        const int k = min(k0 + kk, beta - 1), j = min(j0 + jj, beta - 1);
-        sS[e] = SinvT[int64_t(k) * beta + j];
-      }
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int task = int(threadIdx.x) + u * kBlock;
-        const int jj = task & 63, cc = task >> 6;
-        if (cc >= nc) continue;
-        const int kn = min(64, beta - k0);
-        for (int kk = 0; kk < kn; ++kk) a[u] += sS[kk * 64 + jj] * sT[(k0 + kk) * 16 + cc];
-      }
-      __syncthreads();
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int task = int(threadIdx.x) + u * kBlock;
-      const int j = j0 + (task & 63), cc = task >> 6;
-      if (cc < nc && j < beta) v_out[int64_t(c0 + cc) * beta + j] = sX[j * 16 + cc] + a[u];
+    for (int v = 0; v < 4; ++v) {
+      const int j = rv0 + (lane >> 4) + 4 * v;
+      if (j < beta) v_out[int64_t(c0 + cc) * beta + j] = sX[j * 16 + cc] + acc[v];
     }
     return;
   }
-  lowrank_mfma_rows<T>(pf, theta, Np, beta, nsupp, supp, GT, sT, c0, nchains);
+  lowrank_mfma_rows<T>(pf, theta, Np, beta, nsupp, supp, GT, sT, c0, nchains, blockIdx.x);
 }
 
 // The same product on the matrix cores (lowrank_mfma_rows): a block updates
@@ -951,7 +909,7 @@ __global__ __launch_bounds__(kBlock) void k_lowrank_apply_mfma(T* __restrict__ t
   extern __shared__ double sT[];  // [beta][16], zero past the last chain
   const int c0 = blockIdx.y * 16;
   MfmaRowsPrefetch<T> pf;
-  lowrank_mfma_prefetch<T>(pf, theta, Np, beta, nsupp, supp, GT, c0, nchains);
+  lowrank_mfma_prefetch<T>(pf, theta, Np, beta, nsupp, supp, GT, c0, nchains, blockIdx.x);
   // staged four entries per thread at a time with branch-free loads
   for (int e0 = 0; e0 < beta * 16; e0 += 4 * int(blockDim.x)) {
     double tv[4];
@@ -968,7 +926,7 @@ __global__ __launch_bounds__(kBlock) void k_lowrank_apply_mfma(T* __restrict__ t
     }
   }
   __syncthreads();
-  lowrank_mfma_rows<T>(pf, theta, Np, beta, nsupp, supp, GT, sT, c0, nchains);
+  lowrank_mfma_rows<T>(pf, theta, Np, beta, nsupp, supp, GT, sT, c0, nchains, blockIdx.x);
 }
 
 hipError_t launch_lowrank(const Launch& L, const DevLevel& lv, void* theta, int dir, uint32_t word,
@@ -1013,23 +971,32 @@ hipError_t launch_lowrank_fused(const Launch& L, const DevLevel& lv, void* theta
                                 uint32_t word, int beta, const double* gisq, const double* gam,
                                 double* v_out) {
   if (L.mcur == nullptr || lv.bsnap == nullptr || beta < 1 || beta > 128) return hipErrorInvalidValue;
+  if (lv.bslots != int64_t(beta) * lv.bkp) return hipErrorInvalidValue;
   if (v_out != nullptr && lv.SinvT == nullptr) return hipErrorInvalidValue;
   const int nsupp = lv.nsupp[dir];
   const int nrt = (nsupp + 63) / 64;             // blocks of 64 support rows
   const int nvb = v_out ? (beta + 63) / 64 : 0;  // blocks of 64 rows of v
   if (nrt + nvb == 0) return hipSuccess;
-  // LDS: t of 16 chains, with v also their xi and a 64 x 64 chunk of S^{-1}
-  // (<= 64 KiB for beta <= 128)
-  const size_t shm = (size_t(beta) * 16 * (v_out ? 2 : 1) + (v_out ? 64 * 64 : 0)) * sizeof(double);
+  // LDS: t of 16 chains, with v also their xi (<= 32 KiB for beta <= 128)
+  const size_t shm = size_t(beta) * 16 * (v_out ? 2 : 1) * sizeof(double);
   dim3 grid(unsigned(nrt + nvb), unsigned((L.nchains + 15) / 16));
+#define MGMC_LR_FUSED(T, KP)                                                                      \
+  k_lowrank_fused_mfma<T, KP><<<grid, kBlock, shm, L.stream>>>(                                   \
+      (T*)theta, lv.g.Np, beta, nsupp, lv.supp[dir], lv.GT[dir], lv.bpval, lv.bsnap, lv.bslots,   \
+      gisq, gam, lv.SinvT, v_out, nrt, word, L.mcur, L.seed, L.chain0, L.nchains)
+#define MGMC_LR_FUSED_KP(T)                  \
+  do {                                       \
+    if (lv.bkp == 8) MGMC_LR_FUSED(T, 8);    \
+    else if (lv.bkp == 16) MGMC_LR_FUSED(T, 16); \
+    else if (lv.bkp == 32) MGMC_LR_FUSED(T, 32); \
+    else return hipErrorInvalidValue;        \
+  } while (0)
   if (L.fp32)
-    k_lowrank_fused_mfma<float><<<grid, kBlock, shm, L.stream>>>(
-        (float*)theta, lv.g.Np, beta, nsupp, lv.supp[dir], lv.GT[dir], lv.bptr, lv.bval, lv.bsnap,
-        lv.bnnz, gisq, gam, lv.SinvT, v_out, nrt, word, L.mcur, L.seed, L.chain0, L.nchains);
+    MGMC_LR_FUSED_KP(float);
   else
-    k_lowrank_fused_mfma<double><<<grid, kBlock, shm, L.stream>>>(
-        (double*)theta, lv.g.Np, beta, nsupp, lv.supp[dir], lv.GT[dir], lv.bptr, lv.bval, lv.bsnap,
-        lv.bnnz, gisq, gam, lv.SinvT, v_out, nrt, word, L.mcur, L.seed, L.chain0, L.nchains);
+    MGMC_LR_FUSED_KP(double);
+#undef MGMC_LR_FUSED_KP
+#undef MGMC_LR_FUSED
   return hipGetLastError();
 }
 

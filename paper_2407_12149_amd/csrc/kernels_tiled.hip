@@ -687,16 +687,16 @@ void fill_bm_table(double* t) {
   }
 }
 
-// The snapshot of B's sites for the fused low-rank step, in the entry
-// lists of tile height index gi.
+// The snapshot of B's sites for the fused low-rank step (fixed-width slots
+// per column of B), in the slot lists of tile height index gi.
 static BSnap make_snap(const DevLevel& lv, int gi, bool snap) {
   BSnap bs;
   if (!snap) return bs;
   bs.ptr = lv.bt_ptr[gi];
   bs.ent = lv.bt_ent[gi];
-  bs.idx = lv.bidx;
+  bs.idx = lv.bpidx;
   bs.snap = lv.bsnap;
-  bs.nnz = lv.bnnz;
+  bs.nnz = lv.bslots;
   return bs;
 }
 

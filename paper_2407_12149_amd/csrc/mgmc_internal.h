@@ -50,12 +50,18 @@ struct DevLevel {
   double* GT[2] = {nullptr, nullptr};      // [beta][nsupp], G = C S^{-1}
   double* SinvT = nullptr;                 // [beta][beta], S^{-1} of the forward sweep, transposed
   // B^T theta without a separate pass over theta (2D one-launch sweeps): the
-  // sweep kernels copy the swept values at B's sites into bsnap
-  // ([nchains][bnnz], entry order of bidx); bt_ptr / bt_ent list the entries
-  // whose site lies in each 64 x TY tile, for the tile heights of the three
-  // 2D sweep forms (kSnapTY).
+  // sweep kernels copy the swept values at B's sites into bsnap.  Its layout
+  // gives every column of B the same number bkp (8, 16 or 32) of slots:
+  // [nchains][beta][bkp], column j's entries in the order of bidx, then
+  // zeros, which stay zero, as do the matching bpval weights.  bt_ptr /
+  // bt_ent list the slots whose site lies in each 64 x TY tile, for the tile
+  // heights of the three 2D sweep forms (kSnapTY).
+  int bkp = 0;
+  int64_t bslots = 0;                                // beta * bkp
+  double* bpval = nullptr;                           // [beta][bkp] weights, zero padded
+  int32_t* bpidx = nullptr;                          // [beta][bkp] padded sites (0 on padding)
   int32_t* bt_ptr[3] = {nullptr, nullptr, nullptr};  // [tiles + 1]
-  int32_t* bt_ent[3] = {nullptr, nullptr, nullptr};  // [bnnz]
+  int32_t* bt_ent[3] = {nullptr, nullptr, nullptr};  // [bnnz] slots
   double* bsnap = nullptr;
 };
 
@@ -67,10 +73,10 @@ constexpr int kSnapTY[2][3] = {{32, 8, 22}, {32, 12, 26}};
 // Kernel argument: where a 2D sweep writes the snapshot of B's sites.
 struct BSnap {
   const int32_t* ptr = nullptr;  // bt_ptr of the sweep's tile height
-  const int32_t* ent = nullptr;
-  const int32_t* idx = nullptr;  // bidx
+  const int32_t* ent = nullptr;  // slots
+  const int32_t* idx = nullptr;  // bpidx
   double* snap = nullptr;        // null: no snapshot
-  int64_t nnz = 0;
+  int64_t nnz = 0;               // slots per chain (beta * bkp)
 };
 
 // The low-rank part of the restricted residual, B_{l-1} v with

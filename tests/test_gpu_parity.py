@@ -223,6 +223,18 @@ def test_user_prolongation_weights(tiled):
     check_stepwise(prob, obs, 4, label="user P 63^2", tiled=tiled)
 
 
+def test_user_prolongation_weights_posterior():
+    """User weights on the finest transfer with observations (the low-rank
+    term of the restricted right-hand side through the user weights)."""
+    n = 63
+    nc = 31
+    rng = np.random.default_rng(4)
+    w = rng.uniform(0.2, 1.0, size=(nc * nc, 9))
+    prob, obs = make_problem(2, n, 3, 50.0, beta=5, gamma=1e-3, nchains=3, prolong_w=w.reshape(-1))
+    y = workloads.observed_values(5, seed=12)
+    check_stepwise(prob, obs, 3, y=y, label="user P 63^2 posterior")
+
+
 def test_more_sweeps_and_rhs():
     n = 31
     rng = np.random.default_rng(0)
