@@ -535,6 +535,11 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return sh[0];
 }
 
+// Per chain and block, the sum of F_i theta_i over the block's range of
+// sites, in site order per thread.  The weights of a batch of 16 sites per
+// thread are loaded first; a site with F_i = 0 then reads offset 0 of the
+// field (padding, zero) instead of theta_i, so that a QoI supported on part
+// of the domain reads only that part of the state.
 template <typename T, int DIM>
 __global__ __launch_bounds__(kBlock) void k_qoi_partial(const T* __restrict__ theta, Geom g,
                                                         int64_t N, const double* __restrict__ F,
@@ -546,11 +551,25 @@ __global__ __launch_bounds__(kBlock) void k_qoi_partial(const T* __restrict__ th
   const T* th = theta + int64_t(c) * g.Np;
   double acc = 0.0;
   const int n = g.n;
-  for (int64_t lin = lo + threadIdx.x; lin < hi; lin += blockDim.x) {
-    const int l32 = int(lin);  // N < 2^31 (checked at set-up)
-    const int i1 = 1 + l32 % n, r = l32 / n;
-    const int i2 = 1 + (DIM == 3 ? r % n : r), i3 = DIM == 3 ? 1 + r / n : 0;
-    acc += F[lin] * double(th[pidx(g, i1, i2, i3)]);
+  constexpr int KB = 16;
+  for (int64_t l0 = lo + threadIdx.x; l0 < hi; l0 += KB * blockDim.x) {
+    double fv[KB];
+#pragma unroll
+    for (int u = 0; u < KB; ++u) {
+      const int64_t lin = l0 + int64_t(u) * blockDim.x;
+      fv[u] = F[lin < hi ? lin : lo];
+      if (lin >= hi) fv[u] = 0.0;
+    }
+    double tv[KB];
+#pragma unroll
+    for (int u = 0; u < KB; ++u) {
+      const int l32 = int(l0 + int64_t(u) * blockDim.x);  // N < 2^31 (checked at set-up)
+      const int i1 = 1 + l32 % n, r = l32 / n;
+      const int i2 = 1 + (DIM == 3 ? r % n : r), i3 = DIM == 3 ? 1 + r / n : 0;
+      tv[u] = double(th[fv[u] != 0.0 ? pidx(g, i1, i2, i3) : 0]);
+    }
+#pragma unroll
+    for (int u = 0; u < KB; ++u) acc += fv[u] * tv[u];
   }
   const double s = block_sum(acc, sh);
   if (threadIdx.x == 0) partial[int64_t(c) * nb + b] = s;
