@@ -144,7 +144,9 @@ mgmc_status mgmc_set_graph(mgmc_ctx* ctx, int32_t enabled);
  *     stencil through LDS per chain, 1 keeps each thread's stencil in
  *     registers across colours and chains (256 threads per block), 2 the
  *     same with 512 threads per block (taller tiles), 3 (default) chooses
- *     per level.
+ *     per level, 4 is form 1 with each chain's state tile copied from
+ *     memory into LDS by DMA while the previous chain's colour passes run
+ *     (5-point levels; 9-point levels take form 1).
  *   MGMC_OPT_CHAINS_PER_BLOCK: chains processed by one block of the 2D
  *     sweep; 0 (default) chooses from the grid size and precision.
  *   MGMC_OPT_COARSE_FUSED: 1 runs the levels with at most 63 nodes per axis

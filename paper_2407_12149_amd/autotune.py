@@ -2,7 +2,8 @@
 
 For every level that runs smoother sweeps (levels >= 1) it searches the
 kernel form (LDS tiles, or register-held stencil with 256 or 512 threads per
-block) and the number of chains processed per block, by coordinate descent
+block, and on the finest, 5-point level also the form whose state tiles come
+into LDS by DMA) and the number of chains processed per block, by coordinate descent
 from the finest level down: each level's candidates are timed with the
 library's own update timer while the other levels keep their current best.
 It then tries the bottom levels as one launch.  Results are cached in a JSON
@@ -13,6 +14,7 @@ import os
 from . import mgmc
 
 CANDIDATE_VARIANTS = (1, 2, 0)
+FINEST_VARIANTS = (4,)  # LDS DMA state tiles (5-point level only)
 CANDIDATE_CPB = (0, 1, 2, 4, 8, 16)
 
 
@@ -59,7 +61,7 @@ def autotune(sampler, cache_path=None, updates=3, verbose=False):
         ms_best = _time(sampler, updates)
         for l in range(nlev - 1, 0, -1):
             choice = None
-            for v in CANDIDATE_VARIANTS:
+            for v in CANDIDATE_VARIANTS + (FINEST_VARIANTS if l == nlev - 1 else ()):
                 for c in CANDIDATE_CPB:
                     if c > sampler.nchains or (v == 0 and c != 0):
                         continue

@@ -383,14 +383,14 @@ hipError_t sweep2d(mgmc_ctx* c, int l, const void* in, void* out, int zero_in, c
   // blocks; the automatic choice takes 512 threads for FP64 four-colour
   // sweeps with the fused prolongation (register pressure), else 256
   const bool auto512 = !c->L.fp32 && !lv.cross && coarse != nullptr;
-  const int variant = (sv == 2 || (sv == 3 && auto512)) ? 1 : 0;
+  const int variant = (sv == 2 || (sv == 3 && auto512)) ? 1 : (sv == 4 ? 2 : 0);
   int cpb = c->lvl_cpb[l] >= 0 ? c->lvl_cpb[l] : c->sweep_cpb;
   if (cpb <= 0) {
     // each block reuses its stencil registers for a group of up to 8 chains
     // (reloading the stencil per chain costs more than the state traffic),
     // as long as at least 512 blocks remain to fill the device
     const int nch = c->L.nchains;
-    const int tys = lv.cross ? (variant ? 26 : 12) : (variant ? 22 : 8);
+    const int tys = lv.cross ? (variant == 1 ? 26 : 12) : (variant == 1 ? 22 : 8);
     const int64_t tiles = int64_t((lv.g.n + 63) / 64) * ((lv.g.n + tys - 1) / tys);
     cpb = std::min(nch, 8);
     while (cpb > 1 && tiles * ((nch + cpb - 1) / cpb) < 512) cpb /= 2;
@@ -792,7 +792,7 @@ mgmc_status mgmc_set_option(mgmc_ctx* c, int32_t option, int64_t value) {
       c->tiled = value != 0;
       return MGMC_OK;
     case MGMC_OPT_SWEEP_VARIANT:
-      if (value < 0 || value > 3) return fail(MGMC_EINVAL, "sweep variant must be 0, 1, 2 or 3");
+      if (value < 0 || value > 4) return fail(MGMC_EINVAL, "sweep variant must be 0 .. 4");
       c->sweep_variant = int(value);
       return MGMC_OK;
     case MGMC_OPT_CHAINS_PER_BLOCK:
@@ -816,7 +816,7 @@ mgmc_status mgmc_set_level_option(mgmc_ctx* c, int32_t level, int32_t option, in
   if (level < 0 || level >= c->levels) return fail(MGMC_EINVAL, "level out of range");
   switch (option) {
     case MGMC_OPT_SWEEP_VARIANT:
-      if (value < -1 || value > 3) return fail(MGMC_EINVAL, "sweep variant must be -1, 0, 1, 2 or 3");
+      if (value < -1 || value > 4) return fail(MGMC_EINVAL, "sweep variant must be -1 .. 4");
       c->lvl_variant[level] = int(value);
       return MGMC_OK;
     case MGMC_OPT_CHAINS_PER_BLOCK:

@@ -79,6 +79,24 @@ __device__ __forceinline__ T prolong_lds(const T* __restrict__ sp, int cw, int j
                                wP, x, y);
 }
 
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS
+// operations, not for outstanding vector-memory operations, so LDS DMA
+// copies into another buffer stay in flight across it.  (A fenced
+// __syncthreads would wait for them, the DMA writing LDS.)  The memory
+// clobber keeps the compiler from moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// 16 bytes per lane from memory into LDS (lane l of the wavefront fills
+// bytes 16 l .. 16 l + 15 after dst, dst the same in every lane); the copy
+// completes asynchronously, tracked by the vector-memory counter.
+__device__ __forceinline__ void lds_dma16(const void* src, void* dst) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0);
+#endif
+}
+
 // LDS layout of a tile row: four sub-rows by x mod 4, each of odd length W,
 // so the lanes of a wavefront (pairs four sites apart, the same x mod 4)
 // read consecutive words and neighbour reads are free of bank conflicts.
@@ -255,7 +273,14 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d_tiled(
 // contiguous loads, and reuses them for every colour pass and every chain of
 // the block; only the states go through LDS.  Rows cover the tile plus
 // NPASS-1 halo rows, segments the tile plus one segment either side.
-template <typename T, int NPASS, bool PROLONG, bool USERP, int TYS, int NT, int MC>
+//
+// With DMA (5-point levels) the state region and coarse patch of each chain
+// travel from memory straight into an LDS staging buffer (global_load_lds,
+// 16 contiguous bytes per lane), one of two: the next chain's copy is issued
+// when the current chain starts its colour passes, so it is in flight while
+// they run, and costs no registers.  Each chain then moves its staging into
+// the tile layout, adding the prolongation on the way.
+template <typename T, int NPASS, bool PROLONG, bool USERP, int TYS, int NT, int MC, bool DMA>
 __global__ __launch_bounds__(NT) void k_sweep2d_seg(
     const T* __restrict__ coef, const T* __restrict__ invd, const T* __restrict__ isqd,
     const T* __restrict__ theta_in, T* __restrict__ theta_out, int zero_in,
@@ -276,11 +301,24 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
   static_assert(SY % 2 == 0, "owner rows must split evenly by parity");
   static_assert(GA + HALF * SX <= NT, "block too small for the segment grid");
   using Z = Swz<RX>;
-  __shared__ T sh[MC][RY * Z::RS];
+  __shared__ T sh[DMA ? 1 : MC][DMA ? 1 : RY * Z::RS];
   // coarse patch under the tile region for the fused prolongation
   constexpr int CRX = RX / 2 + 2, CRY = RY / 2 + 2;
   constexpr int KP = PROLONG ? (CRX * CRY + NT - 1) / NT : 0;
-  __shared__ T spsi[MC][PROLONG ? CRY * CRX : 1];
+  __shared__ T spsi[DMA ? 1 : MC][PROLONG && !DMA ? CRY * CRX : 1];
+  // DMA staging (two buffers per array): rows of the region as they lie in
+  // memory, in 16-byte chunks from the aligned element SH0 places left of
+  // the region's first column (each region row starts 2 elements past a
+  // 16-byte boundary of the padded layout)
+  constexpr int CH = 16 / int(sizeof(T));  // elements per chunk
+  constexpr int SH0 = 2 % CH;
+  constexpr int NCT = (RX + SH0 + CH - 1) / CH, NCP = (CRX + SH0 + CH - 1) / CH;  // chunks per row
+  constexpr int RST = NCT * CH, RSP = NCP * CH;                                 // row pitches
+  __shared__ __attribute__((aligned(16))) T stA[DMA ? RY * RST : 1], stB[DMA ? RY * RST : 1];
+  __shared__ T shT[DMA ? RY * Z::RS : 1];  // the tile in layout Z
+  __shared__ __attribute__((aligned(16))) T spA[DMA && PROLONG ? CRY * RSP : 1],
+      spB[DMA && PROLONG ? CRY * RSP : 1];
+  static_assert(!DMA || (MC == 1 && CROSS), "LDS DMA tiles: 5-point levels, one chain per step");
   // double precision draws its normals with the table-driven Box-Muller
   constexpr bool TAB = sizeof(T) == 8;
   __shared__ double stab[TAB ? kBmTable : 1];
@@ -373,7 +411,6 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
     pslot[0] = backward ? NPASS - 1 - pos0 : pos0;
     pslot[1] = backward ? NPASS - 1 - pos1 : pos1;
   }
-  constexpr int KF = (RX * RY + NT - 1) / NT;  // tile elements loaded per thread
   constexpr bool HOIST = CROSS || !PROLONG || sizeof(T) == 4;
   const int cb = int(blockIdx.y) * cpb;
   const int ce = min(nchains, cb + cpb);
@@ -394,6 +431,147 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
       Gauss<T>::pair(blk, z0, z1);
     }
   };
+  // colour pass p of one chain on the LDS tile s: the thread's sites of
+  // that colour (z0, z1: their normals; rcv: the chain's right-hand side on
+  // 9-point levels)
+  auto pass_update = [&](int p, T* s, T z0, T z1, const T* rcv) __attribute__((always_inline)) {
+    const int hp = NPASS - 1 - p;
+    const int colour = pass_colour(p);
+    const int xpar = colour & 1;
+    const int k0 = xpar ? 0 : 1;  // offset of the colour's first site in the segment
+    const int xlo = max(1, tx0 - hp), xhi = min(n, tx0 + TX - 1 + hp);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk) {  // resolve the site index at compile time
+        if (kk != k0) continue;
+        const int k = kk + 2 * j;
+        const int x = 4 * q + 1 + k;
+        if (x < xlo || x > xhi) continue;
+        const int lx = x - ox;
+        // lx = x - tx0 + H with x = 4 q + 1 + k and tx0 = 1 (mod 4), so the
+        // sub-row lx & 3 is known at compile time (constant LDS offsets)
+        const int sxm = (k + H) & 3;
+        const int li = (y - oy) * Z::RS + sxm * Z::W + (lx >> 2);
+        const int oe = Z::east(sxm), ow = Z::west(sxm);
+        T sum = RHSC ? rcv[k] : rhs[RHSC ? 0 : k];
+        int b = 0;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+          const int dx = t % 3 - 1, dy = t / 3 - 1;
+          if (dx == 0 && dy == 0) continue;
+          if (CROSS && dx != 0 && dy != 0) continue;
+          const int o = dy * Z::RS + (dx < 0 ? ow : (dx > 0 ? oe : 0));
+          sum -= cf[k][b++] * s[li + o];
+        }
+        // one explicit contraction, the same in every form that inlines this
+        s[li] = fma(sum, ivd[k], (j == 0 ? z0 : z1) * isd[k]);
+      }
+    }
+  };
+  // The tile's snapshot slots (the same for every chain): thread t keeps
+  // slot b0 + t and its LDS position, so that no chain loads the lists
+  // again; slots past b0 + NT (rare) are looked up per chain.
+  int snap_slot = -1, snap_pos = 0, snap_b0 = 0, snap_b1 = 0;
+  if (bs.snap) {
+    snap_b0 = bs.ptr[blockIdx.x];
+    snap_b1 = bs.ptr[blockIdx.x + 1];
+    if (snap_b0 + int(threadIdx.x) < snap_b1) {
+      snap_slot = bs.ent[snap_b0 + int(threadIdx.x)];
+      const int site = bs.idx[snap_slot];
+      snap_pos = Z::pos(site % g.px - 3 - ox, site / g.px - oy);
+    }
+  }
+  // snapshot of B's sites and the tile's output of chain c from LDS tile s
+  auto finish_chain = [&](int c, const T* s) __attribute__((always_inline)) {
+    if (snap_slot >= 0) bs.snap[int64_t(c) * bs.nnz + snap_slot] = double(s[snap_pos]);
+    for (int i = snap_b0 + NT + int(threadIdx.x); i < snap_b1; i += NT) {
+      const int e = bs.ent[i];
+      const int site = bs.idx[e];
+      bs.snap[int64_t(c) * bs.nnz + e] = double(s[Z::pos(site % g.px - 3 - ox, site / g.px - oy)]);
+    }
+    if (row_in && sx >= 1 && sx <= TX / 4 && y >= ty0 && y <= ty0 + TYS - 1) {
+      T* tho = theta_out + int64_t(c) * g.Np;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int x = 4 * q + 1 + k;
+        if (x <= n) tho[pidx(g, x, y, 0)] = s[Z::pos(x - ox, y - oy)];
+      }
+    }
+  };
+  constexpr int KF = (RX * RY + NT - 1) / NT;  // tile elements per thread
+  if constexpr (DMA) {
+    const int tid = int(threadIdx.x);
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    // LDS DMA of chain c's state region into dst (and coarse patch into
+    // dsp), one 16-byte chunk per lane: instruction k fills chunks
+    // 64 k .. 64 k + 63 of the staging buffer, row by row.  A chunk of a row
+    // outside the grid, or starting right of it, reads offset 0 of the field
+    // (padding, zero); other chunks read memory as it lies, where the
+    // columns outside the grid are ghost entries (zero).
+    auto dma = [&](int c, T* dst, T* dsp) __attribute__((always_inline)) {
+      const T* thi = theta_in + int64_t(c) * g.Np;
+      for (int k = wave; k < (RY * NCT + 63) / 64; k += NT / 64) {
+        const int d = k * 64 + lane, ly = d / NCT, xf = ox - SH0 + (d % NCT) * CH;
+        const int yy = oy + ly;
+        const bool ok = !zero_in && d < RY * NCT && yy >= 1 && yy <= n && xf <= n;
+        if (d < RY * NCT)
+          lds_dma16(thi + (ok ? pidx(g, xf, yy, 0) : 0), dst + k * 64 * CH);
+      }
+      if (PROLONG) {
+        const T* ps = psi + int64_t(c) * gc.Np;
+        for (int k = wave; k < (CRY * NCP + 63) / 64; k += NT / 64) {
+          const int d = k * 64 + lane, r = d / NCP, jf = jx0 - SH0 + (d % NCP) * CH;
+          const int Jy = jy0 + r;
+          const bool ok = d < CRY * NCP && Jy >= 1 && Jy <= gc.n && jf <= gc.n;
+          if (d < CRY * NCP)
+            lds_dma16(ps + (ok ? pidx(gc, jf, Jy, 0) : 0), dsp + k * 64 * CH);
+        }
+      }
+    };
+    auto chain = [&](int c, const T* cst, const T* csp, T* nst, T* nsp) __attribute__((always_inline)) {
+      // this chain's staging has landed (and the previous chain's stores are done)
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      // staging -> tile layout Z, with the prolongation added
+#pragma unroll
+      for (int k = 0; k < KF; ++k) {
+        const int idx = tid + k * NT;
+        if (idx >= RX * RY) continue;
+        const int lx = idx % RX, ly = idx / RX;
+        T v = cst[ly * RST + SH0 + lx];
+        const int xx = ox + lx, yy = oy + ly;
+        if (PROLONG && xx >= 1 && xx <= n && yy >= 1 && yy <= n)
+          v += prolong_lds<T, USERP>(csp + SH0, RSP, jx0, jy0, gc, wP, xx, yy);
+        shT[Z::pos(lx, ly)] = v;
+      }
+      __syncthreads();
+      if (c + 1 < ce) dma(c + 1, nst, nsp);
+      T zz[2][2];
+#pragma unroll
+      for (int sl = 0; sl < 2; ++sl) {
+        zz[sl][0] = zz[sl][1] = T(0);
+        if (HOIST && pass_active(pslot[sl])) draw(c, pslot[sl], zz[sl][0], zz[sl][1]);
+      }
+#pragma unroll
+      for (int p = 0; p < NPASS; ++p) {
+        if ((p == pslot[0] || p == pslot[1]) && pass_active(p)) {
+          T z0 = p == pslot[0] ? zz[0][0] : zz[1][0];
+          T z1 = p == pslot[0] ? zz[0][1] : zz[1][1];
+          if (!HOIST) draw(c, p, z0, z1);
+          pass_update(p, shT, z0, z1, nullptr);
+        }
+        lds_barrier();
+      }
+      finish_chain(c, shT);
+    };
+    if (cb < ce) dma(cb, stA, spA);
+    for (int c = cb; c < ce; c += 2) {
+      chain(c, stA, spA, stB, spB);
+      if (c + 1 < ce) chain(c + 1, stB, spB, stA, spA);
+    }
+    return;
+  }
   // MC chains per step: their tiles sit side by side in LDS and every pass
   // updates all of them between two barriers.  A step past the last chain
   // works on the last chain's data and stores nothing.
@@ -470,42 +648,13 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
     __syncthreads();
 #pragma unroll
     for (int p = 0; p < NPASS; ++p) {
-      const int hp = NPASS - 1 - p;
       if ((p == pslot[0] || p == pslot[1]) && pass_active(p)) {
-        const int colour = pass_colour(p);
-        const int xpar = colour & 1;
-        const int k0 = xpar ? 0 : 1;  // offset of the colour's first site in the segment
-        const int xlo = max(1, tx0 - hp), xhi = min(n, tx0 + TX - 1 + hp);
 #pragma unroll
         for (int mi = 0; mi < MC; ++mi) {
           T z[2] = {p == pslot[0] ? zz[mi][0][0] : zz[mi][1][0],
                     p == pslot[0] ? zz[mi][0][1] : zz[mi][1][1]};
           if (!HOIST) draw(min(c0 + mi, ce - 1), p, z[0], z[1]);
-#pragma unroll
-          for (int j = 0; j < 2; ++j) {
-#pragma unroll
-            for (int kk = 0; kk < 2; ++kk) {  // resolve the site index at compile time
-              if (kk != k0) continue;
-              const int k = kk + 2 * j;
-              const int x = 4 * q + 1 + k;
-              if (x < xlo || x > xhi) continue;
-              const int lx = x - ox;
-              const int li = Z::pos(lx, y - oy);
-              const int sxm = lx & 3;
-              const int oe = Z::east(sxm), ow = Z::west(sxm);
-              T s = RHSC ? rc[RHSC ? mi : 0][k] : rhs[RHSC ? 0 : k];
-              int b = 0;
-#pragma unroll
-              for (int t = 0; t < 9; ++t) {
-                const int dx = t % 3 - 1, dy = t / 3 - 1;
-                if (dx == 0 && dy == 0) continue;
-                if (CROSS && dx != 0 && dy != 0) continue;
-                const int o = dy * Z::RS + (dx < 0 ? ow : (dx > 0 ? oe : 0));
-                s -= cf[k][b++] * sh[mi][li + o];
-              }
-              sh[mi][li] = s * ivd[k] + z[j] * isd[k];
-            }
-          }
+          pass_update(p, sh[mi], z[0], z[1], rc[RHSC ? mi : 0]);
         }
       }
       __syncthreads();
@@ -514,16 +663,7 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
     for (int mi = 0; mi < MC; ++mi) {
       const int c = c0 + mi;
       if (c >= ce) break;
-      if (bs.snap) snap_sites(bs, g, int(blockIdx.x), c, ox, oy, NT,
-                              [&](int lx, int ly) { return double(sh[mi][Z::pos(lx, ly)]); });
-      if (row_in && sx >= 1 && sx <= TX / 4 && y >= ty0 && y <= ty0 + TYS - 1) {
-        T* tho = theta_out + int64_t(c) * g.Np;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int x = 4 * q + 1 + k;
-          if (x <= n) tho[pidx(g, x, y, 0)] = sh[mi][Z::pos(x - ox, y - oy)];
-        }
-      }
+      finish_chain(c, sh[mi]);
     }
     __syncthreads();
   }
@@ -750,6 +890,7 @@ hipError_t launch_sweep_seg(const Launch& L, const DevLevel& lv, const void* the
   if (lv.cross ? fcs != 0 : (f == nullptr || fcs == 0)) return hipErrorInvalidValue;
   const int n = lv.g.n;
   const bool big = variant == 1;
+  const bool dma = variant == 2 && lv.cross;  // LDS DMA tiles (5-point levels)
   if (snap && (lv.bsnap == nullptr || lv.bt_ptr[big ? 2 : 1] == nullptr)) return hipErrorInvalidValue;
   const BSnap bs = make_snap(lv, big ? 2 : 1, snap);
   const int tys = lv.cross ? (big ? 26 : 12) : (big ? 22 : 8);
@@ -762,24 +903,26 @@ hipError_t launch_sweep_seg(const Launch& L, const DevLevel& lv, const void* the
   const bool pro = coarse != nullptr;
   const bool userp = pro && lv.wP != nullptr;
   const Geom gc = pro ? coarse->g : Geom{};
-#define MGMC_SEG_T(T, NP, PR, UP, TYS, NT)                                                           \
-  k_sweep2d_seg<T, NP, PR, UP, TYS, NT, 1><<<grid, NT, 0, L.stream>>>(                              \
+#define MGMC_SEG_T(T, NP, PR, UP, TYS, NT, DM)                                                       \
+  k_sweep2d_seg<T, NP, PR, UP, TYS, NT, 1, DM><<<grid, NT, 0, L.stream>>>(                          \
       (const T*)lv.coef, (const T*)lv.invd, (const T*)lv.isqd, (const T*)theta_in, (T*)theta_out,     \
       zero_in, (const T*)f, fcs, lv.g, (const T*)psi, gc, userp ? lv.wP : nullptr, backward, word,     \
       L.mcur, L.seed, L.chain0, tiles_x, cpb, L.nchains, L.bm_table, bs)
-#define MGMC_SEG_NP(T, NP, TYS, NT)                             \
-  do {                                                          \
-    if (!pro) MGMC_SEG_T(T, NP, false, false, TYS, NT);         \
-    else if (!userp) MGMC_SEG_T(T, NP, true, false, TYS, NT);   \
-    else MGMC_SEG_T(T, NP, true, true, TYS, NT);                \
+#define MGMC_SEG_NP(T, NP, TYS, NT, DM)                             \
+  do {                                                              \
+    if (!pro) MGMC_SEG_T(T, NP, false, false, TYS, NT, DM);         \
+    else if (!userp) MGMC_SEG_T(T, NP, true, false, TYS, NT, DM);   \
+    else MGMC_SEG_T(T, NP, true, true, TYS, NT, DM);                \
   } while (0)
-#define MGMC_SEG_V(T)                                                   \
-  do {                                                                  \
-    if (lv.cross) {                                                     \
-      if (big) MGMC_SEG_NP(T, 2, 26, 512); else MGMC_SEG_NP(T, 2, 12, 256); \
-    } else {                                                            \
-      if (big) MGMC_SEG_NP(T, 4, 22, 512); else MGMC_SEG_NP(T, 4, 8, 256);  \
-    }                                                                   \
+#define MGMC_SEG_V(T)                                                          \
+  do {                                                                         \
+    if (lv.cross) {                                                            \
+      if (big) MGMC_SEG_NP(T, 2, 26, 512, false);                              \
+      else if (dma) MGMC_SEG_NP(T, 2, 12, 256, true);                          \
+      else MGMC_SEG_NP(T, 2, 12, 256, false);                                  \
+    } else {                                                                   \
+      if (big) MGMC_SEG_NP(T, 4, 22, 512, false); else MGMC_SEG_NP(T, 4, 8, 256, false); \
+    }                                                                          \
   } while (0)
   (void)tys;
   (void)nt;

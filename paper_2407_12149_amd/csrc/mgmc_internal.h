@@ -167,8 +167,10 @@ hipError_t launch_sweep_tiled(const Launch& L, const DevLevel& lv, const void* t
                               uint32_t word, int backward, const DevLevel* coarse, const void* psi,
                               bool snap = false);
 // Segment form of the tiled sweep (stencil held in registers across passes
-// and chains).  variant 0: 256 threads per block, 1: 512; cpb_override > 0
-// fixes the chains per block.
+// and chains).  variant 0: 256 threads per block, 1: 512, 2: 256 with the
+// state tiles copied into LDS by DMA, double-buffered across chains
+// (5-point levels; 9-point levels take variant 0); cpb_override > 0 fixes
+// the chains per block.
 hipError_t launch_sweep_seg(const Launch& L, const DevLevel& lv, const void* theta_in,
                             void* theta_out, int zero_in, const void* f, int64_t fcs,
                             uint32_t word, int backward, const DevLevel* coarse, const void* psi,

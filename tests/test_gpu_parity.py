@@ -134,7 +134,7 @@ def test_posterior_2d_variable_stepwise(tiled):
                    tiled=tiled)
 
 
-@pytest.mark.parametrize("variant,cpb", [(0, 0), (1, 0), (1, 4), (2, 3), (2, 0), (3, 0)])
+@pytest.mark.parametrize("variant,cpb", [(0, 0), (1, 0), (1, 4), (2, 3), (2, 0), (3, 0), (4, 0), (4, 3)])
 def test_posterior_2d_many_tiles_many_chains(variant, cpb):
     """255^2 spans several sweep tiles in both directions with a ragged last
     tile; 9 chains exercise chain groups per block (ragged when cpb = 4)."""
@@ -330,6 +330,32 @@ def test_posterior_without_observations_is_state_error():
         s.posterior_sample(np.zeros(2), 0, 1)
     assert ei.value.status == mgmc.MGMC_ESTATE
     s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_dma_tiles_match_register_form(precision):
+    """Form 4 brings each chain's state tile and coarse patch into LDS by DMA
+    and otherwise runs form 1's arithmetic, so the states agree bit for bit
+    (9 chains in groups of 3 and of 9: odd groups end on either buffer)."""
+    n = 255
+    face = workloads.face_array(n, 2, workloads.fourier_log_field(2, nmodes=8, seed=3))
+    prob, obs = make_problem(2, n, 5, 30.0, face=face, beta=5, gamma=1e-3, nchains=9,
+                             precision=precision)
+    y = workloads.observed_values(5, seed=7)
+    from paper_2407_12149_amd import mgmc
+    states = {}
+    for variant, cpb in ((1, 3), (4, 3), (4, 9)):
+        log(f"[dma] {precision} variant {variant} cpb {cpb}")
+        s = mgmc.Sampler(prob, obs=obs)
+        s.set_option(mgmc.MGMC_OPT_SWEEP_VARIANT, variant)
+        s.set_option(mgmc.MGMC_OPT_CHAINS_PER_BLOCK, cpb)
+        s.posterior_sample(y, 0, 3)
+        torch.cuda.synchronize()
+        states[(variant, cpb)] = s.theta.clone()
+        s.close()
+    ref = states[(1, 3)]
+    for key, th in states.items():
+        assert torch.equal(th, ref), f"{precision} {key}: max diff {(th - ref).abs().max().item():.3e}"
 
 
 def test_fp32_tracks_fp64_on_common_random_numbers():
