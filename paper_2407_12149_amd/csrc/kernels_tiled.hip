@@ -100,10 +100,15 @@ __device__ __forceinline__ void lds_dma16(const void* src, void* dst) {
 // LDS layout of a tile row: four sub-rows by x mod 4, each of odd length W,
 // so the lanes of a wavefront (pairs four sites apart, the same x mod 4)
 // read consecutive words and neighbour reads are free of bank conflicts.
-template <int RX>
+// The row stride RS is padded to 9 mod 16 elements (ESZ = 8) or mod 32
+// (ESZ = 4): a segment-sweep wavefront holds 18 segments of each of rows
+// two apart, and 2 RS = 18 (mod 32 bank pairs / 64 banks) puts lane u on
+// bank (pair) u mod 32 (mod 64) whichever rows the lanes fall in.
+template <int RX, int ESZ>
 struct Swz {
   static constexpr int W = ((RX + 3) / 4) | 1;
-  static constexpr int RS = 4 * W;  // row stride
+  static constexpr int MB = ESZ == 8 ? 16 : 32;
+  static constexpr int RS = 4 * W + ((9 - 4 * W) % MB + MB) % MB;  // row stride
   static __device__ __forceinline__ int pos(int lx, int ly) { return ly * RS + (lx & 3) * W + (lx >> 2); }
   // offsets of the x-neighbours of a site with lx & 3 == s
   static __device__ __forceinline__ int east(int s) { return s < 3 ? W : 1 - 3 * W; }
@@ -136,7 +141,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d_tiled(
   constexpr bool CROSS = (NPASS == 2);
   constexpr int H = NPASS, RX = TX + 2 * H, RY = TY + 2 * H;
   constexpr int Q = RX / 4 + 2;  // pair slots per row
-  using Z = Swz<RX>;
+  using Z = Swz<RX, int(sizeof(T))>;
   __shared__ T sh[RY * Z::RS];
   const int n = g.n;
   const int tx0 = int(blockIdx.x % tiles_x) * TX + 1;
@@ -300,7 +305,7 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
   constexpr bool RHSC = !CROSS;
   static_assert(SY % 2 == 0, "owner rows must split evenly by parity");
   static_assert(GA + HALF * SX <= NT, "block too small for the segment grid");
-  using Z = Swz<RX>;
+  using Z = Swz<RX, int(sizeof(T))>;
   __shared__ T sh[DMA ? 1 : MC][DMA ? 1 : RY * Z::RS];
   // coarse patch under the tile region for the fused prolongation
   constexpr int CRX = RX / 2 + 2, CRY = RY / 2 + 2;
