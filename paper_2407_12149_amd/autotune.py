@@ -15,6 +15,7 @@ from . import mgmc
 
 CANDIDATE_VARIANTS = (1, 2, 0)
 FINEST_VARIANTS = (4,)  # LDS DMA state tiles (5-point level only)
+MIN_GAIN = 0.005  # a candidate replaces the current choice only when this much faster
 CANDIDATE_CPB = (0, 1, 2, 4, 8, 16)
 
 
@@ -36,11 +37,12 @@ def apply(sampler, levels):
 
 
 def _time(sampler, updates):
-    sampler.time_updates(1)  # warm-up
-    return sampler.time_updates(updates) / updates
+    """Milliseconds per update: the best of three runs of `updates` updates."""
+    sampler.time_updates(2)  # warm-up
+    return min(sampler.time_updates(updates) / updates for _ in range(3))
 
 
-def autotune(sampler, cache_path=None, updates=3, verbose=False):
+def autotune(sampler, cache_path=None, updates=8, verbose=False):
     """Pick the fastest per-level settings for this sampler, apply them and
     return {"levels": [[variant, cpb] or None per level], "ms": t, "cached": bool}."""
     key = _key(sampler)
@@ -71,7 +73,7 @@ def autotune(sampler, cache_path=None, updates=3, verbose=False):
                     if verbose:
                         print(f"[autotune] {key} level {l} variant={v} cpb={c}: {ms:.3f} ms/update",
                               flush=True)
-                    if ms < ms_best:
+                    if ms < ms_best * (1.0 - MIN_GAIN):
                         ms_best, choice = ms, [v, c]
             if choice is not None:
                 levels[l] = choice
@@ -82,7 +84,7 @@ def autotune(sampler, cache_path=None, updates=3, verbose=False):
         ms = _time(sampler, updates)
         if verbose:
             print(f"[autotune] {key} fused bottom: {ms:.3f} ms/update", flush=True)
-        if ms < ms_best:
+        if ms < ms_best * (1.0 - MIN_GAIN):
             ms_best, fused = ms, 1
         sampler.set_option(mgmc.MGMC_OPT_COARSE_FUSED, fused)
         best = {"levels": levels, "fused": fused, "ms": ms_best, "cached": False}
