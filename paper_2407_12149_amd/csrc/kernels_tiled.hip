@@ -651,6 +651,11 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
       }
     }
     __syncthreads();
+    // Without hoisting (one chain per step), a thread draws the normals of
+    // its next pass during the pass before it, in which its rows have no
+    // colour to update (its two passes have one parity); only a first
+    // pass 0 draws in place.
+    T za0 = T(0), za1 = T(0);
 #pragma unroll
     for (int p = 0; p < NPASS; ++p) {
       if ((p == pslot[0] || p == pslot[1]) && pass_active(p)) {
@@ -658,9 +663,16 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
         for (int mi = 0; mi < MC; ++mi) {
           T z[2] = {p == pslot[0] ? zz[mi][0][0] : zz[mi][1][0],
                     p == pslot[0] ? zz[mi][0][1] : zz[mi][1][1]};
-          if (!HOIST) draw(min(c0 + mi, ce - 1), p, z[0], z[1]);
+          if (!HOIST && (MC > 1 || p == 0)) draw(min(c0 + mi, ce - 1), p, z[0], z[1]);
+          if (!HOIST && MC == 1 && p > 0) {
+            z[0] = za0;
+            z[1] = za1;
+          }
           pass_update(p, sh[mi], z[0], z[1], rc[RHSC ? mi : 0]);
         }
+      } else if (!HOIST && MC == 1 && p + 1 < NPASS && (p + 1 == pslot[0] || p + 1 == pslot[1]) &&
+                 pass_active(p + 1)) {
+        draw(c0, p + 1, za0, za1);
       }
       __syncthreads();
     }
