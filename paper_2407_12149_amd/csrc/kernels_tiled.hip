@@ -417,6 +417,7 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
     pslot[1] = backward ? NPASS - 1 - pos1 : pos1;
   }
   constexpr bool HOIST = CROSS || !PROLONG || sizeof(T) == 4;
+  constexpr bool AHEAD = NPASS == 4 && MC == 1;  // normals drawn in the idle pass before
   const int cb = int(blockIdx.y) * cpb;
   const int ce = min(nchains, cb + cpb);
   const int jx0 = ox >> 1, jy0 = oy >> 1;  // first coarse node under the region
@@ -616,13 +617,15 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
     }
     // ... and draw the noise while they are in flight (except where
     // registers are scarce: FP64 four-colour levels with the prolongation)
+    // (on four-colour levels with one chain per step, only a draw for pass
+    // 0; the others come during the idle pass before theirs, below)
     T zz[MC][2][2];
 #pragma unroll
     for (int mi = 0; mi < MC; ++mi) {
 #pragma unroll
       for (int sl = 0; sl < 2; ++sl) {
         zz[mi][sl][0] = zz[mi][sl][1] = T(0);
-        if (HOIST && c0 + mi < ce && pass_active(pslot[sl]))
+        if (HOIST && (!AHEAD || pslot[sl] == 0) && c0 + mi < ce && pass_active(pslot[sl]))
           draw(c0 + mi, pslot[sl], zz[mi][sl][0], zz[mi][sl][1]);
       }
     }
@@ -651,10 +654,10 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
       }
     }
     __syncthreads();
-    // Without hoisting (one chain per step), a thread draws the normals of
-    // its next pass during the pass before it, in which its rows have no
-    // colour to update (its two passes have one parity); only a first
-    // pass 0 draws in place.
+    // On four-colour levels with one chain per step a thread draws the
+    // normals of its next pass during the pass before it, in which its rows
+    // have no colour to update (its two passes have one parity); only pass
+    // 0 takes normals drawn before the passes (hoisted) or in place.
     T za0 = T(0), za1 = T(0);
 #pragma unroll
     for (int p = 0; p < NPASS; ++p) {
@@ -663,14 +666,15 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
         for (int mi = 0; mi < MC; ++mi) {
           T z[2] = {p == pslot[0] ? zz[mi][0][0] : zz[mi][1][0],
                     p == pslot[0] ? zz[mi][0][1] : zz[mi][1][1]};
-          if (!HOIST && (MC > 1 || p == 0)) draw(min(c0 + mi, ce - 1), p, z[0], z[1]);
-          if (!HOIST && MC == 1 && p > 0) {
+          if (AHEAD && p > 0) {
             z[0] = za0;
             z[1] = za1;
+          } else if (!HOIST) {
+            draw(min(c0 + mi, ce - 1), p, z[0], z[1]);
           }
           pass_update(p, sh[mi], z[0], z[1], rc[RHSC ? mi : 0]);
         }
-      } else if (!HOIST && MC == 1 && p + 1 < NPASS && (p + 1 == pslot[0] || p + 1 == pslot[1]) &&
+      } else if (AHEAD && p + 1 < NPASS && (p + 1 == pslot[0] || p + 1 == pslot[1]) &&
                  pass_active(p + 1)) {
         draw(c0, p + 1, za0, za1);
       }
