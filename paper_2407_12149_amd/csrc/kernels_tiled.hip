@@ -379,12 +379,17 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
     const bool in = row_in && x >= 1 && x <= n;
     const int64_t gi = in ? pidx(g, x, y, 0) : 0;
     if (!CROSS) {
+      // entries towards +x / +y from the neighbour's opposite entry (the
+      // operator is symmetric entry by entry), so four of the eight
+      // neighbour arrays are read
       int b = 0;
 #pragma unroll
       for (int t = 0; t < 9; ++t) {
         const int dx = t % 3 - 1, dy = t / 3 - 1;
         if (dx == 0 && dy == 0) continue;
-        cf[k][b++] = coef[int64_t(t) * g.Np + gi];
+        const bool mirror = t > 4;
+        const int64_t at = mirror ? (in ? pidx(g, x + dx, y + dy, 0) : 0) : gi;
+        cf[k][b++] = coef[int64_t(mirror ? 8 - t : t) * g.Np + at];
       }
     }
     ivd[k] = invd[gi];
@@ -735,7 +740,13 @@ __global__ __launch_bounds__(NT) void k_restrict2d_reg(
     for (int t = 0; t < 9; ++t) {
       const int dx = t % 3 - 1, dy = t / 3 - 1;
       if (CROSS && dx != 0 && dy != 0) continue;
-      cr[k][b++] = coef[int64_t(t) * gf.Np + gr[k]];
+      // The operator is symmetric entry by entry: an entry towards +x or +y
+      // is the opposite entry of that neighbour, so only the centre and the
+      // entries towards -x / -y are read from memory.  (Next to the boundary
+      // the neighbour is a ghost entry, zero, and so is the state it meets.)
+      const bool mirror = t > 4;
+      const int64_t at = mirror ? (in ? pidx(gf, x + dx, y + dy, 0) : 0) : gr[k];
+      cr[k][b++] = coef[int64_t(mirror ? 8 - t : t) * gf.Np + at];
     }
     fr[k] = (f && fcs == 0) ? f[gr[k]] : T(0);
   }
