@@ -31,6 +31,20 @@ static __device__ __forceinline__ int64_t poff(const Geom& g, int dx, int dy, in
   return int64_t(dx) + int64_t(g.px) * (int64_t(dy) + int64_t(g.py) * dz);
 }
 
+// Stencil entry t of the interior padded site i.  Past the centre the entry
+// is read as the opposite entry of the neighbour i + delta(t) (the operators
+// are symmetric entry by entry), so only the centre and the entries towards
+// lower indices come from memory.  The neighbour may be a ghost position,
+// whose entries are zero, as is the state they would multiply.
+template <typename T, int DIM>
+static __device__ __forceinline__ T stencil_entry(const T* __restrict__ coef, const Geom& g, int t,
+                                                  int64_t i) {
+  constexpr int S = DIM == 2 ? 9 : 27;
+  if (t <= S / 2) return coef[int64_t(t) * g.Np + i];
+  const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = DIM == 3 ? t / 9 - 1 : 0;
+  return coef[int64_t(S - 1 - t) * g.Np + i + poff(g, dx, dy, dz)];
+}
+
 template <int DIM>
 static __device__ __forceinline__ void unflatten(int64_t lin, int n, int& i1, int& i2, int& i3) {
   i1 = 1 + int(lin % n);

@@ -44,7 +44,7 @@ __device__ __forceinline__ void gs_update(const T* __restrict__ coef, const T* _
     const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = DIM == 3 ? t / 9 - 1 : 0;
     const int nz = (dx != 0) + (dy != 0) + (dz != 0);
     if (nz == 0 || (CROSS && nz != 1)) continue;
-    s -= coef[int64_t(t) * g.Np + i] * th[i + poff(g, dx, dy, dz)];
+    s -= stencil_entry<T, DIM>(coef, g, t, i) * th[i + poff(g, dx, dy, dz)];
   }
   th[i] = s * invd[i] + z * isqd[i];
 }
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const T* __restrict__ coef,
       const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = DIM == 3 ? t / 9 - 1 : 0;
       const int nz = (dx != 0) + (dy != 0) + (dz != 0);
       if (nz == 0 || (CROSS && nz != 1)) continue;
-      cf[k][b++] = in ? coef[int64_t(t) * g.Np + ia + 2 * k] : T(0);
+      cf[k][b++] = in ? stencil_entry<T, DIM>(coef, g, t, ia + 2 * k) : T(0);
     }
     ivd[k] = in ? invd[ia + 2 * k] : T(0);
     isd[k] = in ? isqd[ia + 2 * k] : T(0);
@@ -168,7 +168,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep_parity3d(const T* __restrict__
     const int64_t i = ia + 2 * k;
     const bool in = k == 0 || two;
 #pragma unroll
-    for (int e = 0; e < 6; ++e) cf[k][e] = in ? coef[int64_t(tix[e]) * g.Np + i] : T(0);
+    // +x, +y, +z entries from the neighbour's opposite entry (symmetric operator)
+    for (int e = 0; e < 6; ++e)
+      cf[k][e] = in ? coef[int64_t(tix[e < 3 ? e : 5 - e]) * g.Np + i + (e < 3 ? 0 : off[e])] : T(0);
     ivd[k] = in ? invd[i] : T(0);
     isd[k] = in ? isqd[i] : T(0);
     rhs[k] = (in && f && fcs == 0) ? f[i] : T(0);
@@ -223,7 +225,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(const T* __restrict__ coef,
       const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = DIM == 3 ? t / 9 - 1 : 0;
       const int nz = (dx != 0) + (dy != 0) + (dz != 0);
       if (CROSS && nz > 1) continue;
-      r -= coef[int64_t(t) * gf.Np + ii] * th[ii + poff(gf, dx, dy, dz)];
+      r -= stencil_entry<T, DIM>(coef, gf, t, ii) * th[ii + poff(gf, dx, dy, dz)];
     }
     const T w = USERP ? T(wP[int64_t(t1) * gc.Np + iJ]) : T(multilinear(ex, ey, ez));
     acc += w * r;
@@ -253,7 +255,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(const T* __restrict__ coef,
     const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = DIM == 3 ? t / 9 - 1 : 0;
     const int nz = (dx != 0) + (dy != 0) + (dz != 0);
     if (CROSS && nz > 1) continue;
-    cf[b++] = coef[int64_t(t) * g.Np + ii];
+    cf[b++] = stencil_entry<T, DIM>(coef, g, t, ii);
   }
   const int cb = int(blockIdx.y) * cpb;
   const int ce = min(nchains, cb + cpb);

@@ -57,7 +57,7 @@ __device__ void cv_sweep(const CoarseLevel& A, T* __restrict__ th, const T* __re
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
           if (t == 4) continue;
-          s -= coef[int64_t(t) * g.Np + ia] * th[ia + poff(g, t % 3 - 1, t / 3 - 1, 0)];
+          s -= stencil_entry<T, 2>(coef, g, t, ia) * th[ia + poff(g, t % 3 - 1, t / 3 - 1, 0)];
         }
         th[ia] = s * invd[ia] + z[k] * isqd[ia];
       }
@@ -141,7 +141,7 @@ __device__ void cv_restrict(const CoarseLevel& F, const CoarseLevel& Cl, const T
     const int64_t ii = pidx(gf, i1, i2, 0);
     T r = f[ii];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) r -= coef[int64_t(t) * gf.Np + ii] * th[ii + poff(gf, t % 3 - 1, t / 3 - 1, 0)];
+    for (int t = 0; t < 9; ++t) r -= stencil_entry<T, 2>(coef, gf, t, ii) * th[ii + poff(gf, t % 3 - 1, t / 3 - 1, 0)];
     rbuf[ii] = r;
   }
   __syncthreads();

@@ -228,7 +228,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d_tiled(
               const int dx = t % 3 - 1, dy = t / 3 - 1;
               if (dx == 0 && dy == 0) continue;
               if (CROSS && dx != 0 && dy != 0) continue;
-              cf[k][b++] = coef[int64_t(t) * g.Np + gi[k]];
+              cf[k][b++] = stencil_entry<T, 2>(coef, g, t, gi[k]);
             }
             ivd[k] = invd[gi[k]];
             isd[k] = isqd[gi[k]];
