@@ -149,10 +149,11 @@ mgmc_status mgmc_set_graph(mgmc_ctx* ctx, int32_t enabled);
  *     (5-point levels; 9-point levels take form 1).
  *   MGMC_OPT_CHAINS_PER_BLOCK: chains processed by one block of the 2D
  *     sweep; 0 (default) chooses from the grid size and precision.
- *   MGMC_OPT_COARSE_FUSED: 1 runs the levels with at most 63 nodes per axis
- *     below the finest (2D, one-launch sweeps) as one launch with one
- *     workgroup per chain and the levels resident in LDS; 0 (default)
- *     launches them level by level (faster for few chains).
+ *   MGMC_OPT_COARSE_FUSED: k >= 1 runs levels 0 .. min(k, m) as one launch
+ *     with one workgroup per chain and the levels resident in LDS (2D,
+ *     one-launch sweeps), where m is the highest level below the finest
+ *     with at most 63 nodes per axis whose levels fit in LDS; 0 (default)
+ *     launches them level by level.  Negative values: EINVAL.
  *   MGMC_OPT_LOWRANK_MFMA: 1 (default) computes the low-rank product G t of
  *     all chains with FP64 matrix-core instructions (16 chains per tile; used
  *     for beta <= 512), and on 2D levels with one-launch sweeps (beta <= 128)

@@ -6,7 +6,7 @@ block, and on the finest, 5-point level also the form whose state tiles come
 into LDS by DMA) and the number of chains processed per block, by coordinate descent
 from the finest level down: each level's candidates are timed with the
 library's own update timer while the other levels keep their current best.
-It then tries the bottom levels as one launch.  Results are cached in a JSON
+It then tries the bottom levels 0 .. k as one launch for each k.  Results are cached in a JSON
 file keyed by problem shape, precision, chain count and device architecture.""" 
 import json
 import os
@@ -78,14 +78,16 @@ def autotune(sampler, cache_path=None, updates=8, verbose=False):
             if choice is not None:
                 levels[l] = choice
             apply(sampler, levels)
-        # the bottom levels as one launch, if that is faster
+        # the bottom levels 0 .. k as one launch, if that is faster (the
+        # library caps k at the deepest level it can fuse)
         fused = 0
-        sampler.set_option(mgmc.MGMC_OPT_COARSE_FUSED, 1)
-        ms = _time(sampler, updates)
-        if verbose:
-            print(f"[autotune] {key} fused bottom: {ms:.3f} ms/update", flush=True)
-        if ms < ms_best * (1.0 - MIN_GAIN):
-            ms_best, fused = ms, 1
+        for k in range(1, min(nlev - 1, 6)):
+            sampler.set_option(mgmc.MGMC_OPT_COARSE_FUSED, k)
+            ms = _time(sampler, updates)
+            if verbose:
+                print(f"[autotune] {key} fused bottom 0..{k}: {ms:.3f} ms/update", flush=True)
+            if ms < ms_best * (1.0 - MIN_GAIN):
+                ms_best, fused = ms, k
         sampler.set_option(mgmc.MGMC_OPT_COARSE_FUSED, fused)
         best = {"levels": levels, "fused": fused, "ms": ms_best, "cached": False}
         if cache_path:

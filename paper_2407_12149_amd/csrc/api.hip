@@ -73,10 +73,11 @@ struct mgmc_ctx {
   int sweep_variant = 3;  // 0: LDS-staged tiles, 1/2: segment owners with 256/512 threads, 3: per level
   int sweep_cpb = 0;      // chains per block of the 2D sweeps; 0 picks by size
   std::vector<int> lvl_variant, lvl_cpb;  // per-level overrides, -1 = context-wide setting
-  // levels 0..coarse_lm run as one workgroup per chain (0: not available)
-  bool coarse_fused = false;
+  // levels 0..lm run as one workgroup per chain, lm = min(coarse_fused,
+  // coarse_lm) (coarse_fused 0: off; coarse_lm 0: not available)
+  int coarse_fused = 0;
   int coarse_lm = 0;
-  size_t coarse_lds = 0;
+  size_t coarse_lds[mgmc::kMaxCoarseLevels] = {};  // LDS bytes per top fused level
   mgmc::CoarseArgs cargs;
   std::vector<void*> allocs;
   // profiling: a ring of event pairs around finest-level sweep launches
@@ -442,7 +443,7 @@ mgmc_status enqueue_cycle(mgmc_ctx* c, const void* fL, const double* F, double* 
     return MGMC_OK;
   };
   // the bottom levels in one launch when available (2D, one-launch sweeps)
-  const int lm = (tiled && c->coarse_fused) ? c->coarse_lm : 0;
+  const int lm = (tiled && c->coarse_fused > 0) ? std::min(c->coarse_fused, c->coarse_lm) : 0;
   if (top == 0) {
     MGMC_LAUNCH(mgmc::launch_coarsest(L, c->lv[0], fL, 0, state(0), c->K, c->Uinv));
   } else {
@@ -494,10 +495,11 @@ mgmc_status enqueue_cycle(mgmc_ctx* c, const void* fL, const double* F, double* 
     }
     if (lm >= 1) {
       mgmc::CoarseArgs a = c->cargs;
+      a.lm = lm;
       a.f_top = c->lv[lm].f;
       cur[lm] = 0;
       a.theta_top = state(lm);
-      MGMC_LAUNCH(mgmc::launch_coarse_vcycle(L, a, c->coarse_lds));
+      MGMC_LAUNCH(mgmc::launch_coarse_vcycle(L, a, c->coarse_lds[lm]));
     } else {
       MGMC_LAUNCH(mgmc::launch_coarsest(L, c->lv[0], c->lv[0].f, c->lv[0].g.Np, state(0), c->K, c->Uinv));
     }
@@ -704,13 +706,17 @@ mgmc_status mgmc_setup(const mgmc_problem* problem, const mgmc_obs* obs, void* h
       int64_t max_bnnz = 0;
       for (int l = 1; l <= lm; ++l) max_bnnz = std::max(max_bnnz, c->lv[l].bnnz);
       const size_t bytes = mgmc::coarse_vcycle_lds(a, c->L.fp32 != 0, max_bnnz);
-      if (bytes <= 160 * 1024 && mgmc::coarse_vcycle_prepare(c->L.fp32 != 0, bytes) == hipSuccess) {
-        c->coarse_lds = bytes;
-        break;
-      }
+      if (bytes <= 160 * 1024 && mgmc::coarse_vcycle_prepare(c->L.fp32 != 0, bytes) == hipSuccess) break;
       --lm;
     }
     c->coarse_lm = lm;
+    for (int k = 1; k <= lm; ++k) {  // LDS of each smaller top level
+      a.lm = k;
+      int64_t max_bnnz = 0;
+      for (int l = 1; l <= k; ++l) max_bnnz = std::max(max_bnnz, c->lv[l].bnnz);
+      c->coarse_lds[k] = mgmc::coarse_vcycle_lds(a, c->L.fp32 != 0, max_bnnz);
+    }
+    a.lm = lm;
     (void)hipGetLastError();
   }
   // keep only what later calls need on the host: the observation columns
@@ -800,7 +806,8 @@ mgmc_status mgmc_set_option(mgmc_ctx* c, int32_t option, int64_t value) {
       c->sweep_cpb = int(value);
       return MGMC_OK;
     case MGMC_OPT_COARSE_FUSED:
-      c->coarse_fused = value != 0;
+      if (value < 0) return fail(MGMC_EINVAL, "MGMC_OPT_COARSE_FUSED must be >= 0");
+      c->coarse_fused = int(std::min<int64_t>(value, mgmc::kMaxCoarseLevels));
       return MGMC_OK;
     case MGMC_OPT_LOWRANK_MFMA:
       if (value < 0 || value > 2) return fail(MGMC_EINVAL, "MGMC_OPT_LOWRANK_MFMA takes 0, 1 or 2");

@@ -93,7 +93,7 @@ def check_stepwise(prob, obs, nsamples, y=None, rhs=None, F=None, label="", tile
         from paper_2407_12149_amd import autotune
         autotune.apply(s, levels)
     if fused is not None:
-        s.set_option(mgmc.MGMC_OPT_COARSE_FUSED, 1 if fused else 0)
+        s.set_option(mgmc.MGMC_OPT_COARSE_FUSED, int(fused))
     for opt, val in (options or {}).items():
         s.set_option(opt, val)
     Fd = None if F is None else torch.tensor(F, device="cuda")
@@ -146,11 +146,12 @@ def test_posterior_2d_many_tiles_many_chains(variant, cpb):
                    label=f"posterior 255^2 variant {variant} cpb {cpb}", variant=variant, cpb=cpb)
 
 
-@pytest.mark.parametrize("fused", [True, False])
+@pytest.mark.parametrize("fused", [3, 1, 0])
 def test_bottom_levels_fused_or_per_level(fused):
-    """The levels up to 63^2 as one launch (one workgroup per chain, LDS
-    resident) or level by level: both follow the oracle; 2 pre- and 3
-    post-sweeps exercise the sweep counts inside the fused bottom."""
+    """The levels up to 63^2 (fused 3) or up to 15^2 (fused 1) as one launch
+    (one workgroup per chain, LDS resident), or level by level (0): all follow
+    the oracle; 2 pre- and 3 post-sweeps exercise the sweep counts inside the
+    fused bottom."""
     n = 255
     face = workloads.face_array(n, 2, workloads.fourier_log_field(2, nmodes=8, seed=5))
     prob, obs = make_problem(2, n, 6, 30.0, face=face, beta=6, gamma=1e-3, nchains=3, nu1=2, nu2=3)
