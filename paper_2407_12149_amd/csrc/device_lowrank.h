@@ -14,13 +14,12 @@ namespace mgmc {
 
 // Forms (t, xi) for chains c0 .. c0 + nc - 1 and hands every observation j
 // and chain slot cc < ncs to put(j, cc, t, xi), with zeros for the slots
-// cc >= nc.  All threads of the block take part.  The snapshot holds the
-// swept values in KP slots per observation ([chain][beta][KP], zero padded,
-// the weights bpval in the same slots); each sum takes its slots in order,
-// CH slots of each of a thread's two observations loaded together.
+// cc >= nc.  All threads of the block take part.  The snapshot holds B's
+// weight times the swept value in KP slots per observation
+// ([chain][beta][KP], zero padded); each sum takes its slots in order, CH
+// slots of each of a thread's two observations loaded together.
 template <int KP, int CH = KP, class Put>
-__device__ __forceinline__ void lowrank_t_xi(const double* __restrict__ bpval,
-                                             const double* __restrict__ bsnap, int64_t bslots,
+__device__ __forceinline__ void lowrank_t_xi(const double* __restrict__ bsnap, int64_t bslots,
                                              int beta, const double* __restrict__ gisq,
                                              const double* __restrict__ gam, uint32_t word,
                                              uint32_t m, uint32_t seed, uint32_t chain0, int c0,
@@ -42,7 +41,7 @@ __device__ __forceinline__ void lowrank_t_xi(const double* __restrict__ bpval,
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
-          for (int u = 0; u < CH; ++u) pr[h][u] = bpval[e0[h] + u0 + u] * sn[e0[h] + u0 + u];
+          for (int u = 0; u < CH; ++u) pr[h][u] = sn[e0[h] + u0 + u];
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
@@ -64,23 +63,6 @@ __device__ __forceinline__ void lowrank_t_xi(const double* __restrict__ bpval,
       if (j < beta) put(j, cc, tv[h], xv[h]);
     }
   }
-}
-
-// The same with the slot count chosen at run time (8, 16 or 32; the callers
-// check it) and CH slots per load batch.
-template <int CH = 32, class Put>
-__device__ __forceinline__ void lowrank_t_xi_any(int kp, const double* __restrict__ bpval,
-                                                 const double* __restrict__ bsnap, int64_t bslots,
-                                                 int beta, const double* __restrict__ gisq,
-                                                 const double* __restrict__ gam, uint32_t word,
-                                                 uint32_t m, uint32_t seed, uint32_t chain0,
-                                                 int c0, int nc, int ncs, Put put) {
-  if (kp == 8)
-    lowrank_t_xi<8, (CH < 8 ? CH : 8)>(bpval, bsnap, bslots, beta, gisq, gam, word, m, seed, chain0, c0, nc, ncs, put);
-  else if (kp == 16)
-    lowrank_t_xi<16, (CH < 16 ? CH : 16)>(bpval, bsnap, bslots, beta, gisq, gam, word, m, seed, chain0, c0, nc, ncs, put);
-  else
-    lowrank_t_xi<32, CH>(bpval, bsnap, bslots, beta, gisq, gam, word, m, seed, chain0, c0, nc, ncs, put);
 }
 
 }  // namespace mgmc

@@ -868,8 +868,8 @@ __device__ __forceinline__ void lowrank_mfma_rows(const MfmaRowsPrefetch<T>& pf,
 }
 
 // The low-rank correction (Alg. 3) in one launch after a 2D sweep that wrote
-// its snapshot of B's sites (bsnap, [nchains][beta][KP] slots, zero padded,
-// with the weights bpval in the same slots).  Every block forms
+// its snapshot of B's sites (bsnap: weight times swept value in
+// [nchains][beta][KP] slots, zero padded).  Every block forms
 // xi = Gamma^{-1/2} zeta and t = B^T theta* - Gamma xi for its group of up to
 // 16 chains from the snapshot, which the correction does not modify, so the
 // blocks need no ordering among themselves; each column sum takes its KP
@@ -881,8 +881,7 @@ __device__ __forceinline__ void lowrank_mfma_rows(const MfmaRowsPrefetch<T>& pf,
 template <typename T, int KP>
 __global__ __launch_bounds__(kBlock) void k_lowrank_fused_mfma(
     T* __restrict__ theta, int64_t Np, int beta, int nsupp, const int32_t* __restrict__ supp,
-    const double* __restrict__ GT, const double* __restrict__ bpval,
-    const double* __restrict__ bsnap, int64_t bslots, const double* __restrict__ gisq,
+    const double* __restrict__ GT, const double* __restrict__ bsnap, int64_t bslots, const double* __restrict__ gisq,
     const double* __restrict__ gam, const double* __restrict__ SinvT, double* __restrict__ v_out,
     int nrt, uint32_t word, const int64_t* __restrict__ mcur, uint32_t seed, uint32_t chain0,
     int nchains) {
@@ -898,7 +897,7 @@ __global__ __launch_bounds__(kBlock) void k_lowrank_fused_mfma(
     mfma_cols_prefetch(pf.av, SinvT, beta, beta, beta, rv0);
   else
     lowrank_mfma_prefetch<T>(pf, theta, Np, beta, nsupp, supp, GT, c0, nchains, blockIdx.x);
-  lowrank_t_xi<KP>(bpval, bsnap, bslots, beta, gisq, gam, word, m, seed, chain0, c0, nc, 16,
+  lowrank_t_xi<KP>(bsnap, bslots, beta, gisq, gam, word, m, seed, chain0, c0, nc, 16,
                    [&](int j, int cc, double t, double xi) {
                      sT[j * 16 + cc] = t;
                      if (vblock) sX[j * 16 + cc] = xi;
@@ -1003,11 +1002,12 @@ hipError_t launch_lowrank_fused(const Launch& L, const DevLevel& lv, void* theta
   dim3 grid(unsigned(nrt + nvb), unsigned((L.nchains + 15) / 16));
 #define MGMC_LR_FUSED(T, KP)                                                                      \
   k_lowrank_fused_mfma<T, KP><<<grid, kBlock, shm, L.stream>>>(                                   \
-      (T*)theta, lv.g.Np, beta, nsupp, lv.supp[dir], lv.GT[dir], lv.bpval, lv.bsnap, lv.bslots,   \
+      (T*)theta, lv.g.Np, beta, nsupp, lv.supp[dir], lv.GT[dir], lv.bsnap, lv.bslots,             \
       gisq, gam, lv.SinvT, v_out, nrt, word, L.mcur, L.seed, L.chain0, L.nchains)
 #define MGMC_LR_FUSED_KP(T)                  \
   do {                                       \
     if (lv.bkp == 8) MGMC_LR_FUSED(T, 8);    \
+    else if (lv.bkp == 12) MGMC_LR_FUSED(T, 12); \
     else if (lv.bkp == 16) MGMC_LR_FUSED(T, 16); \
     else if (lv.bkp == 32) MGMC_LR_FUSED(T, 32); \
     else return hipErrorInvalidValue;        \

@@ -115,9 +115,10 @@ struct Swz {
   static __device__ __forceinline__ int west(int s) { return s > 0 ? -W : 3 * W - 1; }
 };
 
-// Copy the swept values of chain c at B's sites inside tile `tile` into the
-// snapshot (B^T theta is then formed from it without another pass over
-// theta).  at(lx, ly) reads the LDS tile at region coordinates.
+// Write B's weight times the swept value of chain c at B's sites inside
+// tile `tile` into the snapshot (B^T theta is then formed from it without
+// another pass over theta).  at(lx, ly) reads the LDS tile at region
+// coordinates.
 template <class At>
 __device__ __forceinline__ void snap_sites(const BSnap& bs, const Geom& g, int tile, int c, int ox,
                                            int oy, int nt, At at) {
@@ -126,7 +127,7 @@ __device__ __forceinline__ void snap_sites(const BSnap& bs, const Geom& g, int t
     const int e = bs.ent[i];
     const int site = bs.idx[e];
     const int x = site % g.px - 3, y = site / g.px;
-    bs.snap[int64_t(c) * bs.nnz + e] = at(x - ox, y - oy);
+    bs.snap[int64_t(c) * bs.nnz + e] = bs.w[e] * at(x - ox, y - oy);
   }
 }
 
@@ -484,6 +485,7 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
   // slot b0 + t and its LDS position, so that no chain loads the lists
   // again; slots past b0 + NT (rare) are looked up per chain.
   int snap_slot = -1, snap_pos = 0, snap_b0 = 0, snap_b1 = 0;
+  double snap_w = 0.0;
   if (bs.snap) {
     snap_b0 = bs.ptr[blockIdx.x];
     snap_b1 = bs.ptr[blockIdx.x + 1];
@@ -491,15 +493,17 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
       snap_slot = bs.ent[snap_b0 + int(threadIdx.x)];
       const int site = bs.idx[snap_slot];
       snap_pos = Z::pos(site % g.px - 3 - ox, site / g.px - oy);
+      snap_w = bs.w[snap_slot];
     }
   }
-  // snapshot of B's sites and the tile's output of chain c from LDS tile s
+  // snapshot of B's sites (weight times value) and the tile's output of
+  // chain c from LDS tile s
   auto finish_chain = [&](int c, const T* s) __attribute__((always_inline)) {
-    if (snap_slot >= 0) bs.snap[int64_t(c) * bs.nnz + snap_slot] = double(s[snap_pos]);
+    if (snap_slot >= 0) bs.snap[int64_t(c) * bs.nnz + snap_slot] = snap_w * double(s[snap_pos]);
     for (int i = snap_b0 + NT + int(threadIdx.x); i < snap_b1; i += NT) {
       const int e = bs.ent[i];
       const int site = bs.idx[e];
-      bs.snap[int64_t(c) * bs.nnz + e] = double(s[Z::pos(site % g.px - 3 - ox, site / g.px - oy)]);
+      bs.snap[int64_t(c) * bs.nnz + e] = bs.w[e] * double(s[Z::pos(site % g.px - 3 - ox, site / g.px - oy)]);
     }
     if (row_in && sx >= 1 && sx <= TX / 4 && y >= ty0 && y <= ty0 + TYS - 1) {
       T* tho = theta_out + int64_t(c) * g.Np;
@@ -867,6 +871,7 @@ static BSnap make_snap(const DevLevel& lv, int gi, bool snap) {
   bs.ptr = lv.bt_ptr[gi];
   bs.ent = lv.bt_ent[gi];
   bs.idx = lv.bpidx;
+  bs.w = lv.bpval;
   bs.snap = lv.bsnap;
   bs.nnz = lv.bslots;
   return bs;

@@ -50,12 +50,13 @@ struct DevLevel {
   double* GT[2] = {nullptr, nullptr};      // [beta][nsupp], G = C S^{-1}
   double* SinvT = nullptr;                 // [beta][beta], S^{-1} of the forward sweep, transposed
   // B^T theta without a separate pass over theta (2D one-launch sweeps): the
-  // sweep kernels copy the swept values at B's sites into bsnap.  Its layout
-  // gives every column of B the same number bkp (8, 16 or 32) of slots:
-  // [nchains][beta][bkp], column j's entries in the order of bidx, then
-  // zeros, which stay zero, as do the matching bpval weights.  bt_ptr /
-  // bt_ent list the slots whose site lies in each 64 x TY tile, for the tile
-  // heights of the three 2D sweep forms (kSnapTY).
+  // sweep kernels write B's weight times the swept value at each of B's
+  // sites into bsnap.  Its layout gives every column of B the same number
+  // bkp (8, 12, 16 or 32) of slots: [nchains][beta][bkp], column j's entries
+  // in the order of bidx, then zeros, which stay zero (bpval holds the
+  // weights in the same slots).  bt_ptr / bt_ent list the slots whose site
+  // lies in each 64 x TY tile, for the tile heights of the three 2D sweep
+  // forms (kSnapTY).
   int bkp = 0;
   int64_t bslots = 0;                                // beta * bkp
   double* bpval = nullptr;                           // [beta][bkp] weights, zero padded
@@ -75,6 +76,7 @@ struct BSnap {
   const int32_t* ptr = nullptr;  // bt_ptr of the sweep's tile height
   const int32_t* ent = nullptr;  // slots
   const int32_t* idx = nullptr;  // bpidx
+  const double* w = nullptr;     // bpval
   double* snap = nullptr;        // null: no snapshot
   int64_t nnz = 0;               // slots per chain (beta * bkp)
 };
