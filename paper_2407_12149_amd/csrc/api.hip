@@ -251,7 +251,7 @@ mgmc_status upload_level(mgmc_ctx* c, int l) {
     if ((s = c->upload(d.bval, bval)) != MGMC_OK) return s;
     int64_t kmax = 0;
     for (int j = 0; j < beta; ++j) kmax = std::max(kmax, bptr[j + 1] - bptr[j]);
-    const int bkp = kmax <= 8 ? 8 : kmax <= 12 ? 12 : kmax <= 16 ? 16 : kmax <= 32 ? 32 : 0;
+    const int bkp = kmax <= 8 ? 8 : kmax == 9 ? 9 : kmax <= 12 ? 12 : kmax <= 16 ? 16 : kmax <= 32 ? 32 : 0;
     if (c->prob.dim == 2 && l >= 1 && d.bnnz > 0 && bkp > 0) {
       // fixed-width slots per column of B (zero padded)
       d.bkp = bkp;

@@ -1007,6 +1007,7 @@ hipError_t launch_lowrank_fused(const Launch& L, const DevLevel& lv, void* theta
 #define MGMC_LR_FUSED_KP(T)                  \
   do {                                       \
     if (lv.bkp == 8) MGMC_LR_FUSED(T, 8);    \
+    else if (lv.bkp == 9) MGMC_LR_FUSED(T, 9);   \
     else if (lv.bkp == 12) MGMC_LR_FUSED(T, 12); \
     else if (lv.bkp == 16) MGMC_LR_FUSED(T, 16); \
     else if (lv.bkp == 32) MGMC_LR_FUSED(T, 32); \

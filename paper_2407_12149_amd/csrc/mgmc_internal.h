@@ -52,7 +52,7 @@ struct DevLevel {
   // B^T theta without a separate pass over theta (2D one-launch sweeps): the
   // sweep kernels write B's weight times the swept value at each of B's
   // sites into bsnap.  Its layout gives every column of B the same number
-  // bkp (8, 12, 16 or 32) of slots: [nchains][beta][bkp], column j's entries
+  // bkp (8, 9, 12, 16 or 32) of slots: [nchains][beta][bkp], column j's entries
   // in the order of bidx, then zeros, which stay zero (bpval holds the
   // weights in the same slots).  bt_ptr / bt_ent list the slots whose site
   // lies in each 64 x TY tile, for the tile heights of the three 2D sweep

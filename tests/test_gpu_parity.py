@@ -174,6 +174,29 @@ def test_low_rank_step_forms(form):
                    options={mgmc.MGMC_OPT_LOWRANK_MFMA: form})
 
 
+@pytest.mark.parametrize("width", [4, 5])
+def test_low_rank_snapshot_wide_sensors(width):
+    """Sensors averaging width x width nodes (16 or 25 weights per observation
+    on the finest level, more slots on coarser ones), so the snapshot takes
+    its wider slot layouts."""
+    n = 127
+    face = workloads.face_array(n, 2, workloads.fourier_log_field(2, nmodes=8, seed=12))
+    prob, _ = make_problem(2, n, 4, 30.0, face=face, nchains=5)
+    rng = np.random.default_rng(20 + width)
+    m = 9
+    ptr, idx, val = [0], [], []
+    for _ in range(m):
+        x0, y0 = rng.integers(1, n - width, size=2)
+        for dy in range(width):
+            for dx in range(width):
+                idx.append((x0 + dx - 1) + n * (y0 + dy - 1))
+                val.append(1.0 / width ** 2)
+        ptr.append(len(idx))
+    obs = (np.array(ptr, dtype=np.int64), np.array(idx, dtype=np.int32), np.array(val), np.full(m, 1e-3))
+    y = workloads.observed_values(m, seed=13)
+    check_stepwise(prob, obs, 2, y=y, label=f"posterior 127^2 {width}x{width} sensors")
+
+
 def test_low_rank_snapshot_with_lds_tiled_sweeps():
     """The snapshot of the observation sites written by the LDS-tiled sweep
     form (tile height 32) on every level, 70 observations across tiles."""
