@@ -394,7 +394,7 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
       }
     }
     ivd[k] = invd[gi];
-    isd[k] = isqd[gi];
+    isd[k] = sqrt(ivd[k]);  // A_ii^{-1/2} as sqrt(1 / A_ii): one array fewer to read
     if (!RHSC) rhs[k] = f ? f[gi] : T(0);
   }
   // The passes this thread updates sites in ("slots"): on red-black levels
