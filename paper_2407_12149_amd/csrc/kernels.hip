@@ -93,7 +93,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const T* __restrict__ coef,
       cf[k][b++] = in ? stencil_entry<T, DIM>(coef, g, t, ia + 2 * k) : T(0);
     }
     ivd[k] = in ? invd[ia + 2 * k] : T(0);
-    isd[k] = in ? isqd[ia + 2 * k] : T(0);
+    isd[k] = sqrt(ivd[k]);  // A_ii^{-1/2} from the inverse diagonal (0 where absent)
   }
   const int cb = int(blockIdx.y) * cpb;
   const int ce = min(nchains, cb + cpb);
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_parity3d(const T* __restrict__
     for (int e = 0; e < 6; ++e)
       cf[k][e] = in ? coef[int64_t(tix[e < 3 ? e : 5 - e]) * g.Np + i + (e < 3 ? 0 : off[e])] : T(0);
     ivd[k] = in ? invd[i] : T(0);
-    isd[k] = in ? isqd[i] : T(0);
+    isd[k] = sqrt(ivd[k]);  // A_ii^{-1/2} from the inverse diagonal (0 where absent)
     rhs[k] = (in && f && fcs == 0) ? f[i] : T(0);
   }
   const int cb = int(blockIdx.y) * cpb;
