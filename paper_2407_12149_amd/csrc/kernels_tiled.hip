@@ -325,12 +325,16 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
   __shared__ __attribute__((aligned(16))) T spA[DMA && PROLONG ? CRY * RSP : 1],
       spB[DMA && PROLONG ? CRY * RSP : 1];
   static_assert(!DMA || (MC == 1 && CROSS), "LDS DMA tiles: 5-point levels, one chain per step");
-  // double precision draws its normals with the table-driven Box-Muller
+  // double precision draws its normals with the table-driven Box-Muller;
+  // the table's loads are issued first and written to LDS only after the
+  // stencil loads below are in flight too
   constexpr bool TAB = sizeof(T) == 8;
+  constexpr int KTAB = TAB ? (kBmTable + NT - 1) / NT : 1;
   __shared__ double stab[TAB ? kBmTable : 1];
+  double tabv[KTAB];
   if (TAB) {
-    for (int i = int(threadIdx.x); i < kBmTable; i += NT) stab[i] = bmtab[i];
-    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KTAB; ++k) tabv[k] = bmtab[min(int(threadIdx.x) + k * NT, kBmTable - 1)];
   }
   const int n = g.n;
   const int tx0 = int(blockIdx.x % tiles_x) * TX + 1;
@@ -515,6 +519,12 @@ __global__ __launch_bounds__(NT) void k_sweep2d_seg(
     }
   };
   constexpr int KF = (RX * RY + NT - 1) / NT;  // tile elements per thread
+  if (TAB) {
+#pragma unroll
+    for (int k = 0; k < KTAB; ++k)
+      if (int(threadIdx.x) + k * NT < kBmTable) stab[int(threadIdx.x) + k * NT] = tabv[k];
+    __syncthreads();
+  }
   if constexpr (DMA) {
     const int tid = int(threadIdx.x);
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
