@@ -30,32 +30,29 @@ constexpr int kFwdOrder2[4] = {0, 3, 1, 2};
 
 // (P psi)(x, y) for fine node (x, y): the coarse nodes J with |x - 2 J| <= 1
 // per axis are J0 = x >> 1 (offset x & 1) and, for odd x, J1 = (x + 1) >> 1
-// (offset -1); for even x, J1 = J0 enters with weight 0, so every node takes
-// the same four reads and the sum runs in a fixed order (J0y,J0x), (J0y,J1x),
-// (J1y,J0x), (J1y,J1x).  get(jx, jy) reads psi at coarse node (jx, jy).
+// (offset -1); for even x, J1 = J0, so every node takes the same four reads.
+// User weights: J1 = J0 enters with weight 0 and the sum runs in a fixed
+// order (J0y,J0x), (J0y,J1x), (J1y,J0x), (J1y,J1x).  get(jx, jy) reads psi
+// at coarse node (jx, jy).
 template <typename T, bool USERP, class Get>
 __device__ __forceinline__ T prolong_sum(Get get, const Geom& gc, const double* __restrict__ wP,
                                          int x, int y) {
   const int px = x & 1, py = y & 1;
   const int jx0 = x >> 1, jx1 = (x + 1) >> 1, jy0 = y >> 1, jy1 = (y + 1) >> 1;
   const T v00 = get(jx0, jy0), v01 = get(jx1, jy0), v10 = get(jx0, jy1), v11 = get(jx1, jy1);
-  T w00, w01, w10, w11;
-  if (USERP) {
-    auto W = [&](int jx, int jy, int dx, int dy) {
-      return T(wP[int64_t((dx + 1) + 3 * (dy + 1)) * gc.Np + pidx(gc, jx, jy, 0)]);
-    };
-    w00 = W(jx0, jy0, px, py);
-    w01 = px ? W(jx1, jy0, -1, py) : T(0);
-    w10 = py ? W(jx0, jy1, px, -1) : T(0);
-    w11 = (px && py) ? W(jx1, jy1, -1, -1) : T(0);
-  } else {
-    const T hx0 = px ? T(0.5) : T(1), hx1 = px ? T(0.5) : T(0);
-    const T hy0 = py ? T(0.5) : T(1), hy1 = py ? T(0.5) : T(0);
-    w00 = hx0 * hy0;
-    w01 = hx1 * hy0;
-    w10 = hx0 * hy1;
-    w11 = hx1 * hy1;
+  if (!USERP) {
+    // bilinear (weights 1, 1/2, 1/4): with J1 = J0 on an even axis, a
+    // quarter of the four reads is the interpolant in every parity case; it
+    // rounds like the weighted sum unless x and y are both odd
+    return T(0.25) * ((v00 + v10) + (v01 + v11));
   }
+  auto W = [&](int jx, int jy, int dx, int dy) {
+    return T(wP[int64_t((dx + 1) + 3 * (dy + 1)) * gc.Np + pidx(gc, jx, jy, 0)]);
+  };
+  const T w00 = W(jx0, jy0, px, py);
+  const T w01 = px ? W(jx1, jy0, -1, py) : T(0);
+  const T w10 = py ? W(jx0, jy1, px, -1) : T(0);
+  const T w11 = (px && py) ? W(jx1, jy1, -1, -1) : T(0);
   T s = w00 * v00;
   s += w01 * v01;
   s += w10 * v10;
