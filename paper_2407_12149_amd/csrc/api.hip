@@ -650,7 +650,9 @@ mgmc_status mgmc_setup(const mgmc_problem* problem, const mgmc_obs* obs, void* h
     c->L.bm_table = d;
   }
   const int top = c->levels - 1;
-  c->qnb = int(std::min<int64_t>(256, (c->lv[top].N + 4095) / 4096));
+  // QoI partial sums: about 1024 sites per block, at most 16384 partials
+  // for the final reduction (one block)
+  c->qnb = int(std::min<int64_t>(std::max<int64_t>(256, 16384 / problem->nchains), (c->lv[top].N + 1023) / 1024));
   if (c->qnb < 1) c->qnb = 1;
   if ((s = c->alloc(c->qpart, size_t(c->qnb) * problem->nchains)) != MGMC_OK) return cleanup(s);
   if ((s = c->alloc_bytes(c->fL, size_t(c->lv[top].g.Np) * c->esz)) != MGMC_OK) return cleanup(s);

@@ -527,54 +527,67 @@ __global__ __launch_bounds__(kBlock) void k_fill_zero(T* __restrict__ p, int64_t
   if (i < count) p[i] = T(0);
 }
 
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-  sh[threadIdx.x] = v;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (int(threadIdx.x) < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-    __syncthreads();
-  }
-  return sh[0];
-}
-
 // Per chain and block, the sum of F_i theta_i over the block's range of
-// sites, in site order per thread.  The weights of a batch of 16 sites per
-// thread are loaded first; a site with F_i = 0 then reads offset 0 of the
-// field (padding, zero) instead of theta_i, so that a QoI supported on part
-// of the domain reads only that part of the state.
+// sites (in site order per thread, then by wavefront and lane in a fixed
+// tree) into partial[chain][b].  Block (b, y) takes chains 8 y .. 8 y + 7
+// and loads the weights of KB sites per thread once for all of them; a
+// site with F_i = 0 reads offset 0 of the field (padding, zero) instead of
+// theta_i, so that a QoI supported on part of the domain reads only that
+// part of the states.
 template <typename T, int DIM>
 __global__ __launch_bounds__(kBlock) void k_qoi_partial(const T* __restrict__ theta, Geom g,
                                                         int64_t N, const double* __restrict__ F,
-                                                        double* __restrict__ partial, int nb) {
-  __shared__ double sh[kBlock];
-  const int c = blockIdx.y, b = blockIdx.x;
+                                                        double* __restrict__ partial, int nb,
+                                                        int nchains) {
+  constexpr int KB = 4, CG = kQoiChains, NW = kBlock / 64;
+  __shared__ double sh[NW][CG];
+  const int b = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c0 = int(blockIdx.y) * CG;
   const int64_t chunk = (N + nb - 1) / nb;
   const int64_t lo = int64_t(b) * chunk, hi = lo + chunk < N ? lo + chunk : N;
-  const T* th = theta + int64_t(c) * g.Np;
-  double acc = 0.0;
   const int n = g.n;
-  constexpr int KB = 16;
+  double acc[CG];
+#pragma unroll
+  for (int cc = 0; cc < CG; ++cc) acc[cc] = 0.0;
   for (int64_t l0 = lo + threadIdx.x; l0 < hi; l0 += KB * blockDim.x) {
     double fv[KB];
+    int64_t at[KB];
 #pragma unroll
     for (int u = 0; u < KB; ++u) {
       const int64_t lin = l0 + int64_t(u) * blockDim.x;
       fv[u] = F[lin < hi ? lin : lo];
       if (lin >= hi) fv[u] = 0.0;
     }
-    double tv[KB];
 #pragma unroll
     for (int u = 0; u < KB; ++u) {
       const int l32 = int(l0 + int64_t(u) * blockDim.x);  // N < 2^31 (checked at set-up)
       const int i1 = 1 + l32 % n, r = l32 / n;
       const int i2 = 1 + (DIM == 3 ? r % n : r), i3 = DIM == 3 ? 1 + r / n : 0;
-      tv[u] = double(th[fv[u] != 0.0 ? pidx(g, i1, i2, i3) : 0]);
+      at[u] = fv[u] != 0.0 ? pidx(g, i1, i2, i3) : 0;
     }
+    // chains past the last read the last chain again; their sums are not stored
 #pragma unroll
-    for (int u = 0; u < KB; ++u) acc += fv[u] * tv[u];
+    for (int cc = 0; cc < CG; ++cc) {
+      const T* th = theta + int64_t(min(c0 + cc, nchains - 1)) * g.Np;
+      double tv[KB];
+#pragma unroll
+      for (int u = 0; u < KB; ++u) tv[u] = double(th[at[u]]);
+#pragma unroll
+      for (int u = 0; u < KB; ++u) acc[cc] += fv[u] * tv[u];
+    }
   }
-  const double s = block_sum(acc, sh);
-  if (threadIdx.x == 0) partial[int64_t(c) * nb + b] = s;
+#pragma unroll
+  for (int cc = 0; cc < CG; ++cc) {
+    const double v = wave_sum(acc[cc]);
+    if (lane == 0) sh[wave][cc] = v;
+  }
+  __syncthreads();
+  if (int(threadIdx.x) < CG && c0 + int(threadIdx.x) < nchains) {
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) v += sh[w][threadIdx.x];
+    partial[int64_t(c0 + int(threadIdx.x)) * nb + b] = v;
+  }
 }
 
 // One block: wavefront w sums the partials of chains w, w + 4, ... in a
@@ -587,8 +600,16 @@ __global__ __launch_bounds__(kBlock) void k_qoi_final(const double* __restrict__
   const int64_t m = *mcur;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int c = wave; c < nchains; c += kBlock / 64) {
+    // 8 loads in flight per lane, added in block order
+    const double* pc = partial + int64_t(c) * nb;
     double acc = 0.0;
-    for (int b = lane; b < nb; b += 64) acc += partial[int64_t(c) * nb + b];
+    for (int b0 = lane; b0 < nb; b0 += 8 * 64) {
+      double v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] = b0 + 64 * k < nb ? pc[b0 + 64 * k] : 0.0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) acc += v[k];
+    }
     const double s = wave_sum(acc);
     if (lane == 0) qoi[(m - m0) * nchains + c] = s;
   }
@@ -1033,9 +1054,12 @@ hipError_t launch_fill_zero(const Launch& L, void* p, int64_t count) {
 
 hipError_t launch_qoi(const Launch& L, const DevLevel& fine, const void* theta, const double* F,
                       double* partial, int nb, double* qoi, int64_t m0) {
-  if (L.mcur == nullptr) return hipErrorInvalidValue;
-  dim3 grid(nb, L.nchains);
-  MGMC_DISPATCH(L, { k_qoi_partial<T, DIM><<<grid, kBlock, 0, L.stream>>>((const T*)theta, fine.g, fine.N, F, partial, nb); });
+  if (L.mcur == nullptr || nb < 1) return hipErrorInvalidValue;
+  dim3 grid(nb, (L.nchains + kQoiChains - 1) / kQoiChains);
+  MGMC_DISPATCH(L, {
+    k_qoi_partial<T, DIM><<<grid, kBlock, 0, L.stream>>>((const T*)theta, fine.g, fine.N, F, partial,
+                                                         nb, L.nchains);
+  });
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_qoi_final<<<1, kBlock, 0, L.stream>>>(partial, nb, qoi, const_cast<int64_t*>(L.mcur), m0,

@@ -210,7 +210,8 @@ hipError_t launch_lowrank_fused(const Launch& L, const DevLevel& lv, void* theta
                                 double* v_out);
 hipError_t launch_fill_zero(const Launch& L, void* p, int64_t count);
 // q = F^T theta per chain into qoi[m - m0][chain], then m += 1 (the last
-// launch of an update).
+// launches of an update).  partial: nb * nchains doubles.
+constexpr int kQoiChains = 8;  // chains per block of the partial sums
 hipError_t launch_qoi(const Launch& L, const DevLevel& fine, const void* theta, const double* F,
                       double* partial, int nb, double* qoi, int64_t m0);
 hipError_t launch_unpack(const Launch& L, const DevLevel& lv, const void* user, void* theta);
