@@ -280,41 +280,54 @@ template <typename T, int DIM, bool USERP>
 __global__ __launch_bounds__(kBlock) void k_restrict_residual(const T* __restrict__ r, Geom gf,
                                                               T* __restrict__ fcoarse, Geom gc,
                                                               const double* __restrict__ wP,
-                                                              LowRankRhs lr) {
+                                                              LowRankRhs lr, int cpb, int nchains) {
   constexpr int S = DIM == 2 ? 9 : 27;
   const int nc = gc.n;
   const int64_t total = int64_t(nc) * nc * (DIM == 3 ? nc : 1);
   const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (gid >= total) return;
-  const int c = blockIdx.y;
   int J1, J2, J3;
   unflatten<DIM>(gid, nc, J1, J2, J3);
   const int64_t iJ = pidx(gc, J1, J2, J3);
-  const T* rc = r + int64_t(c) * gf.Np;
-  T acc = T(0);
+  const int64_t i0 = pidx(gf, 2 * J1, 2 * J2, DIM == 3 ? 2 * J3 : 0);
+  // user weights are loaded once for the thread's group of chains
+  T wu[USERP ? S : 1];
+  if (USERP) {
 #pragma unroll
-  for (int t1 = 0; t1 < S; ++t1) {
-    const int ex = t1 % 3 - 1, ey = (t1 / 3) % 3 - 1, ez = DIM == 3 ? t1 / 9 - 1 : 0;
-    const T w = USERP ? T(wP[int64_t(t1) * gc.Np + iJ]) : T(multilinear(ex, ey, ez));
-    acc += w * rc[pidx(gf, 2 * J1 + ex, 2 * J2 + ey, DIM == 3 ? 2 * J3 + ez : 0)];
+    for (int t1 = 0; t1 < S; ++t1) wu[t1] = T(wP[int64_t(t1) * gc.Np + iJ]);
   }
-  fcoarse[int64_t(c) * gc.Np + iJ] = T(double(acc) - lowrank_rhs(lr, c, iJ));
+  const int cb = int(blockIdx.y) * cpb;
+  const int ce = min(nchains, cb + cpb);
+#pragma unroll 2
+  for (int c = cb; c < ce; ++c) {
+    const T* rc = r + int64_t(c) * gf.Np;
+    T acc = T(0);
+#pragma unroll
+    for (int t1 = 0; t1 < S; ++t1) {
+      const int ex = t1 % 3 - 1, ey = (t1 / 3) % 3 - 1, ez = DIM == 3 ? t1 / 9 - 1 : 0;
+      const T w = USERP ? wu[t1] : T(multilinear(ex, ey, ez));
+      acc += w * rc[i0 + poff(gf, ex, ey, ez)];
+    }
+    fcoarse[int64_t(c) * gc.Np + iJ] = T(double(acc) - lowrank_rhs(lr, c, iJ));
+  }
 }
 
 template <typename T, int DIM, bool USERP>
 __global__ __launch_bounds__(kBlock) void k_prolong(T* __restrict__ theta, Geom gf,
                                                     const T* __restrict__ psi, Geom gc,
-                                                    const double* __restrict__ wP) {
+                                                    const double* __restrict__ wP, int cpb,
+                                                    int nchains) {
+  constexpr int NT = DIM == 3 ? 8 : 4;  // coarse terms per fine site
   const int nf = gf.n;
   const int64_t total = int64_t(nf) * nf * (DIM == 3 ? nf : 1);
   const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (gid >= total) return;
-  const int c = blockIdx.y;
   int i[3];
   unflatten<DIM>(gid, nf, i[0], i[1], i[2]);
   // per axis the covering coarse nodes J0 = i >> 1 (offset i & 1) and, for
   // odd i, J1 = (i + 1) >> 1 (offset -1); for even i J1 = J0 with weight 0,
-  // so every site sums the same terms in the same order
+  // so every site sums the same terms in the same order.  Nodes and weights
+  // are formed once for the thread's group of chains.
   int J[3][2], D[3][2];
   T h[3][2];
 #pragma unroll
@@ -327,33 +340,40 @@ __global__ __launch_bounds__(kBlock) void k_prolong(T* __restrict__ theta, Geom 
     h[k][0] = odd ? T(0.5) : T(1);
     h[k][1] = odd ? T(0.5) : T(0);
   }
-  const T* ps = psi + int64_t(c) * gc.Np;
-  T s = T(0);
-  bool first = true;
+  int64_t jc[NT];
+  T w[NT];
+  int e = 0;
 #pragma unroll
   for (int a3 = 0; a3 < (DIM == 3 ? 2 : 1); ++a3)
 #pragma unroll
     for (int a2 = 0; a2 < 2; ++a2)
 #pragma unroll
-      for (int a1 = 0; a1 < 2; ++a1) {
-        const int64_t jc = pidx(gc, J[0][a1], J[1][a2], J[2][a3]);
-        T w;
+      for (int a1 = 0; a1 < 2; ++a1, ++e) {
+        jc[e] = pidx(gc, J[0][a1], J[1][a2], J[2][a3]);
         if (USERP) {
           const bool on = (a1 == 0 || (i[0] & 1)) && (a2 == 0 || (i[1] & 1)) &&
                           (DIM == 2 || a3 == 0 || (i[2] & 1));
           const int t = (D[0][a1] + 1) + 3 * (D[1][a2] + 1) + (DIM == 3 ? 9 * (D[2][a3] + 1) : 0);
-          w = on ? T(wP[int64_t(t) * gc.Np + jc]) : T(0);
+          w[e] = on ? T(wP[int64_t(t) * gc.Np + jc[e]]) : T(0);
         } else {
-          w = h[0][a1] * h[1][a2] * (DIM == 3 ? h[2][a3] : T(1));
-        }
-        if (first) {
-          s = w * ps[jc];
-          first = false;
-        } else {
-          s += w * ps[jc];
+          w[e] = h[0][a1] * h[1][a2] * (DIM == 3 ? h[2][a3] : T(1));
         }
       }
-  theta[int64_t(c) * gf.Np + pidx(gf, i[0], i[1], i[2])] += s;
+  const int64_t ii = pidx(gf, i[0], i[1], i[2]);
+  const int cb = int(blockIdx.y) * cpb;
+  const int ce = min(nchains, cb + cpb);
+  // two chains per trip, so the loads of the second overlap the first
+#pragma unroll 2
+  for (int c = cb; c < ce; ++c) {
+    const T* ps = psi + int64_t(c) * gc.Np;
+    T v[NT];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) v[k] = ps[jc[k]];
+    T s = w[0] * v[0];
+#pragma unroll
+    for (int k = 1; k < NT; ++k) s += w[k] * v[k];
+    theta[int64_t(c) * gf.Np + ii] += s;
+  }
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -754,28 +774,34 @@ hipError_t launch_restrict_2stage(const Launch& L, const DevLevel& fine, const v
                                   int64_t fcs, const LowRankRhs& lr) {
   if (scratch == nullptr || scratch == theta) return hipErrorInvalidValue;
   const int rcpb = chain_group(blocks_for(fine.N), L.nchains);
-  dim3 g1(blocks_for(fine.N), unsigned((L.nchains + rcpb - 1) / rcpb)), g2(blocks_for(coarse.N), L.nchains);
+  // FP32: a group of chains per thread amortises the index arithmetic; FP64
+  // moves twice the bytes and runs faster with one chain per thread
+  const int ccpb = L.fp32 ? chain_group(blocks_for(coarse.N), L.nchains) : 1;
+  dim3 g1(blocks_for(fine.N), unsigned((L.nchains + rcpb - 1) / rcpb));
+  dim3 g2(blocks_for(coarse.N), unsigned((L.nchains + ccpb - 1) / ccpb));
   MGMC_DISPATCH(L, {
     if (fine.cross)
       k_residual<T, DIM, true><<<g1, kBlock, 0, L.stream>>>((const T*)fine.coef, (const T*)theta, (const T*)f, fcs, fine.g, fine.N, (T*)scratch, rcpb, L.nchains);
     else
       k_residual<T, DIM, false><<<g1, kBlock, 0, L.stream>>>((const T*)fine.coef, (const T*)theta, (const T*)f, fcs, fine.g, fine.N, (T*)scratch, rcpb, L.nchains);
     if (fine.wP)
-      k_restrict_residual<T, DIM, true><<<g2, kBlock, 0, L.stream>>>((const T*)scratch, fine.g, (T*)coarse.f, coarse.g, fine.wP, lr);
+      k_restrict_residual<T, DIM, true><<<g2, kBlock, 0, L.stream>>>((const T*)scratch, fine.g, (T*)coarse.f, coarse.g, fine.wP, lr, ccpb, L.nchains);
     else
-      k_restrict_residual<T, DIM, false><<<g2, kBlock, 0, L.stream>>>((const T*)scratch, fine.g, (T*)coarse.f, coarse.g, nullptr, lr);
+      k_restrict_residual<T, DIM, false><<<g2, kBlock, 0, L.stream>>>((const T*)scratch, fine.g, (T*)coarse.f, coarse.g, nullptr, lr, ccpb, L.nchains);
   });
   return hipGetLastError();
 }
 
 hipError_t launch_prolong(const Launch& L, const DevLevel& fine, void* theta,
                           const DevLevel& coarse, const void* psi) {
-  dim3 grid(blocks_for(fine.N), L.nchains);
+  // FP32: a group of chains per thread (as in the restriction)
+  const int cpb = L.fp32 ? chain_group(blocks_for(fine.N), L.nchains) : 1;
+  dim3 grid(blocks_for(fine.N), unsigned((L.nchains + cpb - 1) / cpb));
   MGMC_DISPATCH(L, {
     if (fine.wP)
-      k_prolong<T, DIM, true><<<grid, kBlock, 0, L.stream>>>((T*)theta, fine.g, (const T*)psi, coarse.g, fine.wP);
+      k_prolong<T, DIM, true><<<grid, kBlock, 0, L.stream>>>((T*)theta, fine.g, (const T*)psi, coarse.g, fine.wP, cpb, L.nchains);
     else
-      k_prolong<T, DIM, false><<<grid, kBlock, 0, L.stream>>>((T*)theta, fine.g, (const T*)psi, coarse.g, nullptr);
+      k_prolong<T, DIM, false><<<grid, kBlock, 0, L.stream>>>((T*)theta, fine.g, (const T*)psi, coarse.g, nullptr, cpb, L.nchains);
   });
   return hipGetLastError();
 }
