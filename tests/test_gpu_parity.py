@@ -415,6 +415,42 @@ def test_fp32_tracks_fp64_on_common_random_numbers():
     s32.close()
 
 
+
+def test_fp32_3d_chain_groups_track_fp64():
+    """3D FP32 prolongation and residual restriction give each thread a group
+    of chains (here 2, 2 and 1 of 5 chains on the 127^3 level and its 63^3
+    coarse level); the paired FP64 run (one chain per thread) must track it
+    as in 2D, chain by chain."""
+    n = 127
+    face = workloads.face_array(n, 3, workloads.gaussian_log_field(3, 0.1, 1.0, seed=3, nfeatures=64))
+    prob64, obs = make_problem(3, n, 5, 1.0, face=face, beta=6, gamma=2.5e-5, nchains=5)
+    prob32 = dict(prob64, precision="fp32")
+    y = workloads.observed_values(6, seed=5)
+    F = torch.tensor(workloads.subcube_qoi(n, 3), device="cuda")
+    from paper_2407_12149_amd import mgmc
+    log("[fp32] paired run 127^3, 5 chains")
+    s64 = mgmc.Sampler(prob64, obs=obs)
+    s32 = mgmc.Sampler(prob32, obs=obs)
+    q64 = s64.posterior_sample(y, 0, 10, F=F)
+    q32 = s32.posterior_sample(y, 0, 10, F=F)
+    torch.cuda.synchronize()
+    for c in range(prob64["nchains"]):
+        dth = (s64.theta[c] - s32.theta[c].double()).abs()
+        rel = (dth / s64.theta[c].abs().max()).flatten()
+        med = rel.median().item()
+        # the last QoI of the pair differs by at most sum_i |F_i| |dtheta_i|
+        # of the final states (both reductions accumulate in FP64)
+        dq = abs(q64[-1, c].item() - q32[-1, c].item())
+        bound = (F.abs() * dth).sum().item()
+        slack = 1e-12 * (F.abs() * s64.theta[c].abs()).sum().item()
+        log(f"[fp32] chain {c}: last qoi diff {dq:.2e} (bound {bound:.2e}); state rel diff "
+            f"median {med:.2e} max {rel.max().item():.2e}")
+        assert dq <= bound + slack
+        assert med <= 1e-6
+        assert rel.max().item() <= 1e-2
+    s64.close()
+    s32.close()
+
 def test_batch_graph_equals_individual_runs():
     """Contexts of different sizes and dimensions advanced as branches of one
     graph give bitwise the same chains and QoI as separate runs."""
