@@ -57,13 +57,13 @@ _lib = None
 
 
 def load_library():
-    """Load libmgmc.so; raise if it is missing (build it with __graft_entry__.build())."""
+    """Load libmgmc.so; raise if it is missing (build it with python -m paper_2407_12149_amd.build)."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: the HIP library must be built "
-                          "(python -c 'import __graft_entry__ as g; g.build()')")
+                          "(python -m paper_2407_12149_amd.build)")
     lib = ctypes.CDLL(LIB_PATH)
     vp = ctypes.c_void_p
     lib.mgmc_setup.restype = ctypes.c_int

@@ -217,7 +217,8 @@ def subcube_qoi(n, dim, lo=0.25, hi=0.75):
 
 
 def config(name):
-    """Problem description for a named workload (input recipe)."""
+    """Problem description for a named workload: grid, levels, shift, coefficient
+    field, sensors and their noise, chains and QoI weights, all seeded."""
     if name == "prior63":
         n, dim = 63, 2
         return dict(name=name, dim=dim, n=n, levels=4, kappa2=100.0, face_coef=None,
