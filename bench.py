@@ -10,7 +10,7 @@ of all 8 chains (sweeps, low-rank corrections, transfers, coarsest sample and
 the QoI reduction).  ESS/s = steps x chains / (tau x seconds) with tau the
 Wolff IACT of the QoI series of the timed steps.
 
-Prints one JSON line.  --gpus N with N > 1 is refused: this build runs on one
+Prints one JSON line.  --gpus N with N > 1 is refused: the library runs on one
 GPU (chains would shard across GPUs without communication).
 """
 import argparse
@@ -231,7 +231,7 @@ def main():
         print(json.dumps({"copy_ref_bytes": src.numel() * 8, "repeats": 20}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; chains shard across GPUs "
+        print(json.dumps({"error": "the library runs on one GPU; chains shard across GPUs "
                           "without communication but no multi-GPU path is built"}))
         sys.exit(2)
 
