@@ -637,26 +637,33 @@ __global__ __launch_bounds__(kBlock) void k_qoi_final(const double* __restrict__
   if (threadIdx.x == 0) *mcur = m + 1;
 }
 
+// Copies between the user's unpadded [chain][N] states and the padded
+// layout; a thread takes one site for a group of cpb chains, so the site's
+// padded index is formed once for the group.
 template <typename T, int DIM>
 __global__ __launch_bounds__(kBlock) void k_unpack(const T* __restrict__ user, T* __restrict__ th,
-                                                   Geom g, int64_t N) {
+                                                   Geom g, int64_t N, int cpb, int nchains) {
   const int64_t lin = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (lin >= N) return;
-  const int c = blockIdx.y;
   int i1, i2, i3;
   unflatten<DIM>(lin, g.n, i1, i2, i3);
-  th[int64_t(c) * g.Np + pidx(g, i1, i2, i3)] = user[int64_t(c) * N + lin];
+  const int64_t ii = pidx(g, i1, i2, i3);
+  const int cb = int(blockIdx.y) * cpb, ce = min(nchains, cb + cpb);
+#pragma unroll 2
+  for (int c = cb; c < ce; ++c) th[int64_t(c) * g.Np + ii] = user[int64_t(c) * N + lin];
 }
 
 template <typename T, int DIM>
 __global__ __launch_bounds__(kBlock) void k_pack(const T* __restrict__ th, T* __restrict__ user,
-                                                 Geom g, int64_t N) {
+                                                 Geom g, int64_t N, int cpb, int nchains) {
   const int64_t lin = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (lin >= N) return;
-  const int c = blockIdx.y;
   int i1, i2, i3;
   unflatten<DIM>(lin, g.n, i1, i2, i3);
-  user[int64_t(c) * N + lin] = th[int64_t(c) * g.Np + pidx(g, i1, i2, i3)];
+  const int64_t ii = pidx(g, i1, i2, i3);
+  const int cb = int(blockIdx.y) * cpb, ce = min(nchains, cb + cpb);
+#pragma unroll 2
+  for (int c = cb; c < ce; ++c) user[int64_t(c) * N + lin] = th[int64_t(c) * g.Np + ii];
 }
 
 template <typename T, int DIM>
@@ -1093,15 +1100,18 @@ hipError_t launch_qoi(const Launch& L, const DevLevel& fine, const void* theta, 
   return hipGetLastError();
 }
 
+// chain groups in FP32 (as in the prolongation), one chain per thread in FP64
 hipError_t launch_unpack(const Launch& L, const DevLevel& lv, const void* user, void* theta) {
-  dim3 grid(blocks_for(lv.N), L.nchains);
-  MGMC_DISPATCH(L, { k_unpack<T, DIM><<<grid, kBlock, 0, L.stream>>>((const T*)user, (T*)theta, lv.g, lv.N); });
+  const int cpb = L.fp32 ? chain_group(blocks_for(lv.N), L.nchains) : 1;
+  dim3 grid(blocks_for(lv.N), unsigned((L.nchains + cpb - 1) / cpb));
+  MGMC_DISPATCH(L, { k_unpack<T, DIM><<<grid, kBlock, 0, L.stream>>>((const T*)user, (T*)theta, lv.g, lv.N, cpb, L.nchains); });
   return hipGetLastError();
 }
 
 hipError_t launch_pack(const Launch& L, const DevLevel& lv, const void* theta, void* user) {
-  dim3 grid(blocks_for(lv.N), L.nchains);
-  MGMC_DISPATCH(L, { k_pack<T, DIM><<<grid, kBlock, 0, L.stream>>>((const T*)theta, (T*)user, lv.g, lv.N); });
+  const int cpb = L.fp32 ? chain_group(blocks_for(lv.N), L.nchains) : 1;
+  dim3 grid(blocks_for(lv.N), unsigned((L.nchains + cpb - 1) / cpb));
+  MGMC_DISPATCH(L, { k_pack<T, DIM><<<grid, kBlock, 0, L.stream>>>((const T*)theta, (T*)user, lv.g, lv.N, cpb, L.nchains); });
   return hipGetLastError();
 }
 
