@@ -17,6 +17,20 @@ from . import build as _build
 
 _LIB = None
 
+OP_FD, OP_FEM_Q1, OP_SSL13 = 0, 1, 2
+SAMPLER_MGMC, SAMPLER_GIBBS = 0, 1
+
+
+class OraOptions(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int), ("n", ctypes.c_int), ("levels", ctypes.c_int),
+        ("kappa2", ctypes.c_double), ("scale", ctypes.c_double),
+        ("face_coef", ctypes.POINTER(ctypes.c_double)), ("prolong_w", ctypes.POINTER(ctypes.c_double)),
+        ("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("seed", ctypes.c_uint64),
+        ("op", ctypes.c_int), ("gamma", ctypes.c_int), ("omega", ctypes.c_double),
+        ("nu0", ctypes.c_int), ("sampler", ctypes.c_int),
+    ]
+
 _c_double_p = ctypes.POINTER(ctypes.c_double)
 _c_i64_p = ctypes.POINTER(ctypes.c_int64)
 _c_i32_p = ctypes.POINTER(ctypes.c_int32)
@@ -33,6 +47,11 @@ def load():
     lib = ctypes.CDLL(_build.LIB)
     lib.ora_philox4x32_10.argtypes = [_c_u32_p, _c_u32_p, _c_u32_p]
     lib.ora_normal_pair.argtypes = [_c_u32_p, _c_u32_p, _c_double_p]
+    lib.ora_create_ex.restype = ctypes.c_void_p
+    lib.ora_create_ex.argtypes = [ctypes.POINTER(OraOptions)]
+    lib.ora_set_noise_log.argtypes = [ctypes.c_void_p, _c_u32_p, ctypes.c_int64]
+    lib.ora_noise_log_len.restype = ctypes.c_int64
+    lib.ora_noise_log_len.argtypes = [ctypes.c_void_p]
     lib.ora_create.restype = ctypes.c_void_p
     lib.ora_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                ctypes.c_double, _c_double_p, _c_double_p, ctypes.c_int,
@@ -91,13 +110,16 @@ class Oracle:
     """One problem hierarchy of the oracle (prior, or posterior after set_obs)."""
 
     def __init__(self, dim, n, levels, kappa2, scale=0.0, face_coef=None, prolong_w=None,
-                 nu1=1, nu2=1, seed=0):
+                 nu1=1, nu2=1, seed=0, op=OP_FD, gamma=1, omega=1.0, nu0=0, sampler=SAMPLER_MGMC):
         lib = load()
         self._keep = []
         fc = None if face_coef is None else np.ascontiguousarray(face_coef, dtype=np.float64)
         pw = None if prolong_w is None else np.ascontiguousarray(prolong_w, dtype=np.float64)
         self._keep += [fc, pw]
-        h = lib.ora_create(dim, n, levels, kappa2, scale, _dp(fc), _dp(pw), nu1, nu2, seed)
+        opts = OraOptions(dim=dim, n=n, levels=levels, kappa2=kappa2, scale=scale,
+                          face_coef=_dp(fc), prolong_w=_dp(pw), nu1=nu1, nu2=nu2, seed=seed,
+                          op=op, gamma=gamma, omega=omega, nu0=nu0, sampler=sampler)
+        h = lib.ora_create_ex(ctypes.byref(opts))
         if not h:
             raise ValueError("oracle: " + lib.ora_last_error().decode())
         self.h = h
@@ -141,6 +163,20 @@ class Oracle:
 
     def noise_drawn(self):
         return int(self.lib.ora_noise_drawn(self.h))
+
+    def log_noise(self, fn, cap=1 << 20):
+        """Run fn() with draw logging on; returns an [draws, 7] uint32 array of
+        (key0, key1, counter0..3, slot) in draw order."""
+        buf = np.zeros((cap, 7), dtype=np.uint32)
+        self.lib.ora_set_noise_log(self.h, buf.ctypes.data_as(_c_u32_p), cap)
+        try:
+            fn()
+            k = int(self.lib.ora_noise_log_len(self.h))
+        finally:
+            self.lib.ora_set_noise_log(self.h, None, 0)
+        if k > cap:
+            raise ValueError("noise log overflow")
+        return buf[:k].copy()
 
     def cycle(self, theta, chain=0, m=0):
         t = np.ascontiguousarray(theta, dtype=np.float64).copy()

@@ -232,7 +232,7 @@ typedef struct {
   uint32_t* pair;
   uint8_t* slot;
   int32_t* order;      /* sites in forward colour order */
-  int64_t cstart[9];   /* order[cstart[q] .. cstart[q+1]) has colour fwd_order[q] */
+  int64_t cstart[10];  /* order[cstart[q] .. cstart[q+1]) has colour fwd_order[q] */
   int64_t nsupp[2];    /* rows where C_dir (hence G_dir) can be non-zero */
   int32_t* supp[2];
   double* G[2];        /* nsupp x beta, row-major */
@@ -240,6 +240,12 @@ typedef struct {
 
 struct ora_problem {
   int dim, n, L, nu1, nu2, ncolours;
+  int q;        /* colour classes per axis: 2 for 3^d-point stencils, 3 for 5^d-point */
+  int op;       /* fine operator: ORA_OP_FD, ORA_OP_FEM_Q1, ORA_OP_SSL13 */
+  int cycle_gamma; /* recursive calls made by levels below the finest (Alg. 1) */
+  int nu0;      /* 0: exact coarsest sample; k >= 1: Alg. 5 with k symmetric sweeps */
+  int sampler;  /* ORA_SAMPLER_MGMC or ORA_SAMPLER_GIBBS */
+  double omega; /* SOR relaxation of the Gibbs smoother (Sec. 3.3, 3.4) */
   double kappa2, scale, h;
   uint32_t seed_lo;
   level* lv;
@@ -249,6 +255,8 @@ struct ora_problem {
   double* U; /* coarsest Cholesky factor, upper triangular, row-major n0 x n0 */
   int noise_mode;
   int64_t impulse, drawn;
+  uint32_t* noise_log; /* test hook: 7 words per draw (key, counter, slot) */
+  int64_t noise_log_cap, noise_log_len;
   double restrict_scale; /* 1 in the method; other values only in planted-mistake tests */
 };
 
@@ -258,7 +266,12 @@ struct ora_problem {
 static const int FWD2[4] = {0, 3, 1, 2};
 static const int FWD3[8] = {0, 3, 5, 6, 1, 2, 4, 7};
 
-static int fwd_colour(const ora_problem* p, int q) { return p->dim == 2 ? FWD2[q] : FWD3[q]; }
+/* With three classes per axis (5 x 5 stencils, 2D) the nine colours
+ * c = (i_1 mod 3) + 3 (i_2 mod 3) are swept in ascending order. */
+static int fwd_colour(const ora_problem* p, int q) {
+  if (p->q == 3) return q;
+  return p->dim == 2 ? FWD2[q] : FWD3[q];
+}
 
 static void coords(int dim, int n, int64_t lin, int* i) {
   for (int k = 0; k < dim; ++k) {
@@ -286,6 +299,107 @@ static double face_value(const ora_problem* p, const double* face, int k, const 
     mult *= e;
   }
   return face[(int64_t)k * per + idx];
+}
+
+/* Lowest-order conforming (bilinear, Q1) finite elements of Sec. 5.1.1 for
+ * -Laplace + kappa^2 on the uniform grid of n x n interior nodes, assembled
+ * cell by cell from the element matrices of a square of side h (nodes in
+ * counter-clockwise order from the lower left):
+ *   stiffness  (1/6) [4 -1 -2 -1; -1 4 -1 -2; -2 -1 4 -1; -1 -2 -1 4],
+ *   mass       (h^2/36) [4 2 1 2; 2 4 2 1; 1 2 4 2; 2 1 2 4];
+ * rows and columns of boundary nodes are dropped (u = 0 there).  The result
+ * is scaled by s / h^2, so the default s = h^2 gives the Galerkin matrix of
+ * the bilinear form itself (eq. def-A_ell). */
+static int build_fem_q1(ora_problem* p) {
+  level* f = &p->lv[p->L];
+  int n = p->n;
+  int64_t cap = (int64_t)(n + 1) * (n + 1) * 16, nnz = 0;
+  int64_t* ri = malloc((size_t)cap * sizeof(int64_t));
+  int32_t* ci = malloc((size_t)cap * sizeof(int32_t));
+  double* vi = malloc((size_t)cap * sizeof(double));
+  if (!ri || !ci || !vi) return -1;
+  static const double KE[4][4] = {{4, -1, -2, -1}, {-1, 4, -1, -2}, {-2, -1, 4, -1}, {-1, -2, -1, 4}};
+  static const double ME[4][4] = {{4, 2, 1, 2}, {2, 4, 2, 1}, {1, 2, 4, 2}, {2, 1, 2, 4}};
+  static const int CX[4] = {0, 1, 1, 0}, CY[4] = {0, 0, 1, 1};
+  double h = p->h, sc = p->scale / (h * h);
+  for (int cy = 0; cy <= n; ++cy)
+    for (int cx = 0; cx <= n; ++cx) {
+      /* cell with lower-left node (cx, cy); nodes 0..n+1 per axis */
+      for (int a = 0; a < 4; ++a) {
+        int ia[2] = {cx + CX[a], cy + CY[a]};
+        if (ia[0] < 1 || ia[0] > n || ia[1] < 1 || ia[1] > n) continue;
+        for (int b = 0; b < 4; ++b) {
+          int ib[2] = {cx + CX[b], cy + CY[b]};
+          if (ib[0] < 1 || ib[0] > n || ib[1] < 1 || ib[1] > n) continue;
+          double v = KE[a][b] / 6.0 + p->kappa2 * (h * h) * ME[a][b] / 36.0;
+          ri[nnz] = linear(2, n, ia);
+          ci[nnz] = (int32_t)linear(2, n, ib);
+          vi[nnz] = sc * v;
+          ++nnz;
+        }
+      }
+    }
+  int rc = csr_from_coo(&f->A, f->N, f->N, nnz, ri, ci, vi);
+  free(ri);
+  free(ci);
+  free(vi);
+  return rc;
+}
+
+/* Squared shifted Laplace (Sec. 5.1.1, eq. squared_shifted_laplace),
+ * (-Laplace + kappa^2)^2 = Laplace^2 - 2 kappa^2 Laplace + kappa^4, 2D:
+ *   s [ h^-4 (13-point biharmonic stencil) + 2 kappa^2 h^-2 (5-point -Laplace)
+ *       + kappa^4 ],
+ * the biharmonic stencil with weight 20 at the centre, -8 at the four axis
+ * neighbours, 2 at the four diagonal neighbours and 1 at the four nodes two
+ * steps along an axis (Bjorstad's 13-point difference).  Boundary
+ * conditions u = 0 and du/dn = 0 (clamped): nodes on the boundary are zero,
+ * and the ghost node one step outside the boundary takes the value of its
+ * mirror image inside (central difference of du/dn = 0), so a reach past the
+ * boundary adds its weight to the interior mirror node. */
+static int build_ssl13(ora_problem* p) {
+  level* f = &p->lv[p->L];
+  int n = p->n;
+  int64_t N = f->N, cap = N * 13 + N * 5 + N, nnz = 0;
+  int64_t* ri = malloc((size_t)cap * sizeof(int64_t));
+  int32_t* ci = malloc((size_t)cap * sizeof(int32_t));
+  double* vi = malloc((size_t)cap * sizeof(double));
+  if (!ri || !ci || !vi) return -1;
+  static const int OFF[13][2] = {{0, 0},  {1, 0},  {-1, 0}, {0, 1},  {0, -1}, {1, 1},  {1, -1},
+                                 {-1, 1}, {-1, -1}, {2, 0},  {-2, 0}, {0, 2},  {0, -2}};
+  static const double WB[13] = {20, -8, -8, -8, -8, 2, 2, 2, 2, 1, 1, 1, 1};
+  double s = p->scale, h = p->h, ih2 = 1.0 / (h * h), ih4 = ih2 * ih2, k2 = p->kappa2;
+  int i[2], j[2];
+  for (int64_t lin = 0; lin < N; ++lin) {
+    coords(2, n, lin, i);
+    for (int t = 0; t < 13; ++t) {
+      int skip = 0;
+      for (int k = 0; k < 2; ++k) {
+        j[k] = i[k] + OFF[t][k];
+        if (j[k] == 0 || j[k] == n + 1) skip = 1;   /* boundary node: u = 0 */
+        if (j[k] == -1) j[k] = 1;                   /* mirror of the ghost node */
+        if (j[k] == n + 2) j[k] = n;
+      }
+      if (skip) continue;
+      ri[nnz] = lin; ci[nnz] = (int32_t)linear(2, n, j); vi[nnz] = s * ih4 * WB[t]; ++nnz;
+    }
+    for (int t = 0; t < 5; ++t) {
+      int skip = 0;
+      for (int k = 0; k < 2; ++k) {
+        j[k] = i[k] + OFF[t][k];
+        if (j[k] < 1 || j[k] > n) skip = 1;
+      }
+      if (skip) continue;
+      double w = (t == 0) ? 4.0 : -1.0;
+      ri[nnz] = lin; ci[nnz] = (int32_t)linear(2, n, j); vi[nnz] = s * 2.0 * k2 * ih2 * w; ++nnz;
+    }
+    ri[nnz] = lin; ci[nnz] = (int32_t)lin; vi[nnz] = s * k2 * k2; ++nnz;
+  }
+  int rc = csr_from_coo(&f->A, N, N, nnz, ri, ci, vi);
+  free(ri);
+  free(ci);
+  free(vi);
+  return rc;
 }
 
 /* Finite-difference operator of Sec. 5.1.1 in divergence form with face
@@ -378,15 +492,20 @@ static int build_colouring(ora_problem* p, int l) {
   lv->diag = malloc((size_t)N * sizeof(double));
   if (!lv->colour || !lv->pair || !lv->slot || !lv->order || !lv->diag) return -1;
   int i[3];
+  int q = p->q;
   for (int64_t lin = 0; lin < N; ++lin) {
     coords(d, n, lin, i);
-    int c = 0;
+    int c = 0, mult = 1;
     int s[3] = {0, 0, 0}, m[3] = {1, 1, 1};
     for (int k = 0; k < d; ++k) {
-      int par = i[k] & 1;
-      c |= par << k;
-      s[k] = (i[k] - 1) >> 1;
-      m[k] = par ? (n + 1) / 2 : (n - 1) / 2;
+      /* class of the axis coordinate, position in its sublattice, and the
+       * number of coordinates 1..n in the class */
+      int par = i[k] % q;
+      int first = par == 0 ? q : par;
+      c += par * mult;
+      mult *= q;
+      s[k] = (i[k] - 1) / q;
+      m[k] = first <= n ? (n - first) / q + 1 : 0;
     }
     lv->colour[lin] = (uint8_t)c;
     lv->pair[lin] = (uint32_t)((s[0] >> 1) + (int64_t)((m[0] + 1) / 2) * (s[1] + (int64_t)m[1] * s[2]));
@@ -492,19 +611,31 @@ static int coarse_cholesky(ora_problem* p) {
   return 0;
 }
 
-ora_problem* ora_create(int dim, int n, int levels, double kappa2, double scale,
-                        const double* face_coef, const double* prolong_w, int nu1, int nu2,
-                        uint64_t seed) {
+ora_problem* ora_create_ex(const ora_options* o) {
+  int dim = o->dim, n = o->n, levels = o->levels, nu1 = o->nu1, nu2 = o->nu2;
+  g_err[0] = 0;
   if (dim != 2 && dim != 3) { set_err("dim must be 2 or 3"); return NULL; }
   if (n < 1 || ((n + 1) & n) != 0) { set_err("n must be 2^k - 1"); return NULL; }
   int k = 0;
   while ((1 << k) < n + 1) ++k;
   if (levels < 1 || levels > k) { set_err("levels out of range"); return NULL; }
   if (nu1 < 1 || nu2 < 1 || nu1 + nu2 > 16) { set_err("nu1, nu2 out of range"); return NULL; }
+  if (o->op < ORA_OP_FD || o->op > ORA_OP_SSL13) { set_err("unknown operator"); return NULL; }
+  if (o->op != ORA_OP_FD && (dim != 2 || o->face_coef)) {
+    set_err("the FEM and squared shifted Laplace operators are 2D with a = 1");
+    return NULL;
+  }
+  double omega = o->omega > 0.0 ? o->omega : 1.0;
+  if (!(omega < 2.0)) { set_err("omega must lie in (0, 2)"); return NULL; }
+  int gamma = o->gamma > 0 ? o->gamma : 1;
+  if (gamma > 3 || o->nu0 < 0 || o->nu0 > 8) { set_err("gamma or nu0 out of range"); return NULL; }
+  if (o->sampler == ORA_SAMPLER_GIBBS && levels != 1) { set_err("the Gibbs sampler runs on one level"); return NULL; }
+  if (o->sampler != ORA_SAMPLER_MGMC && o->sampler != ORA_SAMPLER_GIBBS) { set_err("unknown sampler"); return NULL; }
   int n0 = ((n + 1) >> (levels - 1)) - 1;
   int64_t N0 = 1;
   for (int j = 0; j < dim; ++j) N0 *= n0;
-  if (N0 > 8192) { set_err("coarsest level too large for a dense factor"); return NULL; }
+  int exact_coarse = o->sampler == ORA_SAMPLER_MGMC && o->nu0 == 0;
+  if (exact_coarse && N0 > 8192) { set_err("coarsest level too large for a dense factor"); return NULL; }
   ora_problem* p = calloc(1, sizeof *p);
   if (!p) return NULL;
   p->dim = dim;
@@ -512,11 +643,17 @@ ora_problem* ora_create(int dim, int n, int levels, double kappa2, double scale,
   p->L = levels - 1;
   p->nu1 = nu1;
   p->nu2 = nu2;
-  p->ncolours = 1 << dim;
-  p->kappa2 = kappa2;
+  p->op = o->op;
+  p->q = o->op == ORA_OP_SSL13 ? 3 : 2;
+  p->ncolours = dim == 2 ? p->q * p->q : 8;
+  p->cycle_gamma = gamma;
+  p->nu0 = o->nu0;
+  p->sampler = o->sampler;
+  p->omega = omega;
+  p->kappa2 = o->kappa2;
   p->h = 1.0 / (n + 1);
-  p->scale = scale > 0.0 ? scale : pow(p->h, dim);
-  p->seed_lo = (uint32_t)seed;
+  p->scale = o->scale > 0.0 ? o->scale : pow(p->h, dim);
+  p->seed_lo = (uint32_t)o->seed;
   p->restrict_scale = 1.0;
   p->lv = calloc((size_t)levels, sizeof(level));
   if (!p->lv) { free(p); return NULL; }
@@ -526,9 +663,12 @@ ora_problem* ora_create(int dim, int n, int levels, double kappa2, double scale,
     for (int j = 0; j < dim; ++j) N *= nl;
     p->lv[l].N = N;
   }
-  if (build_fine_operator(p, face_coef)) goto fail;
+  int rc = o->op == ORA_OP_FEM_Q1 ? build_fem_q1(p)
+           : o->op == ORA_OP_SSL13 ? build_ssl13(p)
+                                   : build_fine_operator(p, o->face_coef);
+  if (rc) goto fail;
   for (int l = p->L; l >= 1; --l) {
-    if (build_prolongation(p, l, (l == p->L) ? prolong_w : NULL)) goto fail;
+    if (build_prolongation(p, l, (l == p->L) ? o->prolong_w : NULL)) goto fail;
     /* Galerkin triple product A_{l-1} = P^T A_l P (eq. A_ell_1_B_ell_1). */
     csr AP;
     memset(&AP, 0, sizeof AP);
@@ -538,7 +678,7 @@ ora_problem* ora_create(int dim, int n, int levels, double kappa2, double scale,
   }
   for (int l = 0; l <= p->L; ++l)
     if (build_colouring(p, l)) goto fail;
-  if (coarse_cholesky(p)) goto fail;
+  if (exact_coarse && coarse_cholesky(p)) goto fail;
   return p;
 fail:
   if (g_err[0] == 0) set_err("allocation failed");
@@ -546,12 +686,30 @@ fail:
   return NULL;
 }
 
+ora_problem* ora_create(int dim, int n, int levels, double kappa2, double scale,
+                        const double* face_coef, const double* prolong_w, int nu1, int nu2,
+                        uint64_t seed) {
+  ora_options o;
+  memset(&o, 0, sizeof o);
+  o.dim = dim;
+  o.n = n;
+  o.levels = levels;
+  o.kappa2 = kappa2;
+  o.scale = scale;
+  o.face_coef = face_coef;
+  o.prolong_w = prolong_w;
+  o.nu1 = nu1;
+  o.nu2 = nu2;
+  o.seed = seed;
+  return ora_create_ex(&o);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Observations and the low-rank smoother setup (Alg. 3)                     */
 /* ------------------------------------------------------------------------ */
 
-/* C = M^{-1} B for M = D + L (forward) or D + L^T (backward) under the colour
- * ordering, one column at a time by substitution in sweep order; rows where
+/* C = M^{-1} B for M = D/omega + L (forward) or D/omega + L^T (backward)
+ * under the colour ordering (Alg. 3 setup, eq. Bellstar_definition), one column at a time by substitution in sweep order; rows where
  * any column is non-zero form the support of C and of G = C S^{-1}. */
 static int lowrank_setup(ora_problem* p, int l, int dir) {
   level* lv = &p->lv[l];
@@ -577,7 +735,7 @@ static int lowrank_setup(ora_problem* p, int l, int dir) {
         double s = b[i];
         for (int64_t e = lv->A.ptr[i]; e < lv->A.ptr[i + 1]; ++e)
           if (lv->A.col[e] != i) s -= lv->A.val[e] * x[lv->A.col[e]];
-        x[i] = s / lv->diag[i];
+        x[i] = (p->omega * s) / lv->diag[i];
       }
     }
     int64_t c = 0;
@@ -681,6 +839,12 @@ static int lowrank_setup(ora_problem* p, int l, int dir) {
   return 0;
 }
 
+/* Level 0 is updated by Gibbs sweeps (Alg. 5, or the standalone Gibbs
+ * sampler) rather than sampled exactly. */
+static int smoothed_coarsest(const ora_problem* p) {
+  return p->sampler == ORA_SAMPLER_GIBBS || p->nu0 > 0;
+}
+
 int ora_set_obs(ora_problem* p, int beta, const int64_t* ptr, const int32_t* idx,
                 const double* val, const double* gamma) {
   if (!p || beta < 0 || (beta > 0 && (!ptr || !idx || !val || !gamma))) {
@@ -718,11 +882,11 @@ int ora_set_obs(ora_problem* p, int beta, const int64_t* ptr, const int32_t* idx
     if (csr_matmul(&p->lv[l].PT, &p->lv[l].B, &p->lv[l - 1].B)) return -1;
   for (int l = 0; l <= p->L; ++l)
     if (csr_transpose(&p->lv[l].B, &p->lv[l].BT)) return -1;
-  for (int l = 1; l <= p->L; ++l)
+  int l0 = smoothed_coarsest(p) ? 0 : 1;
+  for (int l = l0; l <= p->L; ++l)
     for (int dir = 0; dir < 2; ++dir)
       if (lowrank_setup(p, l, dir)) return -1;
-  int rc = coarse_cholesky(p);
-  return rc;
+  return smoothed_coarsest(p) ? 0 : coarse_cholesky(p);
 }
 
 void ora_set_rhs(ora_problem* p, const double* f) {
@@ -756,15 +920,37 @@ int64_t ora_noise_drawn(const ora_problem* p) { return p->drawn; }
 
 void ora_set_restriction_scale(ora_problem* p, double scale) { p->restrict_scale = scale; }
 
+void ora_set_noise_log(ora_problem* p, uint32_t* buf, int64_t cap) {
+  p->noise_log = buf;
+  p->noise_log_cap = buf ? cap : 0;
+  p->noise_log_len = 0;
+}
+
+int64_t ora_noise_log_len(const ora_problem* p) { return p->noise_log_len; }
+
 /* ------------------------------------------------------------------------ */
 /* The Markov update                                                         */
 /* ------------------------------------------------------------------------ */
 
-/* Noise stream.  Key = (seed low word, chain); counter = (pair, level<<8 |
- * sweep<<4 | colour, sample index m, tag) with tag 0 site noise, 1 the
- * low-rank normals zeta_j, 2 the coarsest-level normals. */
+/* Noise stream.  Key = (seed low word, chain); counter = (pair, visit<<16 |
+ * level<<8 | sweep<<4 | colour, sample index m, tag) with tag 0 site noise,
+ * 1 the low-rank normals zeta_j, 2 the coarsest-level normals; visit is 0
+ * except on coarse levels that a W-cycle calls more than once. */
 static double draw(ora_problem* p, uint32_t chain, uint32_t m, uint32_t word1, uint32_t pair,
                    int slot, uint32_t tag) {
+  if (p->noise_log) {
+    if (p->noise_log_len < p->noise_log_cap) {
+      uint32_t* e = p->noise_log + 7 * p->noise_log_len;
+      e[0] = p->seed_lo;
+      e[1] = chain;
+      e[2] = pair;
+      e[3] = word1;
+      e[4] = m;
+      e[5] = tag;
+      e[6] = (uint32_t)slot;
+    }
+    p->noise_log_len++;
+  }
   if (p->noise_mode == 1) {
     p->drawn++;
     return 0.0;
@@ -788,6 +974,7 @@ typedef struct {
   double* r;      /* residual scratch (N_L) */
   double* w;      /* beta */
   double* t;      /* coarse scratch (N_0) */
+  uint32_t* visits; /* per level: calls so far in the current update */
 } workspace;
 
 static void ws_free(workspace* ws, int L) {
@@ -801,6 +988,7 @@ static void ws_free(workspace* ws, int L) {
   free(ws->r);
   free(ws->w);
   free(ws->t);
+  free(ws->visits);
 }
 
 static int ws_alloc(const ora_problem* p, workspace* ws) {
@@ -812,7 +1000,8 @@ static int ws_alloc(const ora_problem* p, workspace* ws) {
   ws->r = malloc((size_t)NL * sizeof(double));
   ws->w = malloc((size_t)(p->beta + 1) * sizeof(double));
   ws->t = malloc((size_t)p->lv[0].N * sizeof(double));
-  if (!ws->theta || !ws->f || !ws->g || !ws->r || !ws->w || !ws->t) return -1;
+  ws->visits = calloc((size_t)p->L + 1, sizeof(uint32_t));
+  if (!ws->theta || !ws->f || !ws->g || !ws->r || !ws->w || !ws->t || !ws->visits) return -1;
   for (int l = 0; l < p->L; ++l) {
     ws->theta[l] = malloc((size_t)p->lv[l].N * sizeof(double));
     ws->f[l] = malloc((size_t)p->lv[l].N * sizeof(double));
@@ -821,21 +1010,25 @@ static int ws_alloc(const ora_problem* p, workspace* ws) {
   return 0;
 }
 
-/* Gibbs smoother with low-rank correction, omega = 1 (Alg. 3):
+/* Gibbs smoother with low-rank correction (Alg. 3), SOR relaxation omega:
  *   g = f + B xi_LR, xi_LR = Gamma^{-1/2} zeta;
- *   theta* = theta + M^{-1}(g + xi_diag - A theta), xi_diag ~ N(0, D), done as
- *     the in-place colour-ordered Gauss-Seidel substitution
- *     theta_i = (g_i - sum_{j != i} A_ij theta_j)/A_ii + z_i/sqrt(A_ii);
+ *   theta* = theta + M^{-1}(g + sqrt((2-omega)/omega) xi_diag - A theta),
+ *     M = D/omega + L, xi_diag ~ N(0, D), done as the in-place colour-ordered
+ *     SOR substitution
+ *     theta_i = (1-omega) theta_i + omega (g_i - sum_{j != i} A_ij theta_j)/A_ii
+ *               + sqrt(omega (2-omega) / A_ii) z_i
+ *     (omega = 1: theta_i = (g_i - sum ...)/A_ii + z_i/sqrt(A_ii));
  *   theta' = theta* - G (B^T theta*).
- * Without observations it is the plain random Gibbs sweep (Alg. 2 with
- * M = D + L, Sec. 3.2). */
-static void smooth(ora_problem* p, workspace* ws, int l, int dir, int sigma, uint32_t chain,
-                   uint32_t m, double* theta, const double* f) {
+ * Without observations it is the plain random Gibbs / SOR sweep (Alg. 2 with
+ * M = D/omega + L, Sec. 3.2-3.3).  `visit` numbers the calls of level l
+ * within one update (W-cycles visit coarse levels several times). */
+static void smooth(ora_problem* p, workspace* ws, int l, int dir, int sigma, uint32_t visit,
+                   uint32_t chain, uint32_t m, double* theta, const double* f) {
   level* lv = &p->lv[l];
   int64_t N = lv->N;
   double* g = ws->g;
   for (int64_t i = 0; i < N; ++i) g[i] = f ? f[i] : 0.0;
-  uint32_t sweep_word = ((uint32_t)l << 8) | ((uint32_t)sigma << 4);
+  uint32_t sweep_word = (visit << 16) | ((uint32_t)l << 8) | ((uint32_t)sigma << 4);
   if (p->beta > 0) {
     for (int j = 0; j < p->beta; ++j) {
       double zeta = draw(p, chain, m, sweep_word, (uint32_t)(j >> 1), j & 1, 1);
@@ -844,6 +1037,7 @@ static void smooth(ora_problem* p, workspace* ws, int l, int dir, int sigma, uin
     }
   }
   int nq = p->ncolours;
+  double om = p->omega;
   for (int qq = 0; qq < nq; ++qq) {
     int q = dir == 0 ? qq : nq - 1 - qq;
     int c = fwd_colour(p, q);
@@ -853,7 +1047,10 @@ static void smooth(ora_problem* p, workspace* ws, int l, int dir, int sigma, uin
       for (int64_t e = lv->A.ptr[i]; e < lv->A.ptr[i + 1]; ++e)
         if (lv->A.col[e] != i) s -= lv->A.val[e] * theta[lv->A.col[e]];
       double z = draw(p, chain, m, sweep_word | (uint32_t)c, lv->pair[i], lv->slot[i], 0);
-      theta[i] = s / lv->diag[i] + z / sqrt(lv->diag[i]);
+      if (om == 1.0)
+        theta[i] = s / lv->diag[i] + z / sqrt(lv->diag[i]);
+      else
+        theta[i] = (1.0 - om) * theta[i] + om * (s / lv->diag[i]) + sqrt(om * (2.0 - om) / lv->diag[i]) * z;
     }
   }
   if (p->beta > 0) {
@@ -872,10 +1069,21 @@ static void smooth(ora_problem* p, workspace* ws, int l, int dir, int sigma, uin
   }
 }
 
-/* Exact coarsest sample (Sec. 3.5, Cholesky sampler of Sec. 5.1.3):
- * U^T g = f_0, then U theta_0 = g + z with z ~ N(0, I); the input is ignored. */
-static void coarse_sample(ora_problem* p, workspace* ws, uint32_t chain, uint32_t m, const double* f,
-                          double* theta) {
+/* Coarsest level (line 3 of Alg. 1).
+ * nu0 = 0: exact sample (Sec. 3.5, Cholesky sampler of Sec. 5.1.3):
+ *   U^T g = f_0, then U theta_0 = g + z with z ~ N(0, I); the input is ignored.
+ * nu0 >= 1: Alg. 5, nu0 symmetric Gibbs sweeps with low-rank correction
+ *   (forward then backward Alg. 3, as the paper's experiments use on the
+ *   coarsest level, Sec. 5.1.3), starting from the input state. */
+static void coarse_sample(ora_problem* p, workspace* ws, uint32_t visit, uint32_t chain, uint32_t m,
+                          const double* f, double* theta) {
+  if (p->nu0 > 0) {
+    for (int j = 0; j < p->nu0; ++j) {
+      smooth(p, ws, 0, 0, 2 * j, visit, chain, m, theta, f);
+      smooth(p, ws, 0, 1, 2 * j + 1, visit, chain, m, theta, f);
+    }
+    return;
+  }
   int64_t n0 = p->lv[0].N;
   const double* U = p->U;
   double* g = ws->t;
@@ -884,7 +1092,7 @@ static void coarse_sample(ora_problem* p, workspace* ws, uint32_t chain, uint32_
     for (int64_t k = 0; k < i; ++k) s -= U[k * n0 + i] * g[k];
     g[i] = s / U[i * n0 + i];
   }
-  for (int64_t i = 0; i < n0; ++i) g[i] += draw(p, chain, m, 0u, (uint32_t)(i >> 1), (int)(i & 1), 2);
+  for (int64_t i = 0; i < n0; ++i) g[i] += draw(p, chain, m, visit << 16, (uint32_t)(i >> 1), (int)(i & 1), 2);
   for (int64_t i = n0 - 1; i >= 0; --i) {
     double s = g[i];
     for (int64_t k = i + 1; k < n0; ++k) s -= U[i * n0 + k] * theta[k];
@@ -892,16 +1100,21 @@ static void coarse_sample(ora_problem* p, workspace* ws, uint32_t chain, uint32_
   }
 }
 
-/* MGMC_l of Alg. 1 with gamma_l = 1 (V-cycle). */
+/* MGMC_l of Alg. 1.  The finest level calls level L-1 once; every level
+ * 1 <= l < L calls level l-1 gamma times (gamma = 1: V-cycle, gamma = 2:
+ * W-cycle, as the paper defines them after Alg. 1), the calls after the first
+ * starting from the previous coarse state.  ws->visits[l] counts the calls of
+ * level l in the current update; the count keys that call's noise. */
 static void mgmc_level(ora_problem* p, workspace* ws, int l, uint32_t chain, uint32_t m, double* theta,
                        const double* f) {
+  uint32_t visit = ws->visits[l]++;
   if (l == 0) {
-    coarse_sample(p, ws, chain, m, f, theta);
+    coarse_sample(p, ws, visit, chain, m, f, theta);
     return;
   }
   level* lv = &p->lv[l];
   int64_t N = lv->N;
-  for (int j = 0; j < p->nu1; ++j) smooth(p, ws, l, 0, j, chain, m, theta, f);
+  for (int j = 0; j < p->nu1; ++j) smooth(p, ws, l, 0, j, visit, chain, m, theta, f);
   /* restriction f_{l-1} = P^T (f_l - At_l theta), At_l = A_l + B_l Gamma^{-1} B_l^T */
   double* r = ws->r;
   for (int64_t i = 0; i < N; ++i) {
@@ -924,19 +1137,35 @@ static void mgmc_level(ora_problem* p, workspace* ws, int l, uint32_t chain, uin
     fc[J] = p->restrict_scale * s;
     psi[J] = 0.0;
   }
-  mgmc_level(p, ws, l - 1, chain, m, psi, fc);
+  int calls = (l == p->L) ? 1 : p->cycle_gamma;
+  for (int k = 0; k < calls; ++k) mgmc_level(p, ws, l - 1, chain, m, psi, fc);
   for (int64_t i = 0; i < N; ++i) {
     double s = 0.0;
     for (int64_t e = lv->P.ptr[i]; e < lv->P.ptr[i + 1]; ++e) s += lv->P.val[e] * psi[lv->P.col[e]];
     theta[i] += s;
   }
-  for (int j = 0; j < p->nu2; ++j) smooth(p, ws, l, 1, p->nu1 + j, chain, m, theta, f);
+  for (int j = 0; j < p->nu2; ++j) smooth(p, ws, l, 1, p->nu1 + j, visit, chain, m, theta, f);
+}
+
+/* One Markov update: the MGMC cycle, or for the standalone Gibbs sampler of
+ * Sec. 5.1.3 nu1 symmetric Gibbs sweeps (forward then backward Alg. 3,
+ * i.e. Alg. 4) on the single level. */
+static void update(ora_problem* p, workspace* ws, uint32_t chain, uint32_t m, double* theta) {
+  for (int l = 0; l <= p->L; ++l) ws->visits[l] = 0;
+  if (p->sampler == ORA_SAMPLER_GIBBS) {
+    for (int j = 0; j < p->nu1; ++j) {
+      smooth(p, ws, p->L, 0, 2 * j, 0, chain, m, theta, p->fL);
+      smooth(p, ws, p->L, 1, 2 * j + 1, 0, chain, m, theta, p->fL);
+    }
+    return;
+  }
+  mgmc_level(p, ws, p->L, chain, m, theta, p->fL);
 }
 
 int ora_cycle(ora_problem* p, int64_t chain, int64_t m, double* theta) {
   workspace ws;
   if (ws_alloc(p, &ws)) { ws_free(&ws, p->L); set_err("allocation failed"); return -1; }
-  mgmc_level(p, &ws, p->L, (uint32_t)chain, (uint32_t)m, theta, p->fL);
+  update(p, &ws, (uint32_t)chain, (uint32_t)m, theta);
   ws_free(&ws, p->L);
   return 0;
 }
@@ -947,7 +1176,7 @@ int ora_chain(ora_problem* p, int64_t chain, int64_t m0, int64_t nsamples, doubl
   if (ws_alloc(p, &ws)) { ws_free(&ws, p->L); set_err("allocation failed"); return -1; }
   int64_t N = p->lv[p->L].N;
   for (int64_t k = 0; k < nsamples; ++k) {
-    mgmc_level(p, &ws, p->L, (uint32_t)chain, (uint32_t)(m0 + k), theta, p->fL);
+    update(p, &ws, (uint32_t)chain, (uint32_t)(m0 + k), theta);
     if (F && qoi) {
       double s = 0.0;
       for (int64_t i = 0; i < N; ++i) s += F[i] * theta[i];
@@ -961,13 +1190,14 @@ int ora_chain(ora_problem* p, int64_t chain, int64_t m0, int64_t nsamples, doubl
 
 int ora_smooth(ora_problem* p, int level_index, int direction, int sigma, int64_t chain, int64_t m,
                double* theta, const double* f) {
-  if (level_index < 1 || level_index > p->L || (direction != 0 && direction != 1)) {
+  int lmin = smoothed_coarsest(p) ? 0 : 1;
+  if (level_index < lmin || level_index > p->L || (direction != 0 && direction != 1)) {
     set_err("invalid smoother arguments");
     return -1;
   }
   workspace ws;
   if (ws_alloc(p, &ws)) { ws_free(&ws, p->L); return -1; }
-  smooth(p, &ws, level_index, direction, sigma, (uint32_t)chain, (uint32_t)m, theta, f);
+  smooth(p, &ws, level_index, direction, sigma, 0u, (uint32_t)chain, (uint32_t)m, theta, f);
   ws_free(&ws, p->L);
   return 0;
 }

@@ -62,6 +62,36 @@ void ora_normal_pair(const uint32_t ctr[4], const uint32_t key[2], double out[2]
 ora_problem* ora_create(int dim, int n, int levels, double kappa2, double scale,
                         const double* face_coef, const double* prolong_w,
                         int nu1, int nu2, uint64_t seed);
+
+/* Fine operators (Sec. 5.1.1): finite differences in divergence form (above),
+ * lowest-order bilinear finite elements for -Laplace + kappa^2 (2D, a = 1),
+ * or the 13-point difference of the squared shifted Laplace
+ * (-Laplace + kappa^2)^2 with clamped boundaries (2D, a = 1). */
+enum { ORA_OP_FD = 0, ORA_OP_FEM_Q1 = 1, ORA_OP_SSL13 = 2 };
+/* Samplers of Sec. 5.1.3: MGMC (Alg. 1), or the standalone Gibbs sampler,
+ * nu1 symmetric Gibbs sweeps (Alg. 4) per update on a single level. */
+enum { ORA_SAMPLER_MGMC = 0, ORA_SAMPLER_GIBBS = 1 };
+
+/* All set-up choices.  Zero-initialised fields give ora_create's defaults. */
+typedef struct {
+  int dim, n, levels;
+  double kappa2, scale;
+  const double* face_coef;
+  const double* prolong_w;
+  int nu1, nu2;
+  uint64_t seed;
+  int op;        /* ORA_OP_*; the 13-point operator sweeps in nine colours
+                    (i_1 mod 3) + 3 (i_2 mod 3), ascending, on every level */
+  int gamma;     /* calls of level l-1 made by levels 1 <= l < L (Alg. 1:
+                    1 = V-cycle, 2 = W-cycle; the finest level calls once);
+                    0 selects 1 */
+  double omega;  /* SOR relaxation of every Gibbs sweep, 0 < omega < 2
+                    (Sec. 3.3 eq. SOR_smoother, Sec. 3.4); 0 selects 1 */
+  int nu0;       /* 0: exact coarsest sample; 1..8: Alg. 5 with nu0 symmetric
+                    Gibbs sweeps with low-rank correction on level 0 */
+  int sampler;   /* ORA_SAMPLER_* (Gibbs needs levels == 1) */
+} ora_options;
+ora_problem* ora_create_ex(const ora_options* options);
 void ora_destroy(ora_problem* p);
 const char* ora_last_error(void);
 
@@ -84,6 +114,14 @@ int ora_set_posterior_rhs(ora_problem* p, const double* y);
  * map of one update exactly. */
 void ora_set_noise(ora_problem* p, int mode, int64_t impulse_index);
 int64_t ora_noise_drawn(const ora_problem* p);
+
+/* Test hook: log every normal drawn, in draw order, as 7 words (key word 0,
+ * key word 1, counter words 0..3, slot), into buf (at most cap entries; the
+ * count keeps running past cap).  buf = NULL switches logging off.  Used to
+ * check that no two draws of a run share a (key, counter, slot), i.e. that
+ * the noise components are independent as Alg. 3 requires. */
+void ora_set_noise_log(ora_problem* p, uint32_t* buf, int64_t cap);
+int64_t ora_noise_log_len(const ora_problem* p);
 
 /* One MGMC update theta <- MGMC_L(At, f_L, theta) for sample index m of chain
  * `chain` (Alg. 1).  theta has N_L entries, lexicographic, x fastest. */

@@ -194,6 +194,37 @@ def patch_sensors(n, dim, m, seed):
     return ptr, np.array(idx, dtype=np.int32), np.array(val, dtype=np.float64)
 
 
+def ball_sensors(n, dim, m, radius, seed):
+    """m sensors, each the mean over the nodes x_i with |x_i - c_j| <= radius
+    (the ball averages of Sec. 5.1.2, eq. observations, in nodal
+    quadrature), centres c_j drawn uniformly in [2 radius, 1 - 2 radius]^dim.
+    At a fixed radius the functional does not change with h, unlike a patch
+    of a fixed number of nodes.  Returns CSR over observations."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / (n + 1)
+    centres = rng.uniform(2 * radius, 1 - 2 * radius, size=(m, dim))
+    ptr = np.zeros(m + 1, dtype=np.int64)
+    idx, val = [], []
+    for j, c in enumerate(centres):
+        lo = [max(1, int(np.ceil((c[k] - radius) / h))) for k in range(dim)]
+        hi = [min(n, int(np.floor((c[k] + radius) / h))) for k in range(dim)]
+        axes = [np.arange(lo[k], hi[k] + 1) for k in range(dim)]
+        grids = np.meshgrid(*axes[::-1], indexing="ij")[::-1]
+        pts = np.stack([g.reshape(-1) for g in grids], axis=1)
+        d2 = ((pts * h - c) ** 2).sum(axis=1)
+        pts = pts[d2 <= radius ** 2]
+        if len(pts) == 0:  # coarse grid: the nearest node
+            pts = np.clip(np.rint(c / h), 1, n).astype(int)[None, :]
+        lin = np.zeros(len(pts), dtype=np.int64)
+        for k in range(dim - 1, -1, -1):
+            lin = lin * n + (pts[:, k] - 1)
+        order = np.argsort(lin)
+        idx.extend(lin[order].tolist())
+        val.extend([1.0 / len(pts)] * len(pts))
+        ptr[j + 1] = len(idx)
+    return ptr, np.array(idx, dtype=np.int32), np.array(val, dtype=np.float64)
+
+
 def observed_values(m, seed, low=1.0, high=4.0):
     """Fixed observed values in [1, 4], as in the paper's posterior set-up."""
     return np.random.default_rng(seed).uniform(low, high, size=m)
