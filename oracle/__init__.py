@@ -210,7 +210,7 @@ class Oracle:
         N = self.level_sites(level)
         shape = {0: (N, N), 1: (N, self.level_sites(level - 1)) if level > 0 else (0, 0),
                  2: (N, self.beta), 3: (N, self.beta), 4: (N, self.beta), 5: (N, N),
-                 6: (N, N), 7: (N,)}[what]
+                 6: (N, N), 7: (N,), 8: (N,)}[what]
         out = np.zeros(shape)
         if self.lib.ora_dense(self.h, level, what, _dp(out)) != 0:
             raise ValueError("oracle: dense accessor failed")

@@ -1257,6 +1257,9 @@ int ora_dense(const ora_problem* p, int l, int what, double* out) {
     case 7:
       for (int64_t r = 0; r < N; ++r) out[r] = lv->colour[r];
       return 0;
+    case 8:
+      for (int64_t r = 0; r < N; ++r) out[r] = lv->diag[r];
+      return 0;
     default:
       return -1;
   }

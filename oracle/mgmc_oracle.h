@@ -151,7 +151,8 @@ int ora_beta(const ora_problem* p);
 /* Dense copies for tests.  what: 0 prior A_l (N x N), 1 P_l (N_l x N_{l-1}),
  * 2 B_l (N_l x beta), 3 G_fwd (N_l x beta), 4 G_bwd, 5 coarsest Cholesky
  * factor U (upper, At_0 = U^T U), 6 At_l = A_l + B_l Gamma^{-1} B_l^T,
- * 7 colour of each site as double.  Returns 0 on success. */
+ * 7 colour of each site as double, 8 diagonal A_ii (N).  Returns 0 on
+ * success. */
 int ora_dense(const ora_problem* p, int level, int what, double* out);
 
 #ifdef __cplusplus
