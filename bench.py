@@ -7,8 +7,10 @@ A = h^2 (kappa^2 I - div(a grad)) with kappa = 10 and log a a 64-mode random
 Fourier field, 64 observations (3 x 3 patch means, Gamma = 1e-4 I, data in
 [1, 4]), 7-level V(1,1) cycles, 8 chains, FP64.  One step is one MGMC update
 of all 8 chains (sweeps, low-rank corrections, transfers, coarsest sample and
-the QoI reduction).  ESS/s = steps x chains / (tau x seconds) with tau the
-Wolff IACT of the QoI series of the timed steps.
+the QoI reduction).  ESS/s = steps x chains / (tau x seconds): seconds of the
+timed steps, tau the Wolff IACT of the QoI series of a separate untimed run of
+1000 burn-in and 10000 updates of every chain (the paper's protocol), so that
+the figure does not depend on --steps.
 
 Prints one JSON line.  --gpus N with N > 1 is refused: the library runs on one
 GPU (chains would shard across GPUs without communication).
@@ -42,6 +44,47 @@ def sweep_bytes(n, dim, nchains, esz, faces_per_site):
     once for all chains."""
     N = n ** dim
     return N * nchains * 2 * esz + N * esz + N * (faces_per_site + 1) * esz
+
+
+def update_bytes(cfg, nchains, esz, posterior):
+    """Algorithmic HBM bytes of one V(1,1) update of all chains, as compulsory
+    traffic with fused kernels: per site of every level l >= 1, per chain the
+    state read and written in both sweeps (4 words), the right-hand side read
+    by both sweeps (2 words; none on the finest prior level) and the transfer
+    (2 / 2^d words); per site, shared by the chains, the operator read by both
+    sweeps (d + 1 words on the finest level, the non-redundant half of a
+    Galerkin stencil plus the diagonal on coarse levels); plus the coarsest
+    factor and inverse read once each."""
+    dim, levels = cfg["dim"], cfg["levels"]
+    ns = [cfg["n"]]
+    for _ in range(levels - 1):
+        ns.append((ns[-1] - 1) // 2)
+    total = 0.0
+    for depth, n in enumerate(ns[:-1]):
+        N = n ** dim
+        finest = depth == 0
+        rhs = 0 if (finest and not posterior) else 2
+        coef = dim + 1 if finest else (5 if dim == 2 else 14)
+        total += N * esz * (nchains * (4 + rhs + 2.0 / 2 ** dim) + 2 * coef)
+    total += 2 * (ns[-1] ** dim) ** 2 * 8
+    return total
+
+
+def long_run_iact(sampler, y, F, burn, nsamples):
+    """IACT of the QoI from one untimed run of `burn` + `nsamples` updates
+    (the paper's protocol, Sec. 5.3.2: burn-in, then Wolff windowing of the
+    series), independent of the number of timed steps.  Returns the mean over
+    chains, its error (Wolff per chain, combined), and the per-chain values."""
+    from paper_2407_12149_amd import diagnostics
+    import torch
+    sampler.posterior_sample(y, 10_000_000, burn, want_qoi=False)
+    q = sampler.posterior_sample(y, 10_000_000 + burn, nsamples, F=F)
+    torch.cuda.synchronize()
+    qs = q.cpu().numpy()
+    est = [diagnostics.iact_wolff(qs[:, c]) for c in range(qs.shape[1])]
+    taus = np.array([e[0] for e in est])
+    err = float(np.sqrt(sum(e[1] ** 2 for e in est)) / len(est))
+    return float(taus.mean()), err, taus.tolist()
 
 
 def measured_traffic():
@@ -165,6 +208,69 @@ def batched(args):
     return out
 
 
+def table1(args):
+    """The paper's Table 1 comparison on one MI355X: MGMC, the standalone
+    Gibbs sampler (one symmetric sweep per update) and the exact Cholesky
+    sampler (banded factor) for the bilinear-FEM posterior of -Laplace +
+    kappa^2 (kappa = 10, Sec. 5.1), 8 observations averaging 3 x 3 node
+    patches with Gamma_jj in [1e-6, 2e-6] and data in [1, 4] (Sec. 5.1.2),
+    QoI the mean over nodes within 0.025 of the centre.  Per grid and
+    sampler: time per sample (one chain's share of a step of 8 chains), IACT
+    (Wolff, after burn-in) and time per independent sample; FP64."""
+    import torch
+
+    from paper_2407_12149_amd import diagnostics, mgmc, workloads
+
+    out = {"metric": "time per independent sample, MGMC vs Gibbs vs Cholesky (paper Table 1 "
+                     "block 1 on one MI355X)", "unit": "ms", "n_gpus": 1,
+           "higher_is_better": False, "dtype": "f64", "data": "synthetic", "rows": []}
+    nch = 8
+    for n in args.table1_grids:
+        levels = int(np.log2(n + 1)) - 2
+        ptr, idx, val = workloads.patch_sensors(n, 2, 8, seed=2)
+        gamma = np.random.default_rng(7).uniform(1e-6, 2e-6, size=8)
+        y = workloads.observed_values(8, seed=3)
+        h = 1.0 / (n + 1)
+        x = np.arange(1, n + 1) * h
+        X, Y = np.meshgrid(x, x, indexing="xy")
+        F = (((X - 0.5) ** 2 + (Y - 0.5) ** 2) <= 0.025 ** 2).astype(np.float64).reshape(-1)
+        F /= F.sum()
+        Fd = torch.tensor(F, device="cuda")
+        for sampler in ("mgmc", "gibbs", "cholesky"):
+            prob = dict(dim=2, n=n, levels=levels if sampler == "mgmc" else 1, kappa2=100.0,
+                        op="fem", sampler=sampler, nchains=nch, seed=0)
+            log(f"[table1] {n}^2 {sampler}: set-up")
+            t0 = time.perf_counter()
+            s = mgmc.Sampler(prob, obs=(ptr, idx, val, gamma))
+            setup_s = time.perf_counter() - t0
+            s.set_graph(True)
+            burn = 200 if sampler != "gibbs" else 2000
+            nsamp = args.table1_samples if sampler != "cholesky" else min(args.table1_samples, 400)
+            s.posterior_sample(y, 0, burn, want_qoi=False)
+            torch.cuda.synchronize()
+            start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            start.record(s.stream)
+            q = s.posterior_sample(y, burn, nsamp, F=Fd)
+            stop.record(s.stream)
+            torch.cuda.synchronize()
+            ms_step = start.elapsed_time(stop) / nsamp
+            qs = q.cpu().numpy()
+            if sampler == "cholesky":
+                tau, dtau = 1.0, 0.0
+            else:
+                est = [diagnostics.iact_wolff(qs[:, c]) for c in range(nch)]
+                tau = float(np.mean([e[0] for e in est]))
+                dtau = float(np.sqrt(sum(e[1] ** 2 for e in est)) / nch)
+            row = {"grid": f"{n + 1}x{n + 1} cells", "sampler": sampler, "setup_s": setup_s,
+                   "iact": tau, "iact_err": dtau, "ms_per_step_8_chains": ms_step,
+                   "ms_per_sample": ms_step / nch, "ms_per_independent_sample": ms_step / nch * tau,
+                   "samples": nsamp}
+            log(f"[table1] {row}")
+            out["rows"].append(row)
+            s.close()
+    return out
+
+
 LEARNED_PARAMS = os.path.join(ROOT, "paper_2407_12149_amd", "pnet_learned511.npy")
 
 
@@ -205,11 +311,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", type=int, default=1)
     ap.add_argument("--fp32", type=int, default=1, help="also run the FP32 sampler (paired)")
+    ap.add_argument("--iact-burn", type=int, default=1000,
+                    help="burn-in updates of the untimed run that estimates the IACT")
+    ap.add_argument("--iact-samples", type=int, default=10000,
+                    help="updates of the untimed IACT run (0: estimate from the timed steps)")
     ap.add_argument("--workload", default="posterior1023",
-                    choices=["posterior1023", "posterior255", "batched512"],
+                    choices=["posterior1023", "posterior255", "batched512", "table1"],
                     help="posterior1023 (2D, FP64 with paired FP32; default), posterior255 "
                          "(3D posterior at scale, 64 chains, FP32 with paired FP64; host set-up "
                          "takes about a minute per precision), batched512")
+    ap.add_argument("--table1-grids", type=int, nargs="+", default=[127, 255, 511])
+    ap.add_argument("--table1-samples", type=int, default=4000)
     ap.add_argument("--tune-cache", default=None,
                     help="JSON cache of the per-level kernel choices (default: tune afresh)")
     ap.add_argument("--tune", type=int, default=1, help="autotune the sweep kernels before timing")
@@ -242,6 +354,9 @@ def main():
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", 0)))
     if args.workload == "batched512":
         print(json.dumps(batched(args)), flush=True)
+        return
+    if args.workload == "table1":
+        print(json.dumps(table1(args)), flush=True)
         return
     wl = args.workload
     log(f"[bench] generating workload {wl}")
@@ -280,7 +395,11 @@ def main():
         seconds = start.elapsed_time(stop) / 1e3
         qs = q.cpu().numpy()
         taus = [diagnostics.iact_wolff(qs[:, c])[0] for c in range(nch)]
-        tau = float(np.mean(taus))
+        tau_timed = float(np.mean(taus))
+        long_tau = None
+        if precision == primary and args.iact_samples > 0:
+            log(f"[bench] {precision}: IACT from {args.iact_burn} + {args.iact_samples} untimed updates")
+            long_tau = long_run_iact(s, y, F, args.iact_burn, args.iact_samples)
         # kernel time of the finest-level sweeps, bracketed by HIP events on
         # the sampler's stream during a further run of the same workload
         log(f"[bench] {precision}: kernel timing {args.profile_steps} steps")
@@ -294,12 +413,19 @@ def main():
         per_launch_s = kms / 1e3 / max(launches, 1)
         launches_per_sweep = launches / (2.0 * args.profile_steps)
         bytes_launch = sweep_bytes(n, dim, nch, esz, dim) / launches_per_sweep
-        return dict(seconds=seconds, q=qs, tau=tau, setup_s=setup_s, per_launch_s=per_launch_s, tuned=tuned,
+        return dict(seconds=seconds, q=qs, tau_timed=tau_timed, long_tau=long_tau, setup_s=setup_s,
+                    per_launch_s=per_launch_s, tuned=tuned,
                     launches_per_sweep=launches_per_sweep, bytes_launch=bytes_launch,
                     achieved=bytes_launch / per_launch_s / 1e9)
 
     r64 = run(primary)
-    seconds, tau = r64["seconds"], r64["tau"]
+    seconds = r64["seconds"]
+    if r64["long_tau"] is not None:
+        tau, tau_err, tau_chains = r64["long_tau"]
+        tau_source = f"{args.iact_burn} burn-in + {args.iact_samples} updates x {nch} chains, untimed"
+    else:
+        tau, tau_err, tau_chains = r64["tau_timed"], None, None
+        tau_source = f"the {args.steps} timed updates"
     value = args.steps * nch / (tau * seconds)
     achieved = r64["achieved"]
     setup_s = r64["setup_s"]
@@ -310,9 +436,12 @@ def main():
         # start; errors of the FP32 QoI relative to the FP64 one
         q64, q32 = (r64["q"], r32["q"]) if primary == "fp64" else (r32["q"], r64["q"])
         sd = q64.std()
+        # the paired chains track each other to rounding, so they share the
+        # long-run IACT of the primary precision
         extra[paired] = {
-            "value": args.steps * nch / (r32["tau"] * r32["seconds"]),
-            "ms_per_step": r32["seconds"] * 1e3 / args.steps, "iact": r32["tau"],
+            "value": args.steps * nch / (tau * r32["seconds"]),
+            "ms_per_step": r32["seconds"] * 1e3 / args.steps, "iact": tau,
+            "iact_timed_steps": r32["tau_timed"],
             "sweep_gbs": r32["achieved"], "sweep_frac": r32["achieved"] / PEAK_HBM_GBS,
             "mean_err_rel_sd": float(abs(q32.mean() - q64.mean()) / sd),
             "var_err_rel": float(abs(q32.var() - q64.var()) / q64.var()),
@@ -336,7 +465,18 @@ def main():
                    "graph": bool(args.graph),
                    "kernel_forms": r64["tuned"]["levels"] if r64["tuned"] else "default"},
         "iact": tau,
+        "iact_err": tau_err,
+        "iact_source": tau_source,
+        "iact_chains": tau_chains,
+        "iact_timed_steps": r64["tau_timed"],
         "setup_s": setup_s,
+        "update_roofline": {
+            "bytes_per_step": update_bytes(cfg, nch, 4 if primary == "fp32" else 8, True),
+            "achieved": update_bytes(cfg, nch, 4 if primary == "fp32" else 8, True) / seconds * args.steps / 1e9,
+            "unit": "GB/s", "peak": PEAK_HBM_GBS,
+            "frac": update_bytes(cfg, nch, 4 if primary == "fp32" else 8, True) / seconds * args.steps / 1e9 / PEAK_HBM_GBS,
+            "note": "whole update: compulsory traffic of all levels per step / ms_per_step",
+        },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS,
                      "traffic": measured_traffic() if wl == "posterior1023" else None,

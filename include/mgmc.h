@@ -61,6 +61,30 @@ typedef enum {
                     low-rank terms in FP64 */
 } mgmc_precision;
 
+/* Fine operators of Sec. 5.1.1. */
+typedef enum {
+  MGMC_OP_FD = 0,     /* finite differences in divergence form (above), 5/7-point */
+  MGMC_OP_FEM_Q1 = 1, /* 2D, a = 1: lowest-order bilinear finite elements for
+                         -Laplace + kappa^2, the Galerkin matrix of the bilinear
+                         form times s / h^2 (9-point) */
+  MGMC_OP_SSL13 = 2   /* 2D, a = 1: squared shifted Laplace (-Laplace + kappa^2)^2,
+                         s [h^-4 (13-point biharmonic difference) + 2 kappa^2 h^-2
+                         (5-point -Laplace) + kappa^4] with u = du/dn = 0 on the
+                         boundary (ghost nodes mirror the interior); its Galerkin
+                         coarse operators are 25-point and every level sweeps in
+                         the nine colours (i_1 mod 3) + 3 (i_2 mod 3), ascending */
+} mgmc_operator;
+
+/* Samplers of Sec. 5.1.3. */
+typedef enum {
+  MGMC_SAMPLER_MGMC = 0,    /* Alg. 1 */
+  MGMC_SAMPLER_GIBBS = 1,   /* levels == 1: each update is nu1 symmetric Gibbs sweeps
+                               (forward then backward Alg. 3, i.e. Alg. 4) */
+  MGMC_SAMPLER_CHOLESKY = 2 /* levels == 1: each update is an independent exact
+                               sample theta = At^{-1} f + U^{-1} z, At = U^T U by a
+                               banded Cholesky factor in lexicographic order */
+} mgmc_sampler;
+
 typedef struct {
   int32_t dim;             /* 2 or 3 */
   int32_t n;               /* interior nodes per dimension, n = 2^k - 1 */
@@ -81,6 +105,18 @@ typedef struct {
   int32_t nchains;         /* >= 1 chains sharing the operator */
   int64_t chain_offset;    /* chain c draws the noise of chain id chain_offset + c */
   uint64_t seed;           /* the low 32 bits key the noise */
+  /* Fields below default to the plain method when zero. */
+  int32_t op;              /* mgmc_operator (MGMC_OP_FD when 0) */
+  int32_t cycle_gamma;     /* calls of level l-1 made by every level 1 <= l < L
+                              (Alg. 1, gamma_l; the finest level calls once):
+                              0 or 1 V-cycle, 2 W-cycle, at most 3 */
+  double omega;            /* SOR relaxation of every Gibbs sweep (Sec. 3.3 eq.
+                              SOR_smoother, Sec. 3.4 eq. M_lowrank_gibbs),
+                              0 < omega < 2; 0 selects 1 */
+  int32_t nu0;             /* 0: exact Cholesky sample on level 0; 1..8: Alg. 5,
+                              nu0 symmetric Gibbs sweeps with low-rank correction
+                              on level 0 (what the paper's experiments run) */
+  int32_t sampler;         /* mgmc_sampler (MGMC_SAMPLER_MGMC when 0) */
 } mgmc_problem;
 
 typedef struct {
@@ -99,8 +135,11 @@ typedef struct {
  * hip_stream: a hipStream_t (NULL = default stream) used by every later call.
  * Host arrays are copied; the caller may free them on return.
  * Errors: EINVAL (shape, levels, nu, NULL arrays, gamma <= 0, site index out
- * of range), ENOTSPD, ENOMEM, EDEVICE, EUNSUPPORTED (some level l >= 1 whose
- * observation matrix B_l holds more than 8192 - 2 beta weights). */
+ * of range, operator / sampler / gamma / omega / nu0 out of range or not
+ * matching dim and levels), ENOTSPD (non-positive diagonal or no Cholesky
+ * factor; found on the host before any device work), ENOMEM, EDEVICE,
+ * EUNSUPPORTED (some smoothed level whose observation matrix B_l holds more
+ * than 8192 - 2 beta weights; a banded factor above 2^31 entries). */
 mgmc_status mgmc_setup(const mgmc_problem* problem, const mgmc_obs* obs, void* hip_stream,
                        mgmc_ctx** out);
 
@@ -148,7 +187,8 @@ mgmc_status mgmc_set_graph(mgmc_ctx* ctx, int32_t enabled);
  *     memory into LDS by DMA while the previous chain's colour passes run
  *     (5-point levels; 9-point levels take form 1).
  *   MGMC_OPT_CHAINS_PER_BLOCK: chains processed by one block of the 2D
- *     sweep; 0 (default) chooses from the grid size and precision.
+ *     sweep, or (3D contexts) by one thread of the per-site kernels (capped
+ *     at 16); 0 (default) chooses from the grid size and precision.
  *   MGMC_OPT_COARSE_FUSED: k >= 1 runs levels 0 .. min(k, m) as one launch
  *     with one workgroup per chain and the levels resident in LDS (2D,
  *     one-launch sweeps), where m is the highest level below the finest

@@ -8,7 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmgmc.so")
 SOURCES = ["csrc/api.hip", "csrc/kernels.hip", "csrc/kernels_tiled.hip", "csrc/hierarchy.cpp",
-           "csrc/api_pnet.hip", "csrc/kernels_pnet.hip", "csrc/kernels_coarse.hip"]
+           "csrc/api_pnet.hip", "csrc/kernels_pnet.hip", "csrc/kernels_coarse.hip",
+           "csrc/kernels_ext.hip"]
 
 
 def build(verbose: bool = False) -> str:

@@ -28,7 +28,7 @@ mgmc_status fail(mgmc_status s, const std::string& msg) {
   } while (0)
 
 inline int64_t host_pidx(const mgmc::Geom& g, const int* i, int dim) {
-  return int64_t(i[0] + 3) + int64_t(g.px) * (int64_t(i[1]) + int64_t(g.py) * (dim == 3 ? i[2] : 0));
+  return g.o0 + int64_t(i[0] + 3) + int64_t(g.px) * (int64_t(i[1]) + int64_t(g.py) * (dim == 3 ? i[2] : 0));
 }
 
 inline int64_t padded_of(const mgmc::Geom& g, int dim, int64_t lin) {
@@ -65,6 +65,15 @@ struct mgmc_ctx {
   int64_t* mcur = nullptr;
   double* qpart = nullptr;
   void* fL = nullptr;  // padded finest right-hand side, shared by the chains
+  // update forms beyond the tuned V-cycle: W-cycles, SOR relaxation, Alg. 5
+  // on level 0 or 5 x 5 stencils run the per-colour kernels level by level
+  bool generic = false;
+  int sampler = MGMC_SAMPLER_MGMC, gamma = 1, nu0 = 0;
+  // banded single-level exact sampler
+  double* Uband = nullptr;
+  double* mu = nullptr;     // At^{-1} f of the last right-hand side (null: f = 0)
+  double* bandx = nullptr;  // [nchains][N] FP64 scratch of the back substitution
+  bool mu_set = false;
   mgmc::HostHierarchy H;
   std::vector<double> last_y;
   bool posterior_ready = false;
@@ -149,7 +158,17 @@ mgmc_status validate(const mgmc_problem* p, const mgmc_obs* obs) {
     N0 *= n0;
     N *= p->n;
   }
-  if (N0 > 4096) return fail(MGMC_EINVAL, "coarsest level has more than 4096 sites; use more levels");
+  if (p->op < MGMC_OP_FD || p->op > MGMC_OP_SSL13) return fail(MGMC_EINVAL, "unknown operator");
+  if (p->op != MGMC_OP_FD && (p->dim != 2 || p->face_coef))
+    return fail(MGMC_EINVAL, "the FEM and squared shifted Laplace operators are 2D with a = 1");
+  if (p->cycle_gamma < 0 || p->cycle_gamma > 3) return fail(MGMC_EINVAL, "cycle_gamma must be in [0, 3]");
+  if (!(p->omega == 0.0 || (p->omega > 0.0 && p->omega < 2.0))) return fail(MGMC_EINVAL, "omega must lie in (0, 2) (0 selects 1)");
+  if (p->nu0 < 0 || p->nu0 > 8) return fail(MGMC_EINVAL, "nu0 must be in [0, 8]");
+  if (p->sampler < MGMC_SAMPLER_MGMC || p->sampler > MGMC_SAMPLER_CHOLESKY) return fail(MGMC_EINVAL, "unknown sampler");
+  if (p->sampler != MGMC_SAMPLER_MGMC && p->levels != 1) return fail(MGMC_EINVAL, "the Gibbs and Cholesky samplers take levels = 1");
+  if (p->sampler == MGMC_SAMPLER_GIBBS && p->nu1 > 8) return fail(MGMC_EINVAL, "the Gibbs sampler takes nu1 <= 8");
+  const bool exact_dense = p->sampler == MGMC_SAMPLER_MGMC && p->nu0 == 0;
+  if (exact_dense && N0 > 4096) return fail(MGMC_EINVAL, "coarsest level has more than 4096 sites; use more levels");
   if (N > (int64_t(1) << 31) - 1) return fail(MGMC_EINVAL, "grid too large");
   if (p->face_coef) {
     int64_t per = p->n + 1;
@@ -187,9 +206,9 @@ mgmc_status upload_level(mgmc_ctx* c, int l) {
   const mgmc::HostLevel& h = H.lv[l];
   mgmc::DevLevel& d = c->lv[l];
   const int dim = H.dim, S = H.S, nch = c->prob.nchains;
-  d.g = mgmc::make_geom(dim, h.n);
+  d.g = mgmc::make_geom(dim, h.n, H.R == 2 ? 2 : 1);
   d.N = h.N;
-  d.cross = (l == H.L);
+  d.cross = (l == H.L) && H.op == MGMC_OP_FD;
   const int64_t Np = d.g.Np;
   std::vector<int64_t> pad(h.N);
   for (int64_t i = 0; i < h.N; ++i) pad[i] = padded_of(d.g, dim, i);
@@ -210,22 +229,26 @@ mgmc_status upload_level(mgmc_ctx* c, int l) {
   }
   if (!h.wP.empty()) {
     const mgmc::HostLevel& hc = H.lv[l - 1];
-    const mgmc::Geom gc = mgmc::make_geom(dim, hc.n);
-    std::vector<double> w(size_t(S) * gc.Np, 0.0);
+    const mgmc::Geom gc = mgmc::make_geom(dim, hc.n, H.R == 2 ? 2 : 1);
+    const int SP = dim == 2 ? 9 : 27;  // prolongation offsets {-1,0,1}^dim
+    std::vector<double> w(size_t(SP) * gc.Np, 0.0);
     for (int64_t J = 0; J < hc.N; ++J) {
       const int64_t pj = padded_of(gc, dim, J);
-      for (int t = 0; t < S; ++t) w[size_t(t) * gc.Np + pj] = h.wP[size_t(J) * S + t];
+      for (int t = 0; t < SP; ++t) w[size_t(t) * gc.Np + pj] = h.wP[size_t(J) * SP + t];
     }
     mgmc_status s = c->upload(d.wP, w);
     if (s != MGMC_OK) return s;
   }
   mgmc_status s = c->alloc_bytes(d.buf[0], size_t(nch) * Np * c->esz);
   if (s != MGMC_OK) return s;
-  if (l >= 1) {  // second buffer: out-of-place 2D sweeps, 3D residual scratch
+  const bool smoothed = l >= 1 || H.level0_lowrank;  // level runs smoother sweeps
+  if (smoothed) {  // second buffer: out-of-place 2D sweeps, residual scratch
     s = c->alloc_bytes(d.buf[1], size_t(nch) * Np * c->esz);
     if (s != MGMC_OK) return s;
   }
-  if (l < H.L) {
+  // a per-chain right-hand side below the finest level; on a 9-point finest
+  // level (FEM) too, where the one-launch 2D sweeps take one per chain
+  if (l < H.L || (l == H.L && !d.cross && dim == 2 && l >= 1)) {
     s = c->alloc_bytes(d.f, size_t(nch) * Np * c->esz);
     if (s != MGMC_OK) return s;
   }
@@ -244,7 +267,7 @@ mgmc_status upload_level(mgmc_ctx* c, int l) {
       bptr[j + 1] = int64_t(bidx.size());
     }
     d.bnnz = int64_t(bidx.size());
-    if (l >= 1 && d.bnnz > 8192 - 2 * int64_t(beta))
+    if (smoothed && d.bnnz > 8192 - 2 * int64_t(beta))
       return fail(MGMC_EUNSUPPORTED, "observation weights on a level exceed the low-rank kernel's LDS (8192 - 2 beta)");
     if ((s = c->upload(d.bptr, bptr)) != MGMC_OK) return s;
     if ((s = c->upload(d.bidx, bidx)) != MGMC_OK) return s;
@@ -252,7 +275,7 @@ mgmc_status upload_level(mgmc_ctx* c, int l) {
     int64_t kmax = 0;
     for (int j = 0; j < beta; ++j) kmax = std::max(kmax, bptr[j + 1] - bptr[j]);
     const int bkp = kmax <= 8 ? 8 : kmax == 9 ? 9 : kmax <= 12 ? 12 : kmax <= 16 ? 16 : kmax <= 32 ? 32 : 0;
-    if (c->prob.dim == 2 && l >= 1 && d.bnnz > 0 && bkp > 0) {
+    if (c->prob.dim == 2 && smoothed && H.R == 1 && d.bnnz > 0 && bkp > 0) {
       // fixed-width slots per column of B (zero padded)
       d.bkp = bkp;
       d.bslots = int64_t(beta) * bkp;
@@ -310,7 +333,7 @@ mgmc_status upload_level(mgmc_ctx* c, int l) {
     if ((s = c->upload(d.brptr, brptr)) != MGMC_OK) return s;
     if ((s = c->upload(d.brcol, brcol)) != MGMC_OK) return s;
     if ((s = c->upload(d.brval, brval)) != MGMC_OK) return s;
-    if (l >= 1) {
+    if (smoothed) {
       for (int dir = 0; dir < 2; ++dir) {
         const int64_t ns = int64_t(h.supp[dir].size());
         d.nsupp[dir] = int32_t(ns);
@@ -408,6 +431,97 @@ bool fused_lowrank(const mgmc_ctx* c, const mgmc::DevLevel& lv) {
   return c->beta > 0 && c->beta <= 128 && c->L.lowrank_mfma == 1 && lv.bsnap != nullptr;
 }
 
+// One in-place smoother sweep of level l with the per-colour kernels (all
+// colours in forward or backward order), as the update forms beyond the tuned
+// V-cycle use them: nine-colour passes on 5 x 5 stencils, parity passes on
+// 3D 7-point levels, else one launch per colour.
+mgmc_status sweep_in_place(mgmc_ctx* c, int l, void* theta, const void* f, int64_t fcs,
+                           uint32_t word, bool backward) {
+  const mgmc::Launch& L = c->L;
+  mgmc::DevLevel& lv = c->lv[l];
+  if (c->H.R == 2) {
+    for (int qq = 0; qq < 9; ++qq) {
+      const int colour = backward ? 8 - qq : qq;
+      MGMC_LAUNCH(mgmc::launch_sweep_wide(L, lv, theta, f, fcs, word, colour));
+    }
+    return MGMC_OK;
+  }
+  if (c->prob.dim == 3 && lv.cross) {
+    for (int pp = 0; pp < 2; ++pp)
+      MGMC_LAUNCH(mgmc::launch_sweep_parity3d(L, lv, theta, f, fcs, word, backward ? 1 - pp : pp));
+    return MGMC_OK;
+  }
+  const int nq = 1 << c->prob.dim;
+  for (int qq = 0; qq < nq; ++qq) {
+    const int q = backward ? nq - 1 - qq : qq;
+    MGMC_LAUNCH(mgmc::launch_sweep_colour(L, lv, theta, f, fcs, word, mgmc::forward_colour(c->prob.dim, 2, q)));
+  }
+  return MGMC_OK;
+}
+
+// MGMC_l of Alg. 1 for the general forms (gamma_l calls of level l-1 from
+// every level 1 <= l < L, one from the finest; SOR relaxation; Alg. 5 on
+// level 0; 5 x 5 stencils), in place on buffer 0 of every level.  visits[l]
+// counts the calls of level l in this update and keys their noise.
+mgmc_status generic_level(mgmc_ctx* c, int l, const void* fL, std::vector<int>& visits) {
+  const mgmc::Launch& L = c->L;
+  const int top = c->levels - 1, beta = c->beta;
+  const int visit = visits[l]++;
+  mgmc::DevLevel& lv = c->lv[l];
+  const void* f = (l == top) ? fL : lv.f;
+  const int64_t fcs = (l == top) ? 0 : lv.g.Np;
+  void* th = lv.buf[0];
+  mgmc_status st;
+  if (l == 0 && c->nu0 == 0) {
+    MGMC_LAUNCH(mgmc::launch_coarsest(L, lv, f, fcs, th, c->K, c->Uinv, mgmc::noise_word(0, 0, visit)));
+    return MGMC_OK;
+  }
+  if (l == 0) {  // Alg. 5: nu0 symmetric Gibbs sweeps with low-rank correction
+    for (int j = 0; j < c->nu0; ++j)
+      for (int dir = 0; dir < 2; ++dir) {
+        const uint32_t word = mgmc::noise_word(0, 2 * j + dir, visit);
+        if ((st = sweep_in_place(c, 0, th, f, fcs, word, dir == 1)) != MGMC_OK) return st;
+        if (beta) MGMC_LAUNCH(mgmc::launch_lowrank(L, lv, th, dir, word, beta, c->gisq, c->gam, c->t, nullptr));
+      }
+    return MGMC_OK;
+  }
+  const int nu1 = c->prob.nu1, nu2 = c->prob.nu2;
+  for (int j = 0; j < nu1; ++j) {
+    const uint32_t word = mgmc::noise_word(l, j, visit);
+    if ((st = sweep_in_place(c, l, th, f, fcs, word, false)) != MGMC_OK) return st;
+    if (beta)
+      MGMC_LAUNCH(mgmc::launch_lowrank(L, lv, th, 0, word, beta, c->gisq, c->gam, c->t, j == nu1 - 1 ? c->v : nullptr));
+  }
+  mgmc::DevLevel& cl = c->lv[l - 1];
+  mgmc::LowRankRhs lr;
+  if (beta) {
+    lr.row_of = cl.brow_of;
+    lr.ptr = cl.brptr;
+    lr.col = cl.brcol;
+    lr.val = cl.brval;
+    lr.v = c->v;
+    lr.beta = beta;
+  }
+  if (c->H.R == 2)
+    MGMC_LAUNCH(mgmc::launch_restrict_wide(L, lv, th, lv.buf[1], cl, f, fcs, lr));
+  else if (c->prob.dim == 3)
+    MGMC_LAUNCH(mgmc::launch_restrict_2stage(L, lv, th, lv.buf[1], cl, f, fcs, lr));
+  else
+    MGMC_LAUNCH(mgmc::launch_restrict(L, lv, th, cl, f, fcs, lr));
+  // psi^(0) = 0, then gamma_l calls of MGMC_{l-1} (Alg. 1)
+  MGMC_LAUNCH(mgmc::launch_fill_zero(L, cl.buf[0], int64_t(L.nchains) * cl.g.Np));
+  const int calls = (l == top) ? 1 : c->gamma;
+  for (int k = 0; k < calls; ++k)
+    if ((st = generic_level(c, l - 1, fL, visits)) != MGMC_OK) return st;
+  MGMC_LAUNCH(mgmc::launch_prolong(L, lv, th, cl, cl.buf[0]));
+  for (int j = 0; j < nu2; ++j) {
+    const uint32_t word = mgmc::noise_word(l, nu1 + j, visit);
+    if ((st = sweep_in_place(c, l, th, f, fcs, word, true)) != MGMC_OK) return st;
+    if (beta) MGMC_LAUNCH(mgmc::launch_lowrank(L, lv, th, 1, word, beta, c->gisq, c->gam, c->t, nullptr));
+  }
+  return MGMC_OK;
+}
+
 // One MGMC update of every chain (Alg. 1), enqueued on the context stream.
 // cur[l] names the buffer holding the state of level l; a tiled sweep reads
 // it and writes the other one.  The finest level ends every update in
@@ -436,21 +550,57 @@ mgmc_status enqueue_cycle(mgmc_ctx* c, const void* fL, const double* F, double* 
     for (int qq = 0; qq < nq; ++qq) {
       const int q = backward ? nq - 1 - qq : qq;
       mgmc_status st = timed(c, l == top, [&] {
-        return mgmc::launch_sweep_colour(L, lv, state(l), f, fcs, word, mgmc::forward_colour(c->prob.dim, q));
+        return mgmc::launch_sweep_colour(L, lv, state(l), f, fcs, word, mgmc::forward_colour(c->prob.dim, 2, q));
       });
       if (st != MGMC_OK) return st;
     }
     return MGMC_OK;
   };
+  if (c->sampler == MGMC_SAMPLER_CHOLESKY) {
+    // exact sample of the single level: theta = mu + U^{-1} z
+    MGMC_LAUNCH(mgmc::launch_band_sample(L, c->lv[0], c->Uband, c->H.band, c->mu_set ? c->mu : nullptr,
+                                         c->bandx, state(0), 0u));
+  } else if (c->sampler == MGMC_SAMPLER_GIBBS) {
+    // nu1 symmetric Gibbs sweeps (forward then backward Alg. 3) on level 0
+    mgmc::DevLevel& lv = c->lv[0];
+    const bool fast = tiled && c->H.R == 1 && L.omega == 1.0;
+    for (int j = 0; j < nu1; ++j)
+      for (int dir = 0; dir < 2; ++dir) {
+        const uint32_t word = mgmc::noise_word(0, 2 * j + dir, 0);
+        if (fast) {
+          const bool snap = fused_lowrank(c, lv);
+          mgmc_status st = timed(c, true, [&] {
+            return sweep2d(c, 0, state(0), lv.buf[1 - cur[0]], 0, fL, 0, word, dir, nullptr, nullptr, snap);
+          });
+          if (st != MGMC_OK) return st;
+          cur[0] ^= 1;
+          if (snap) {
+            MGMC_LAUNCH(mgmc::launch_lowrank_fused(L, lv, state(0), dir, word, beta, c->gisq, c->gam, nullptr));
+            continue;
+          }
+        } else {
+          mgmc_status st = sweep_in_place(c, 0, state(0), fL, 0, word, dir == 1);
+          if (st != MGMC_OK) return st;
+        }
+        if (beta) MGMC_LAUNCH(mgmc::launch_lowrank(L, lv, state(0), dir, word, beta, c->gisq, c->gam, c->t, nullptr));
+      }
+  } else if (c->generic) {
+    std::vector<int> visits(c->levels, 0);
+    mgmc_status st = generic_level(c, top, fL, visits);
+    if (st != MGMC_OK) return st;
+  }
   // the bottom levels in one launch when available (2D, one-launch sweeps)
   const int lm = (tiled && c->coarse_fused > 0) ? std::min(c->coarse_fused, c->coarse_lm) : 0;
-  if (top == 0) {
+  if (c->sampler != MGMC_SAMPLER_MGMC || c->generic) {
+    // done above
+  } else if (top == 0) {
     MGMC_LAUNCH(mgmc::launch_coarsest(L, c->lv[0], fL, 0, state(0), c->K, c->Uinv));
   } else {
     for (int l = top; l >= std::max(1, lm + 1); --l) {
       mgmc::DevLevel& lv = c->lv[l];
-      const void* f = (l == top) ? fL : lv.f;
-      const int64_t fcs = (l == top) ? 0 : lv.g.Np;
+      const bool own = l < top || lv.f != nullptr;  // per-chain right-hand side
+      const void* f = own ? lv.f : fL;
+      const int64_t fcs = own ? lv.g.Np : 0;
       const bool zero_start = l < top;  // psi^(0) = 0 on coarse levels
       if (zero_start && !tiled) MGMC_LAUNCH(mgmc::launch_fill_zero(L, state(l), int64_t(nch) * lv.g.Np));
       for (int j = 0; j < nu1; ++j) {
@@ -505,8 +655,9 @@ mgmc_status enqueue_cycle(mgmc_ctx* c, const void* fL, const double* F, double* 
     }
     for (int l = std::max(1, lm + 1); l <= top; ++l) {
       mgmc::DevLevel& lv = c->lv[l];
-      const void* f = (l == top) ? fL : lv.f;
-      const int64_t fcs = (l == top) ? 0 : lv.g.Np;
+      const bool own = l < top || lv.f != nullptr;
+      const void* f = own ? lv.f : fL;
+      const int64_t fcs = own ? lv.g.Np : 0;
       const void* psi = state(l - 1);
       for (int j = 0; j < nu2; ++j) {
         const uint32_t word = mgmc::noise_word(l, nu1 + j);
@@ -547,6 +698,8 @@ mgmc_status run_samples(mgmc_ctx* c, const void* fL, int64_t m0, int64_t nsample
                         const double* F, double* qoi) {
   const int top = c->levels - 1;
   MGMC_LAUNCH(mgmc::launch_unpack(c->L, c->lv[top], theta, c->lv[top].buf[0]));
+  if (c->lv[top].f != nullptr)  // per-chain copies of the finest right-hand side
+    MGMC_LAUNCH(mgmc::launch_broadcast(c->L, c->lv[top], fL, c->lv[top].f));
   MGMC_LAUNCH(mgmc::launch_set_m(c->stream, c->mcur, m0));
   if (c->use_graph && c->stream != nullptr && nsamples > 1) {
     hipGraph_t graph = nullptr;
@@ -583,6 +736,21 @@ mgmc_status run_samples(mgmc_ctx* c, const void* fL, int64_t m0, int64_t nsample
   return MGMC_OK;
 }
 
+// mu = At^{-1} f with the banded factor, which after set-up lives on the
+// device only: copied back for the host solve (an empty result on failure).
+std::vector<double> band_solve_device(mgmc_ctx* c, const double* f) {
+  mgmc::HostHierarchy& H = c->H;
+  const size_t cnt = size_t(H.lv[H.L].N) * size_t(H.band + 1);
+  H.Uband.resize(cnt);
+  if (hipMemcpy(H.Uband.data(), c->Uband, cnt * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+    std::vector<double>().swap(H.Uband);
+    return {};
+  }
+  std::vector<double> mu = mgmc::band_solve(H, f);
+  std::vector<double>().swap(H.Uband);
+  return mu;
+}
+
 mgmc_status check_run_args(mgmc_ctx* c, int64_t m0, int64_t nsamples, void* theta, const double* F,
                            double* qoi) {
   if (!c) return fail(MGMC_EINVAL, "context is NULL");
@@ -604,8 +772,6 @@ mgmc_status mgmc_setup(const mgmc_problem* problem, const mgmc_obs* obs, void* h
   *out = nullptr;
   mgmc_status s = validate(problem, obs);
   if (s != MGMC_OK) return s;
-  int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(MGMC_EDEVICE, "no HIP device available");
   mgmc_ctx* c = new (std::nothrow) mgmc_ctx();
   if (!c) return fail(MGMC_ENOMEM, "host allocation failed");
   c->prob = *problem;
@@ -624,11 +790,23 @@ mgmc_status mgmc_setup(const mgmc_problem* problem, const mgmc_obs* obs, void* h
   c->L.seed = uint32_t(problem->seed);
   c->L.chain0 = uint32_t(problem->chain_offset);
   c->L.lowrank_mfma = 1;
+  c->L.omega = problem->omega > 0.0 ? problem->omega : 1.0;
+  c->sampler = problem->sampler;
+  c->gamma = problem->cycle_gamma > 0 ? problem->cycle_gamma : 1;
+  c->nu0 = problem->sampler == MGMC_SAMPLER_MGMC ? problem->nu0 : 0;
+  c->generic = problem->sampler == MGMC_SAMPLER_MGMC &&
+               (c->gamma != 1 || c->L.omega != 1.0 || c->nu0 > 0 || problem->op == MGMC_OP_SSL13);
   std::string err;
   s = mgmc::build_hierarchy(*problem, obs, c->H, err);
   if (s != MGMC_OK) {
     delete c;
     return fail(s, err);
+  }
+  // the host hierarchy (and its ENOTSPD checks) needs no device
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    delete c;
+    return fail(MGMC_EDEVICE, "no HIP device available");
   }
   c->beta = c->H.beta;
   c->lv.assign(c->levels, mgmc::DevLevel{});
@@ -638,8 +816,16 @@ mgmc_status mgmc_setup(const mgmc_problem* problem, const mgmc_obs* obs, void* h
   };
   for (int l = 0; l < c->levels; ++l)
     if ((s = upload_level(c, l)) != MGMC_OK) return cleanup(s);
-  if ((s = c->upload(c->K, c->H.K)) != MGMC_OK) return cleanup(s);
-  if ((s = c->upload(c->Uinv, c->H.Uinv)) != MGMC_OK) return cleanup(s);
+  if (!c->H.K.empty()) {
+    if ((s = c->upload(c->K, c->H.K)) != MGMC_OK) return cleanup(s);
+    if ((s = c->upload(c->Uinv, c->H.Uinv)) != MGMC_OK) return cleanup(s);
+  }
+  if (c->sampler == MGMC_SAMPLER_CHOLESKY) {
+    if ((s = c->upload(c->Uband, c->H.Uband)) != MGMC_OK) return cleanup(s);
+    std::vector<double>().swap(c->H.Uband);
+    if ((s = c->alloc(c->mu, size_t(c->lv[0].N))) != MGMC_OK) return cleanup(s);
+    if ((s = c->alloc(c->bandx, size_t(c->lv[0].N) * problem->nchains)) != MGMC_OK) return cleanup(s);
+  }
   if ((s = c->alloc(c->mcur, 1)) != MGMC_OK) return cleanup(s);
   c->L.mcur = c->mcur;
   {
@@ -667,7 +853,7 @@ mgmc_status mgmc_setup(const mgmc_problem* problem, const mgmc_obs* obs, void* h
   }
   // the bottom of the V-cycle as one launch: the highest level below the
   // finest with at most 63 nodes per axis, if its levels fit in LDS
-  if (problem->dim == 2 && top >= 2) {
+  if (problem->dim == 2 && top >= 2 && !c->generic && c->sampler == MGMC_SAMPLER_MGMC) {
     int lm = 0;
     for (int l = 1; l < top && l < mgmc::kMaxCoarseLevels; ++l)
       if (c->lv[l].g.n <= 63) lm = l;
@@ -724,7 +910,7 @@ mgmc_status mgmc_setup(const mgmc_problem* problem, const mgmc_obs* obs, void* h
   // keep only what later calls need on the host: the observation columns
   for (int l = 0; l < c->levels; ++l) {
     mgmc::HostLevel& h = c->H.lv[l];
-    std::vector<double>().swap(h.st);
+    if (c->sampler != MGMC_SAMPLER_CHOLESKY) std::vector<double>().swap(h.st);
     for (int d = 0; d < 2; ++d) {
       std::vector<double>().swap(h.C[d]);
       std::vector<double>().swap(h.G[d]);
@@ -748,6 +934,18 @@ mgmc_status mgmc_sample(mgmc_ctx* c, int64_t m0, int64_t nsamples, void* theta, 
     fL = c->fL;
   }
   c->posterior_ready = false;
+  if (c->sampler == MGMC_SAMPLER_CHOLESKY) {
+    c->mu_set = rhs != nullptr;
+    if (rhs) {  // mu = At^{-1} f by the banded factor on the host, once per call
+      const int64_t N = c->lv[0].N;
+      std::vector<double> f(static_cast<size_t>(N));
+      MGMC_HIP(hipStreamSynchronize(c->stream));
+      MGMC_HIP(hipMemcpy(f.data(), rhs, size_t(N) * sizeof(double), hipMemcpyDeviceToHost));
+      std::vector<double> mu = band_solve_device(c, f.data());
+      if (mu.empty()) return fail(MGMC_EDEVICE, "copying the banded factor failed");
+      MGMC_HIP(hipMemcpy(c->mu, mu.data(), size_t(N) * sizeof(double), hipMemcpyHostToDevice));
+    }
+  }
   return run_samples(c, fL, m0, nsamples, theta, F, qoi);
 }
 
@@ -773,6 +971,12 @@ mgmc_status mgmc_posterior_sample(mgmc_ctx* c, const double* y, int64_t m0, int6
       MGMC_HIP(hipMemcpy(c->fL, pf.data(), pf.size() * sizeof(float), hipMemcpyHostToDevice));
     } else {
       MGMC_HIP(hipMemcpy(c->fL, padded.data(), padded.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    if (c->sampler == MGMC_SAMPLER_CHOLESKY) {
+      std::vector<double> mu = band_solve_device(c, f.data());
+      if (mu.empty()) return fail(MGMC_EDEVICE, "copying the banded factor failed");
+      MGMC_HIP(hipMemcpy(c->mu, mu.data(), mu.size() * sizeof(double), hipMemcpyHostToDevice));
+      c->mu_set = true;
     }
     c->last_y.assign(y, y + c->beta);
     c->posterior_ready = true;
@@ -806,6 +1010,7 @@ mgmc_status mgmc_set_option(mgmc_ctx* c, int32_t option, int64_t value) {
     case MGMC_OPT_CHAINS_PER_BLOCK:
       if (value < 0 || value > 65535) return fail(MGMC_EINVAL, "chains per block out of range");
       c->sweep_cpb = int(value);
+      c->L.cpb_force = c->prob.dim == 3 ? int(value) : 0;
       return MGMC_OK;
     case MGMC_OPT_COARSE_FUSED:
       if (value < 0) return fail(MGMC_EINVAL, "MGMC_OPT_COARSE_FUSED must be >= 0");
@@ -966,6 +1171,8 @@ mgmc_status mgmc_batch_sample(mgmc_batch* b, int64_t m0, int64_t nsamples, void*
     mgmc_ctx* c = b->ctx[i];
     const int top = c->levels - 1;
     hipError_t e = mgmc::launch_unpack(c->L, c->lv[top], thetas[i], c->lv[top].buf[0]);
+    if (e == hipSuccess && c->lv[top].f != nullptr)
+      e = mgmc::launch_broadcast(c->L, c->lv[top], c->posterior_ready ? c->fL : nullptr, c->lv[top].f);
     if (e == hipSuccess) e = mgmc::launch_set_m(c->stream, c->mcur, m0);
     if (e != hipSuccess) s = fail(MGMC_EDEVICE, std::string("batch start: ") + hipGetErrorString(e));
   }

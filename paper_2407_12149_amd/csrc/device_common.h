@@ -13,7 +13,7 @@ constexpr int kBlock = 256;
 
 
 static __device__ __forceinline__ int64_t pidx(const Geom& g, int i1, int i2, int i3) {
-  return int64_t(i1 + 3) + int64_t(g.px) * (int64_t(i2) + int64_t(g.py) * i3);
+  return g.o0 + int64_t(i1 + 3) + int64_t(g.px) * (int64_t(i2) + int64_t(g.py) * i3);
 }
 
 // (B_{l-1} v)(J) for coarse padded site iJ and chain c (0 without a low-rank term).

@@ -4,9 +4,9 @@
 // One Philox block gives two normals: u1 from words (x0, x1), u2 from (x2, x3)
 // as the top 53 bits plus half an ulp scaled by 2^-53; z = sqrt(-2 ln u1)
 // (cos, sin)(2 pi u2).  The double-precision logarithm and sine/cosine are
-// short series written out here (few live registers inside the sweeps).  The single-precision variant takes the top 24 bits of
-// x0 and x2, so its normals track the double ones to ~1e-7 from the same
-// counters.
+// short series written out here (few live registers inside the sweeps).  The
+// single-precision variant forms the same uniforms (see Gauss<float>), so its
+// normals track the double ones to float rounding from the same counters.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -175,16 +175,30 @@ struct Gauss<double> {
   }
 };
 
+// Single precision from the same 53-bit uniforms as the double path, so that
+// the two differ by float rounding only.  u = hi + lo with hi = (x0 >> 8)
+// 2^-24 (exact in float) and 0 < lo < 2^-24 the remaining 29 bits plus half
+// an ulp; ln u = ln hi + lo / hi (the dropped terms of log1p are below
+// 2^-25 absolute, since lo / hi <= 2^-12) when hi >= 2^-12, else ln(hi + lo)
+// directly (|ln u| > 8 there).  The angle 2 pi u2 = 2 pi hi2 + 2 pi lo2 is
+// applied as sin/cos of the first part rotated by the small second one.
+// Radius and angle thus carry float rounding relative to the double
+// transform, not the 24-bit truncation of u.
 template <>
 struct Gauss<float> {
   static __device__ __forceinline__ void pair(const Block4& x, float& z0, float& z1) {
-    const float u1 = (float(x.x0 >> 8) + 0.5f) * 0x1p-24f;
-    const float u2 = (float(x.x2 >> 8) + 0.5f) * 0x1p-24f;
-    const float rad = sqrtf(-2.0f * logf(u1));
+    const float h1 = float(x.x0 >> 8) * 0x1p-24f;
+    const float l1 = (float(((x.x0 & 0xffu) << 21) | (x.x1 >> 11)) + 0.5f) * 0x1p-53f;
+    const bool big = h1 >= 0x1p-12f;
+    const float lg = logf(big ? h1 : h1 + l1) + (big ? __fdividef(l1, h1) : 0.0f);
+    const float rad = sqrtf(-2.0f * lg);
+    const float h2 = float(x.x2 >> 8) * 0x1p-24f;
+    const float l2 = (float(((x.x2 & 0xffu) << 21) | (x.x3 >> 11)) + 0.5f) * 0x1p-53f;
     float sn, cs;
-    sincospif(2.0f * u2, &sn, &cs);
-    z0 = rad * cs;
-    z1 = rad * sn;
+    sincospif(2.0f * h2, &sn, &cs);
+    const float d = 6.28318530717958647692f * l2;
+    z0 = rad * fmaf(-d, sn, cs);
+    z1 = rad * fmaf(d, cs, sn);
   }
 };
 

@@ -1,13 +1,15 @@
 // Structured construction of the MGMC hierarchy (host, FP64).
 //
-//  * fine operator: s (kappa^2 I - div(a grad)) by finite differences with face
-//    coefficients and zero Dirichlet data (paper Sec. 5.1.1);
+//  * fine operator (paper Sec. 5.1.1): s (kappa^2 I - div(a grad)) by finite
+//    differences with face coefficients and zero Dirichlet data, bilinear
+//    finite elements for -Laplace + kappa^2, or the 13-point squared shifted
+//    Laplace with clamped boundaries;
 //  * prolongation: column J of P carries w_J(delta) at fine node 2J + delta,
 //    multilinear by default (Sec. 3.1, Sec. 5.1.3 "Samplers");
 //  * Galerkin coarse operators A_{l-1} = P^T A_l P and B_{l-1} = P^T B_l
 //    (eq. A_ell_1_B_ell_1), assembled stencil-wise;
 //  * low-rank smoother data C = M^{-1} B, S = Gamma + B^T C, G = C S^{-1}
-//    (Alg. 3 with omega = 1, M = D + L in colour order);
+//    (Alg. 3, M = D / omega + L in colour order);
 //  * the coarsest exact sampler from the Cholesky factor At_0 = U^T U
 //    (Sec. 3.5 and the Cholesky sampler of Sec. 5.1.3).
 #include "hierarchy.h"
@@ -40,27 +42,30 @@ struct Geo {
   }
 };
 
-inline int stencil_index(int dim, const int* d) {
+// Stencil entry of offset d in a stencil of radius R.
+inline int stencil_index(int dim, int R, const int* d) {
   int t = 0, m = 1;
   for (int k = 0; k < dim; ++k) {
-    t += (d[k] + 1) * m;
-    m *= 3;
+    t += (d[k] + R) * m;
+    m *= 2 * R + 1;
   }
   return t;
 }
 
-inline void stencil_delta(int dim, int t, int* d) {
+inline void stencil_delta(int dim, int R, int t, int* d) {
   for (int k = 0; k < dim; ++k) {
-    d[k] = t % 3 - 1;
-    t /= 3;
+    d[k] = t % (2 * R + 1) - R;
+    t /= 2 * R + 1;
   }
 }
 
-// Multilinear weight of offset delta, or the user's weight of coarse node J.
-inline double pweight(const HostLevel& fine, int S, int dim, int64_t J, int t) {
-  if (!fine.wP.empty()) return fine.wP[size_t(J) * S + t];
+// Multilinear weight of prolongation offset delta (t = index of delta in the
+// 3^dim box), or the user's weight of coarse node J.
+inline double pweight(const HostLevel& fine, int dim, int64_t J, int t) {
+  const int SP = dim == 2 ? 9 : 27;
+  if (!fine.wP.empty()) return fine.wP[size_t(J) * SP + t];
   int d[3];
-  stencil_delta(dim, t, d);
+  stencil_delta(dim, 1, t, d);
   double w = 1.0;
   for (int k = 0; k < dim; ++k)
     if (d[k] != 0) w *= 0.5;
@@ -112,14 +117,95 @@ void fine_operator(const mgmc_problem& p, HostHierarchy& H) {
         for (int j = 0; j < dim; ++j) d[j] = 0;
         if (i[k] < n) {
           d[k] = 1;
-          f.st[size_t(stencil_index(dim, d)) * f.N + lin] = -s * ih2 * ap;
+          f.st[size_t(stencil_index(dim, 1, d)) * f.N + lin] = -s * ih2 * ap;
         }
         if (i[k] > 1) {
           d[k] = -1;
-          f.st[size_t(stencil_index(dim, d)) * f.N + lin] = -s * ih2 * am;
+          f.st[size_t(stencil_index(dim, 1, d)) * f.N + lin] = -s * ih2 * am;
         }
       }
       f.st[size_t(centre) * f.N + lin] = s * p.kappa2 + s * ih2 * faces;
+    }
+  });
+}
+
+// Bilinear (Q1) finite elements for -Laplace + kappa^2 on the uniform 2D grid
+// (Sec. 5.1.1): each site's 9-point row is the sum, over the four cells
+// around it, of the element stiffness (1/6)[4 -1 -2 -1; ...] and kappa^2 times
+// the element mass (h^2/36)[4 2 1 2; ...] between the site's corner and the
+// neighbour's corner of that cell, scaled by s / h^2.  Couplings to boundary
+// nodes are dropped (u = 0 there).
+void fem_q1_operator(const mgmc_problem& p, HostHierarchy& H) {
+  HostLevel& f = H.lv[H.L];
+  const int n = p.n;
+  f.st.assign(size_t(H.S) * f.N, 0.0);
+  const double h = H.h, sc = H.scale / (h * h);
+  // element matrices, corners counter-clockwise from the lower left
+  const double KE[4][4] = {{4, -1, -2, -1}, {-1, 4, -1, -2}, {-2, -1, 4, -1}, {-1, -2, -1, 4}};
+  const double ME[4][4] = {{4, 2, 1, 2}, {2, 4, 2, 1}, {1, 2, 4, 2}, {2, 1, 2, 4}};
+  const int CX[4] = {0, 1, 1, 0}, CY[4] = {0, 0, 1, 1};
+  Geo g{2, n, f.N};
+  parallel_for(f.N, [&](int64_t b, int64_t e) {
+    int i[2], d[2];
+    for (int64_t lin = b; lin < e; ++lin) {
+      g.coords(lin, i);
+      for (int a = 0; a < 4; ++a) {  // the site is corner a of the cell
+        const int cx = i[0] - CX[a], cy = i[1] - CY[a];
+        for (int bb = 0; bb < 4; ++bb) {
+          const int j0 = cx + CX[bb], j1 = cy + CY[bb];
+          if (j0 < 1 || j0 > n || j1 < 1 || j1 > n) continue;
+          d[0] = j0 - i[0];
+          d[1] = j1 - i[1];
+          const double v = KE[a][bb] / 6.0 + p.kappa2 * (h * h) * ME[a][bb] / 36.0;
+          f.st[size_t(stencil_index(2, 1, d)) * f.N + lin] += sc * v;
+        }
+      }
+    }
+  });
+}
+
+// Squared shifted Laplace (Sec. 5.1.1), 2D:
+// s [h^-4 B13 + 2 kappa^2 h^-2 L5 + kappa^4 I] with the 13-point biharmonic
+// difference B13 (20 at the centre, -8 at the axis neighbours, 2 at the
+// diagonal ones, 1 two steps along an axis) and the 5-point -Laplace L5.
+// Clamped boundary: boundary nodes are 0, and a reach to the ghost node one
+// step outside the boundary lands on the interior node it mirrors.
+void ssl13_operator(const mgmc_problem& p, HostHierarchy& H) {
+  HostLevel& f = H.lv[H.L];
+  const int n = p.n;
+  f.st.assign(size_t(H.S) * f.N, 0.0);
+  const double s = H.scale, ih2 = 1.0 / (H.h * H.h), ih4 = ih2 * ih2, k2 = p.kappa2;
+  const int OFF[13][2] = {{0, 0},  {1, 0},   {-1, 0}, {0, 1}, {0, -1}, {1, 1}, {1, -1},
+                          {-1, 1}, {-1, -1}, {2, 0},  {-2, 0}, {0, 2}, {0, -2}};
+  const double WB[13] = {20, -8, -8, -8, -8, 2, 2, 2, 2, 1, 1, 1, 1};
+  Geo g{2, n, f.N};
+  parallel_for(f.N, [&](int64_t b, int64_t e) {
+    int i[2], j[2], d[2];
+    for (int64_t lin = b; lin < e; ++lin) {
+      g.coords(lin, i);
+      for (int t = 0; t < 13; ++t) {
+        bool skip = false;
+        for (int k = 0; k < 2; ++k) {
+          j[k] = i[k] + OFF[t][k];
+          if (j[k] == 0 || j[k] == n + 1) skip = true;
+          if (j[k] == -1) j[k] = 1;
+          if (j[k] == n + 2) j[k] = n;
+          d[k] = j[k] - i[k];
+        }
+        if (!skip) f.st[size_t(stencil_index(2, 2, d)) * f.N + lin] += s * ih4 * WB[t];
+      }
+      for (int t = 0; t < 5; ++t) {
+        bool skip = false;
+        for (int k = 0; k < 2; ++k) {
+          j[k] = i[k] + OFF[t][k];
+          if (j[k] < 1 || j[k] > n) skip = true;
+          d[k] = OFF[t][k];
+        }
+        if (!skip)
+          f.st[size_t(stencil_index(2, 2, d)) * f.N + lin] += s * 2.0 * k2 * ih2 * (t == 0 ? 4.0 : -1.0);
+      }
+      d[0] = d[1] = 0;
+      f.st[size_t(stencil_index(2, 2, d)) * f.N + lin] += s * k2 * k2;
     }
   });
 }
@@ -129,23 +215,24 @@ void fine_operator(const mgmc_problem& p, HostHierarchy& H) {
 // lies in the support of the columns K covering it.
 void galerkin(const HostHierarchy& H, int lf, HostLevel& c) {
   const HostLevel& f = H.lv[lf];
-  const int dim = H.dim, S = H.S, nf = f.n, nc = c.n;
+  const int dim = H.dim, S = H.S, R = H.R, nf = f.n, nc = c.n;
+  const int SP = dim == 2 ? 9 : 27;  // prolongation offsets {-1,0,1}^dim
   Geo gf{dim, nf, f.N}, gc{dim, nc, c.N};
   c.st.assign(size_t(S) * c.N, 0.0);
   parallel_for(c.N, [&](int64_t b, int64_t e) {
     int J[3], d1[3], d2[3], i[3], j[3], K[3], opts[3][2], dl[3][2], nopt[3];
     for (int64_t Jl = b; Jl < e; ++Jl) {
       gc.coords(Jl, J);
-      for (int t1 = 0; t1 < S; ++t1) {
-        stencil_delta(dim, t1, d1);
+      for (int t1 = 0; t1 < SP; ++t1) {
+        stencil_delta(dim, 1, t1, d1);
         for (int k = 0; k < dim; ++k) i[k] = 2 * J[k] + d1[k];
-        const double w1 = pweight(f, S, dim, Jl, t1);
+        const double w1 = pweight(f, dim, Jl, t1);
         if (w1 == 0.0) continue;
         const int64_t il = gf.lin(i);
         for (int t2 = 0; t2 < S; ++t2) {
           const double a = f.st[size_t(t2) * f.N + il];
           if (a == 0.0) continue;
-          stencil_delta(dim, t2, d2);
+          stencil_delta(dim, R, t2, d2);
           bool inside = true;
           for (int k = 0; k < dim; ++k) {
             j[k] = i[k] + d2[k];
@@ -174,8 +261,8 @@ void galerkin(const HostHierarchy& H, int lf, HostLevel& c) {
               dd[k] = dl[k][o];
               dk[k] = K[k] - J[k];
             }
-            const double w2 = pweight(f, S, dim, gc.lin(K), stencil_index(dim, dd));
-            c.st[size_t(stencil_index(dim, dk)) * c.N + Jl] += w1 * a * w2;
+            const double w2 = pweight(f, dim, gc.lin(K), stencil_index(dim, 1, dd));
+            c.st[size_t(stencil_index(dim, R, dk)) * c.N + Jl] += w1 * a * w2;
           }
         }
       }
@@ -186,7 +273,7 @@ void galerkin(const HostHierarchy& H, int lf, HostLevel& c) {
 // B_{l-1} = P^T B_l column by column.
 void restrict_observations(const HostHierarchy& H, int lf, HostLevel& c) {
   const HostLevel& f = H.lv[lf];
-  const int dim = H.dim, S = H.S, nc = c.n;
+  const int dim = H.dim, nc = c.n;
   Geo gf{dim, f.n, f.N}, gc{dim, nc, c.N};
   c.Bcol.assign(f.Bcol.size(), {});
   for (size_t col = 0; col < f.Bcol.size(); ++col) {
@@ -215,7 +302,7 @@ void restrict_observations(const HostHierarchy& H, int lf, HostLevel& c) {
           dd[k] = dl[k][o];
         }
         const int64_t Kl = gc.lin(K);
-        acc[Kl] += pweight(f, S, dim, Kl, stencil_index(dim, dd)) * b;
+        acc[Kl] += pweight(f, dim, Kl, stencil_index(dim, 1, dd)) * b;
       }
     }
     c.Bcol[col].assign(acc.begin(), acc.end());
@@ -262,7 +349,8 @@ bool dense_inverse(std::vector<double> a, int m, std::vector<double>& inv) {
 // spread non-zeros by one stencil radius.
 mgmc_status lowrank_level(HostHierarchy& H, int l, std::string& err) {
   HostLevel& lv = H.lv[l];
-  const int dim = H.dim, S = H.S, n = lv.n, beta = H.beta, nq = H.ncolours;
+  const int dim = H.dim, S = H.S, n = lv.n, beta = H.beta, nq = H.ncolours, R = H.R;
+  const int q = R + 1;
   const int centre = (S - 1) / 2;
   Geo g{dim, n, lv.N};
   for (int dir = 0; dir < 2; ++dir) {
@@ -278,8 +366,8 @@ mgmc_status lowrank_level(HostHierarchy& H, int l, std::string& err) {
         if (lv.Bcol[j].empty()) continue;
         int64_t vol = 1;
         for (int k = 0; k < dim; ++k) {
-          lo[k] = std::max(1, lo[k] - (nq - 1));
-          hi[k] = std::min(n, hi[k] + (nq - 1));
+          lo[k] = std::max(1, lo[k] - (nq - 1) * R);
+          hi[k] = std::min(n, hi[k] + (nq - 1) * R);
           ext[k] = hi[k] - lo[k] + 1;
           vol *= ext[k];
         }
@@ -294,14 +382,15 @@ mgmc_status lowrank_level(HostHierarchy& H, int l, std::string& err) {
           b[boxlin(i)] = bv;
         }
         for (int qq = 0; qq < nq; ++qq) {
-          const int colour = forward_colour(dim, dir == 0 ? qq : nq - 1 - qq);
+          const int colour = forward_colour(dim, q, dir == 0 ? qq : nq - 1 - qq);
           for (int64_t v = 0; v < vol; ++v) {
             int64_t r = v;
-            int c = 0;
+            int c = 0, mult = 1;
             for (int k = 0; k < dim; ++k) {
               i[k] = lo[k] + int(r % ext[k]);
               r /= ext[k];
-              c |= (i[k] & 1) << k;
+              c += (i[k] % q) * mult;
+              mult *= q;
             }
             if (c != colour) continue;
             const int64_t il = g.lin(i);
@@ -310,7 +399,7 @@ mgmc_status lowrank_level(HostHierarchy& H, int l, std::string& err) {
               if (t == centre) continue;
               const double a = lv.st[size_t(t) * lv.N + il];
               if (a == 0.0) continue;
-              stencil_delta(dim, t, d);
+              stencil_delta(dim, R, t, d);
               int jn[3];
               bool in = true;
               for (int k = 0; k < dim; ++k) {
@@ -319,7 +408,7 @@ mgmc_status lowrank_level(HostHierarchy& H, int l, std::string& err) {
               }
               if (in) s -= a * x[boxlin(jn)];
             }
-            x[v] = s / lv.st[size_t(centre) * lv.N + il];
+            x[v] = (H.omega * s) / lv.st[size_t(centre) * lv.N + il];
           }
         }
         for (int64_t v = 0; v < vol; ++v) {
@@ -392,7 +481,7 @@ mgmc_status coarsest(HostHierarchy& H, std::string& err) {
     for (int t = 0; t < S; ++t) {
       const double v = c.st[size_t(t) * N0 + r];
       if (v == 0.0) continue;
-      stencil_delta(H.dim, t, d);
+      stencil_delta(H.dim, H.R, t, d);
       bool in = true;
       for (int k = 0; k < H.dim; ++k) {
         j[k] = i[k] + d[k];
@@ -444,13 +533,22 @@ mgmc_status coarsest(HostHierarchy& H, std::string& err) {
 
 }  // namespace
 
-int forward_colour(int dim, int q) { return dim == 2 ? kFwd2[q] : kFwd3[q]; }
+int forward_colour(int dim, int nclass, int q) {
+  if (nclass == 3) return q;
+  return dim == 2 ? kFwd2[q] : kFwd3[q];
+}
 
 mgmc_status build_hierarchy(const mgmc_problem& p, const mgmc_obs* obs, HostHierarchy& H,
                             std::string& err) {
   H.dim = p.dim;
-  H.S = p.dim == 2 ? 9 : 27;
-  H.ncolours = 1 << p.dim;
+  H.op = p.op;
+  H.R = p.op == MGMC_OP_SSL13 ? 2 : 1;
+  H.S = 1;
+  for (int k = 0; k < p.dim; ++k) H.S *= 2 * H.R + 1;
+  H.ncolours = 1;
+  for (int k = 0; k < p.dim; ++k) H.ncolours *= H.R + 1;
+  H.omega = p.omega > 0.0 ? p.omega : 1.0;
+  H.level0_lowrank = p.sampler == MGMC_SAMPLER_GIBBS || (p.sampler == MGMC_SAMPLER_MGMC && p.nu0 > 0);
   H.L = p.levels - 1;
   H.h = 1.0 / (p.n + 1);
   H.scale = p.scale > 0 ? p.scale : std::pow(H.h, p.dim);
@@ -461,9 +559,14 @@ mgmc_status build_hierarchy(const mgmc_problem& p, const mgmc_obs* obs, HostHier
     for (int k = 0; k < p.dim; ++k) N *= nl;
     H.lv[l].N = N;
   }
-  fine_operator(p, H);
+  if (p.op == MGMC_OP_FEM_Q1)
+    fem_q1_operator(p, H);
+  else if (p.op == MGMC_OP_SSL13)
+    ssl13_operator(p, H);
+  else
+    fine_operator(p, H);
   if (p.prolong_w && H.L >= 1) {
-    const size_t cnt = size_t(H.lv[H.L - 1].N) * H.S;
+    const size_t cnt = size_t(H.lv[H.L - 1].N) * (p.dim == 2 ? 9 : 27);
     H.lv[H.L].wP.assign(p.prolong_w, p.prolong_w + cnt);
   }
   for (int l = H.L; l >= 1; --l) galerkin(H, l, H.lv[l - 1]);
@@ -487,12 +590,131 @@ mgmc_status build_hierarchy(const mgmc_problem& p, const mgmc_obs* obs, HostHier
       f.Bcol[j].assign(col.begin(), col.end());
     }
     for (int l = H.L; l >= 1; --l) restrict_observations(H, l, H.lv[l - 1]);
-    for (int l = 1; l <= H.L; ++l) {
+    for (int l = H.level0_lowrank ? 0 : 1; l <= H.L; ++l) {
       mgmc_status st = lowrank_level(H, l, err);
       if (st != MGMC_OK) return st;
     }
   }
+  if (p.sampler == MGMC_SAMPLER_CHOLESKY) return band_cholesky(H, err);
+  if (H.level0_lowrank) return MGMC_OK;
   return coarsest(H, err);
+}
+
+// Banded Cholesky At = U^T U of the single level, lexicographic order.  The
+// band is the largest |i - j| of a non-zero of At (stencil reach, widened by
+// the couplings B Gamma^{-1} B^T of each observation's sites).  Right-looking
+// in panels of kPanel rows: a panel's rows are finished one by one (each
+// updates the rest of the panel), then the panel's rank-kPanel update of the
+// next `band` rows runs over host threads.
+mgmc_status band_cholesky(HostHierarchy& H, std::string& err) {
+  const HostLevel& lv = H.lv[H.L];
+  const int64_t N = lv.N;
+  const int dim = H.dim, R = H.R, S = H.S;
+  Geo g{dim, lv.n, N};
+  int64_t band = 0;
+  int dvec[3], iv[3];
+  for (int t = 0; t < S; ++t) {
+    stencil_delta(dim, R, t, dvec);
+    int64_t off = 0, m = 1;
+    for (int k = 0; k < dim; ++k) {
+      off += dvec[k] * m;
+      m *= lv.n;
+    }
+    bool used = false;
+    for (int64_t i = 0; i < N && !used; ++i) used = lv.st[size_t(t) * N + i] != 0.0;
+    if (used) band = std::max(band, off < 0 ? -off : off);
+  }
+  for (int j = 0; j < H.beta; ++j)
+    if (!lv.Bcol[j].empty()) band = std::max(band, lv.Bcol[j].back().first - lv.Bcol[j].front().first);
+  const int64_t W = band + 1;
+  if (N * W > (int64_t(1) << 31)) {
+    err = "banded factor exceeds 2^31 entries";
+    return MGMC_EUNSUPPORTED;
+  }
+  std::vector<double> U(size_t(N) * W, 0.0);
+  for (int64_t i = 0; i < N; ++i) {
+    g.coords(i, iv);
+    for (int t = 0; t < S; ++t) {
+      const double v = lv.st[size_t(t) * N + i];
+      if (v == 0.0) continue;
+      stencil_delta(dim, R, t, dvec);
+      int jv[3];
+      bool in = true;
+      for (int k = 0; k < dim; ++k) {
+        jv[k] = iv[k] + dvec[k];
+        if (jv[k] < 1 || jv[k] > lv.n) in = false;
+      }
+      if (!in) continue;
+      const int64_t j = g.lin(jv);
+      if (j >= i) U[size_t(i) * W + (j - i)] += v;
+    }
+  }
+  for (int b = 0; b < H.beta; ++b)
+    for (const auto& [r1, v1] : lv.Bcol[b])
+      for (const auto& [r2, v2] : lv.Bcol[b])
+        if (r2 >= r1) U[size_t(r1) * W + (r2 - r1)] += v1 * v2 / H.gamma[b];
+  constexpr int64_t kPanel = 32;
+  for (int64_t p0 = 0; p0 < N; p0 += kPanel) {
+    const int64_t p1 = std::min(N, p0 + kPanel);
+    for (int64_t i = p0; i < p1; ++i) {
+      double* ui = &U[size_t(i) * W];
+      if (!(ui[0] > 0.0)) {
+        err = "single-level matrix At is not positive definite";
+        return MGMC_ENOTSPD;
+      }
+      const double d = std::sqrt(ui[0]);
+      ui[0] = d;
+      const double id = 1.0 / d;
+      for (int64_t k = 1; k < W; ++k) ui[k] *= id;
+      // rows i+1 .. p1-1 of the panel
+      for (int64_t j = i + 1; j < p1 && j - i < W; ++j) {
+        const double uij = ui[j - i];
+        if (uij == 0.0) continue;
+        double* uj = &U[size_t(j) * W];
+        for (int64_t k = j; k - i < W; ++k) uj[k - j] -= uij * ui[k - i];
+      }
+    }
+    // rank-(p1 - p0) update of rows p1 .. p1 + band - 1
+    const int64_t r0 = p1, r1 = std::min(N, p1 + band);
+    parallel_for(r1 - r0, [&](int64_t b0, int64_t e0) {
+      for (int64_t j = r0 + b0; j < r0 + e0; ++j) {
+        double* uj = &U[size_t(j) * W];
+        for (int64_t i = p0; i < p1; ++i) {
+          if (j - i >= W) continue;
+          const double* ui = &U[size_t(i) * W];
+          const double uij = ui[j - i];
+          if (uij == 0.0) continue;
+          const int64_t kend = std::min(N, i + W);
+          for (int64_t k = j; k < kend; ++k) uj[k - j] -= uij * ui[k - i];
+        }
+      }
+    });
+  }
+  H.band = band;
+  H.Uband = std::move(U);
+  return MGMC_OK;
+}
+
+std::vector<double> band_solve(const HostHierarchy& H, const double* f) {
+  const int64_t N = H.lv[H.L].N, W = H.band + 1;
+  const std::vector<double>& U = H.Uband;
+  std::vector<double> g(size_t(N), 0.0);
+  // U^T g = f (U^T lower triangular): column-oriented forward substitution
+  for (int64_t i = 0; i < N; ++i) g[size_t(i)] = f ? f[i] : 0.0;
+  for (int64_t i = 0; i < N; ++i) {
+    const double* ui = &U[size_t(i) * W];
+    g[size_t(i)] /= ui[0];
+    const double gi = g[size_t(i)];
+    for (int64_t k = 1; k < W && i + k < N; ++k) g[size_t(i + k)] -= ui[k] * gi;
+  }
+  // U mu = g: row-oriented back substitution
+  for (int64_t i = N - 1; i >= 0; --i) {
+    const double* ui = &U[size_t(i) * W];
+    double s = g[size_t(i)];
+    for (int64_t k = 1; k < W && i + k < N; ++k) s -= ui[k] * g[size_t(i + k)];
+    g[size_t(i)] = s / ui[0];
+  }
+  return g;
 }
 
 std::vector<double> posterior_rhs(const HostHierarchy& H, const double* y) {

@@ -21,9 +21,16 @@
 
 namespace mgmc {
 
-Geom make_geom(int dim, int n) {
+Geom make_geom(int dim, int n, int halo) {
   Geom g;
   g.n = n;
+  if (halo == 2) {
+    g.px = ((n + 6) + 3) / 4 * 4;
+    g.py = n + 4;
+    g.o0 = g.px;
+    g.Np = int64_t(g.px) * g.py;
+    return g;
+  }
   g.px = ((n + 5) + 3) / 4 * 4;
   g.py = n + 2;
   g.Np = int64_t(g.px) * g.py * (dim == 3 ? (n + 2) : 1);
@@ -31,6 +38,14 @@ Geom make_geom(int dim, int n) {
 }
 
 namespace {
+
+// Relaxed site update of the random SOR sweep (Sec. 3.3, eq. SOR_smoother;
+// noise covariance (2 - omega)/omega D, eq. low_rank_smoother_covariance):
+// (1 - omega) theta_i + omega s / A_ii + sqrt(omega (2 - omega) / A_ii) z.
+template <typename T>
+__device__ __forceinline__ T sor_site(T old, T s, T ivd, T isd, T z, T om) {
+  return (T(1) - om) * old + om * (s * ivd) + sqrt(om * (T(2) - om)) * isd * z;
+}
 
 // One Gauss-Seidel site update (neighbours in ascending index order).
 template <typename T, int DIM, bool CROSS>
@@ -56,7 +71,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const T* __restrict__ coef,
                                                   const T* __restrict__ f, int64_t fcs, Geom g,
                                                   int colour, uint32_t word,
                                                   const int64_t* __restrict__ mcur, uint32_t seed,
-                                                  uint32_t chain0, int cpb, int nchains) {
+                                                  uint32_t chain0, int cpb, int nchains, T om) {
   constexpr int S = DIM == 2 ? 9 : 27;
   constexpr int NB = CROSS ? 2 * DIM : S - 1;  // neighbours per site
   const int p1 = colour & 1, p2 = (colour >> 1) & 1, p3 = (colour >> 2) & 1;
@@ -119,8 +134,13 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const T* __restrict__ coef,
     const Block4 blk = philox10(pair, word | uint32_t(colour), m, 0u, seed, chain0 + c);
     T z[2];
     Gauss<T>::pair(blk, z[0], z[1]);
-    th[ia] = s[0] * ivd[0] + z[0] * isd[0];
-    if (two) th[ia + 2] = s[1] * ivd[1] + z[1] * isd[1];
+    if (om == T(1)) {
+      th[ia] = s[0] * ivd[0] + z[0] * isd[0];
+      if (two) th[ia + 2] = s[1] * ivd[1] + z[1] * isd[1];
+    } else {
+      th[ia] = sor_site(th[ia], s[0], ivd[0], isd[0], z[0], om);
+      if (two) th[ia + 2] = sor_site(th[ia + 2], s[1], ivd[1], isd[1], z[1], om);
+    }
   }
 }
 
@@ -136,7 +156,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_parity3d(const T* __restrict__
                                                            Geom g, int parity, uint32_t word,
                                                            const int64_t* __restrict__ mcur,
                                                            uint32_t seed, uint32_t chain0, int cpb,
-                                                           int nchains) {
+                                                           int nchains, T om) {
   const int n = g.n;
   const int qmax = ((n + 1) / 2 + 1) / 2;  // pairs per row for the odd x-sublattice
   const int64_t total = int64_t(qmax) * n * n;
@@ -192,8 +212,13 @@ __global__ __launch_bounds__(kBlock) void k_sweep_parity3d(const T* __restrict__
     const Block4 blk = philox10(pair, word | uint32_t(colour), m, 0u, seed, chain0 + c);
     T z[2];
     Gauss<T>::pair(blk, z[0], z[1]);
-    th[ia] = s[0] * ivd[0] + z[0] * isd[0];
-    if (two) th[ia + 2] = s[1] * ivd[1] + z[1] * isd[1];
+    if (om == T(1)) {
+      th[ia] = s[0] * ivd[0] + z[0] * isd[0];
+      if (two) th[ia + 2] = s[1] * ivd[1] + z[1] * isd[1];
+    } else {
+      th[ia] = sor_site(th[ia], s[0], ivd[0], isd[0], z[0], om);
+      if (two) th[ia + 2] = sor_site(th[ia + 2], s[1], ivd[1], isd[1], z[1], om);
+    }
   }
 }
 
@@ -390,7 +415,7 @@ __global__ __launch_bounds__(kBlock) void k_coarsest(const double* __restrict__ 
                                                      const T* __restrict__ f0, int64_t fcs,
                                                      T* __restrict__ theta0, Geom g, int N0,
                                                      const int64_t* __restrict__ mcur,
-                                                     uint32_t seed, uint32_t chain0) {
+                                                     uint32_t seed, uint32_t chain0, uint32_t word) {
   extern __shared__ double sh[];
   double* fv = sh;
   double* zv = sh + N0;
@@ -402,7 +427,7 @@ __global__ __launch_bounds__(kBlock) void k_coarsest(const double* __restrict__ 
     fv[k] = f0 ? double(f0[int64_t(c) * fcs + pidx(g, i1, i2, i3)]) : 0.0;
   }
   for (int p = threadIdx.x; 2 * p < N0; p += blockDim.x) {
-    const Block4 blk = philox10(uint32_t(p), 0u, m, 2u, seed, chain0 + c);
+    const Block4 blk = philox10(uint32_t(p), word, m, 2u, seed, chain0 + c);
     double z0, z1;
     Gauss<double>::pair(blk, z0, z1);
     zv[2 * p] = z0;
@@ -683,7 +708,8 @@ inline unsigned blocks_for(int64_t count) { return unsigned((count + kBlock - 1)
 
 // Chains per thread for kernels that keep a site's stencil in registers
 // across chains: up to 16, halved while fewer than ~2048 blocks would remain.
-inline int chain_group(int64_t blocks, int nchains) {
+inline int chain_group(int64_t blocks, int nchains, int force = 0) {
+  if (force > 0) return std::min(std::min(force, 16), nchains);
   int cpb = 1;
   while (cpb < 16 && cpb < nchains && blocks * ((nchains + 2 * cpb - 1) / (2 * cpb)) >= 2048) cpb *= 2;
   return cpb;
@@ -723,17 +749,17 @@ hipError_t launch_sweep_colour(const Launch& L, const DevLevel& lv, void* theta,
   const int m3 = L.dim == 3 ? ext((colour >> 2) & 1) : 1;
   const int64_t total = int64_t((m1 + 1) / 2) * m2 * m3;
   if (total == 0) return hipSuccess;
-  const int cpb = chain_group(blocks_for(total), L.nchains);
+  const int cpb = chain_group(blocks_for(total), L.nchains, L.cpb_force);
   dim3 grid(blocks_for(total), unsigned((L.nchains + cpb - 1) / cpb));
   MGMC_DISPATCH(L, {
     if (lv.cross)
       k_sweep<T, DIM, true><<<grid, kBlock, 0, L.stream>>>(
           (const T*)lv.coef, (const T*)lv.invd, (const T*)lv.isqd, (T*)theta, (const T*)f, fcs,
-          lv.g, colour, word, L.mcur, L.seed, L.chain0, cpb, L.nchains);
+          lv.g, colour, word, L.mcur, L.seed, L.chain0, cpb, L.nchains, T(L.omega));
     else
       k_sweep<T, DIM, false><<<grid, kBlock, 0, L.stream>>>(
           (const T*)lv.coef, (const T*)lv.invd, (const T*)lv.isqd, (T*)theta, (const T*)f, fcs,
-          lv.g, colour, word, L.mcur, L.seed, L.chain0, cpb, L.nchains);
+          lv.g, colour, word, L.mcur, L.seed, L.chain0, cpb, L.nchains, T(L.omega));
   });
   return hipGetLastError();
 }
@@ -744,12 +770,12 @@ hipError_t launch_sweep_parity3d(const Launch& L, const DevLevel& lv, void* thet
   const int n = lv.g.n;
   const int64_t total = int64_t(((n + 1) / 2 + 1) / 2) * n * n;
   const int64_t blocks = blocks_for(total);
-  const int cpb = chain_group(blocks, L.nchains);
+  const int cpb = chain_group(blocks, L.nchains, L.cpb_force);
   dim3 grid(unsigned(blocks), unsigned((L.nchains + cpb - 1) / cpb));
   if (L.fp32)
-    k_sweep_parity3d<float><<<grid, kBlock, 0, L.stream>>>((const float*)lv.coef, (const float*)lv.invd, (const float*)lv.isqd, (float*)theta, (const float*)f, fcs, lv.g, parity, word, L.mcur, L.seed, L.chain0, cpb, L.nchains);
+    k_sweep_parity3d<float><<<grid, kBlock, 0, L.stream>>>((const float*)lv.coef, (const float*)lv.invd, (const float*)lv.isqd, (float*)theta, (const float*)f, fcs, lv.g, parity, word, L.mcur, L.seed, L.chain0, cpb, L.nchains, float(L.omega));
   else
-    k_sweep_parity3d<double><<<grid, kBlock, 0, L.stream>>>((const double*)lv.coef, (const double*)lv.invd, (const double*)lv.isqd, (double*)theta, (const double*)f, fcs, lv.g, parity, word, L.mcur, L.seed, L.chain0, cpb, L.nchains);
+    k_sweep_parity3d<double><<<grid, kBlock, 0, L.stream>>>((const double*)lv.coef, (const double*)lv.invd, (const double*)lv.isqd, (double*)theta, (const double*)f, fcs, lv.g, parity, word, L.mcur, L.seed, L.chain0, cpb, L.nchains, L.omega);
   return hipGetLastError();
 }
 
@@ -780,10 +806,10 @@ hipError_t launch_restrict_2stage(const Launch& L, const DevLevel& fine, const v
                                   void* scratch, const DevLevel& coarse, const void* f,
                                   int64_t fcs, const LowRankRhs& lr) {
   if (scratch == nullptr || scratch == theta) return hipErrorInvalidValue;
-  const int rcpb = chain_group(blocks_for(fine.N), L.nchains);
+  const int rcpb = chain_group(blocks_for(fine.N), L.nchains, L.cpb_force);
   // FP32: a group of chains per thread amortises the index arithmetic; FP64
   // moves twice the bytes and runs faster with one chain per thread
-  const int ccpb = L.fp32 ? chain_group(blocks_for(coarse.N), L.nchains) : 1;
+  const int ccpb = L.fp32 ? chain_group(blocks_for(coarse.N), L.nchains, L.cpb_force) : 1;
   dim3 g1(blocks_for(fine.N), unsigned((L.nchains + rcpb - 1) / rcpb));
   dim3 g2(blocks_for(coarse.N), unsigned((L.nchains + ccpb - 1) / ccpb));
   MGMC_DISPATCH(L, {
@@ -799,10 +825,23 @@ hipError_t launch_restrict_2stage(const Launch& L, const DevLevel& fine, const v
   return hipGetLastError();
 }
 
+hipError_t launch_restrict_residual(const Launch& L, const DevLevel& fine, const void* r,
+                                    const DevLevel& coarse, const LowRankRhs& lr) {
+  const int ccpb = L.fp32 ? chain_group(blocks_for(coarse.N), L.nchains, L.cpb_force) : 1;
+  dim3 g2(blocks_for(coarse.N), unsigned((L.nchains + ccpb - 1) / ccpb));
+  MGMC_DISPATCH(L, {
+    if (fine.wP)
+      k_restrict_residual<T, DIM, true><<<g2, kBlock, 0, L.stream>>>((const T*)r, fine.g, (T*)coarse.f, coarse.g, fine.wP, lr, ccpb, L.nchains);
+    else
+      k_restrict_residual<T, DIM, false><<<g2, kBlock, 0, L.stream>>>((const T*)r, fine.g, (T*)coarse.f, coarse.g, nullptr, lr, ccpb, L.nchains);
+  });
+  return hipGetLastError();
+}
+
 hipError_t launch_prolong(const Launch& L, const DevLevel& fine, void* theta,
                           const DevLevel& coarse, const void* psi) {
   // FP32: a group of chains per thread (as in the restriction)
-  const int cpb = L.fp32 ? chain_group(blocks_for(fine.N), L.nchains) : 1;
+  const int cpb = L.fp32 ? chain_group(blocks_for(fine.N), L.nchains, L.cpb_force) : 1;
   dim3 grid(blocks_for(fine.N), unsigned((L.nchains + cpb - 1) / cpb));
   MGMC_DISPATCH(L, {
     if (fine.wP)
@@ -814,13 +853,13 @@ hipError_t launch_prolong(const Launch& L, const DevLevel& fine, void* theta,
 }
 
 hipError_t launch_coarsest(const Launch& L, const DevLevel& lv0, const void* f0, int64_t fcs,
-                           void* theta0, const double* K, const double* Uinv) {
+                           void* theta0, const double* K, const double* Uinv, uint32_t word) {
   if (L.mcur == nullptr) return hipErrorInvalidValue;
   const int N0 = int(lv0.N);
   const size_t shmem = size_t(2) * N0 * sizeof(double);
   dim3 grid(unsigned((N0 + 3) / 4), unsigned(L.nchains));
   MGMC_DISPATCH(L, {
-    k_coarsest<T, DIM><<<grid, kBlock, shmem, L.stream>>>(K, Uinv, (const T*)f0, fcs, (T*)theta0, lv0.g, N0, L.mcur, L.seed, L.chain0);
+    k_coarsest<T, DIM><<<grid, kBlock, shmem, L.stream>>>(K, Uinv, (const T*)f0, fcs, (T*)theta0, lv0.g, N0, L.mcur, L.seed, L.chain0, word);
   });
   return hipGetLastError();
 }
@@ -1102,14 +1141,14 @@ hipError_t launch_qoi(const Launch& L, const DevLevel& fine, const void* theta, 
 
 // chain groups in FP32 (as in the prolongation), one chain per thread in FP64
 hipError_t launch_unpack(const Launch& L, const DevLevel& lv, const void* user, void* theta) {
-  const int cpb = L.fp32 ? chain_group(blocks_for(lv.N), L.nchains) : 1;
+  const int cpb = L.fp32 ? chain_group(blocks_for(lv.N), L.nchains, L.cpb_force) : 1;
   dim3 grid(blocks_for(lv.N), unsigned((L.nchains + cpb - 1) / cpb));
   MGMC_DISPATCH(L, { k_unpack<T, DIM><<<grid, kBlock, 0, L.stream>>>((const T*)user, (T*)theta, lv.g, lv.N, cpb, L.nchains); });
   return hipGetLastError();
 }
 
 hipError_t launch_pack(const Launch& L, const DevLevel& lv, const void* theta, void* user) {
-  const int cpb = L.fp32 ? chain_group(blocks_for(lv.N), L.nchains) : 1;
+  const int cpb = L.fp32 ? chain_group(blocks_for(lv.N), L.nchains, L.cpb_force) : 1;
   dim3 grid(blocks_for(lv.N), unsigned((L.nchains + cpb - 1) / cpb));
   MGMC_DISPATCH(L, { k_pack<T, DIM><<<grid, kBlock, 0, L.stream>>>((const T*)theta, (T*)user, lv.g, lv.N, cpb, L.nchains); });
   return hipGetLastError();

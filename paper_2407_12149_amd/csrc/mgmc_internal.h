@@ -18,9 +18,14 @@ struct Geom {
   int px = 0;      // x pitch
   int py = 0;      // rows per plane (n + 2)
   int64_t Np = 0;  // padded entries per field
+  int64_t o0 = 0;  // offset of row 0 (px with a two-node halo, else 0)
 };
 
-Geom make_geom(int dim, int n);
+// halo 1: the layout above.  halo 2 (2D levels with 5 x 5 stencils): rows
+// -1 .. n+2 and x positions from i1 = -3, so node (i1, i2) sits at
+// o0 + (i1 + 3) + px i2 with o0 = px, px = round_up(n + 6, 4), py = n + 4;
+// every reach of two nodes from an interior node stays inside the field.
+Geom make_geom(int dim, int n, int halo = 1);
 
 struct DevLevel {
   Geom g;
@@ -144,14 +149,19 @@ struct Launch {
   const int64_t* mcur = nullptr;  // device: current sample index
   int lowrank_mfma = 0;           // low-rank G t product on the matrix cores
   const double* bm_table = nullptr;  // device: Box-Muller table (device_rng.h), kBmTable doubles
+  int cpb_force = 0;  // > 0: chains per thread of the per-site kernels (3D contexts), else by size
+  double omega = 1.0;  // SOR relaxation of the per-colour sweeps (others need 1)
 };
 
 // Host: fill the Box-Muller table of gauss_pair_tab (device_rng.h).
 constexpr int kBmTable = 770;
 void fill_bm_table(double* t);
 
-// Noise counter word 1: level << 8 | sweep << 4 | colour.
-__host__ __device__ inline uint32_t noise_word(int level, int sigma) { return (uint32_t(level) << 8) | (uint32_t(sigma) << 4); }
+// Noise counter word 1: visit << 16 | level << 8 | sweep << 4 | colour, the
+// visit counting the calls of a level within one update (W-cycles).
+__host__ __device__ inline uint32_t noise_word(int level, int sigma, int visit = 0) {
+  return (uint32_t(visit) << 16) | (uint32_t(level) << 8) | (uint32_t(sigma) << 4);
+}
 
 // One colour pass, in place on theta.
 hipError_t launch_sweep_colour(const Launch& L, const DevLevel& lv, void* theta, const void* f,
@@ -193,7 +203,24 @@ hipError_t launch_restrict_2stage(const Launch& L, const DevLevel& fine, const v
 hipError_t launch_prolong(const Launch& L, const DevLevel& fine, void* theta,
                           const DevLevel& coarse, const void* psi);
 hipError_t launch_coarsest(const Launch& L, const DevLevel& lv0, const void* f0, int64_t fcs,
-                           void* theta0, const double* K, const double* Uinv);
+                           void* theta0, const double* K, const double* Uinv, uint32_t word = 0);
+// Levels with 5 x 5 stencils (2D, nine colours (i_1 mod 3) + 3 (i_2 mod 3)):
+// one colour pass in place, and the residual into scratch followed by the
+// restriction P^T r (minus B_{l-1} v).
+hipError_t launch_sweep_wide(const Launch& L, const DevLevel& lv, void* theta, const void* f,
+                             int64_t fcs, uint32_t word, int colour);
+hipError_t launch_restrict_wide(const Launch& L, const DevLevel& fine, const void* theta,
+                                void* scratch, const DevLevel& coarse, const void* f, int64_t fcs,
+                                const LowRankRhs& lr);
+hipError_t launch_restrict_residual(const Launch& L, const DevLevel& fine, const void* r,
+                                    const DevLevel& coarse, const LowRankRhs& lr);
+// Exact single-level sample theta = mu + U^{-1} z with the banded factor
+// U (N rows of band + 1 entries, FP64): x ([nchains][N] FP64 scratch) takes
+// the normals z (tag 2, counter word `word`), the back substitution runs in
+// place, and theta (padded, state precision) receives mu + x; mu may be null
+// (f = 0).
+hipError_t launch_band_sample(const Launch& L, const DevLevel& lv, const double* U, int64_t band,
+                              const double* mu, double* x, void* theta, uint32_t word);
 // Low-rank correction after a sweep in direction dir (Alg. 3):
 // theta -= G (B^T theta - Gamma xi) with xi = Gamma^{-1/2} zeta; t receives
 // B^T theta - Gamma xi per chain ([nchains][beta] scratch).  v_out != nullptr
@@ -217,6 +244,8 @@ hipError_t launch_qoi(const Launch& L, const DevLevel& fine, const void* theta, 
 hipError_t launch_unpack(const Launch& L, const DevLevel& lv, const void* user, void* theta);
 hipError_t launch_pack(const Launch& L, const DevLevel& lv, const void* theta, void* user);
 hipError_t launch_unpack_rhs(const Launch& L, const DevLevel& lv, const double* user, void* f);
+// dst[c] = src (padded, state precision) for every chain, or 0 where src is null.
+hipError_t launch_broadcast(const Launch& L, const DevLevel& lv, const void* src, void* dst);
 hipError_t launch_set_m(hipStream_t s, int64_t* mcur, int64_t value);
 hipError_t launch_advance_m(hipStream_t s, int64_t* mcur);
 

@@ -17,6 +17,10 @@ MGMC_OK, MGMC_EINVAL, MGMC_ENOMEM, MGMC_EDEVICE, MGMC_ENOTSPD, MGMC_EUNSUPPORTED
 MGMC_FP64, MGMC_FP32 = 0, 1
 MGMC_OPT_TILED_SWEEPS, MGMC_OPT_SWEEP_VARIANT, MGMC_OPT_CHAINS_PER_BLOCK = 1, 2, 3
 MGMC_OPT_COARSE_FUSED, MGMC_OPT_LOWRANK_MFMA = 4, 5
+MGMC_OP_FD, MGMC_OP_FEM_Q1, MGMC_OP_SSL13 = 0, 1, 2
+MGMC_SAMPLER_MGMC, MGMC_SAMPLER_GIBBS, MGMC_SAMPLER_CHOLESKY = 0, 1, 2
+_OPS = {"fd": MGMC_OP_FD, "fem": MGMC_OP_FEM_Q1, "ssl13": MGMC_OP_SSL13}
+_SAMPLERS = {"mgmc": MGMC_SAMPLER_MGMC, "gibbs": MGMC_SAMPLER_GIBBS, "cholesky": MGMC_SAMPLER_CHOLESKY}
 
 EXPORTED = [
     "mgmc_setup", "mgmc_sample", "mgmc_posterior_sample", "mgmc_levels", "mgmc_level_sites",
@@ -37,6 +41,8 @@ class mgmc_problem(ctypes.Structure):
         ("scale", ctypes.c_double), ("face_coef", _dp), ("prolong_w", _dp),
         ("precision", ctypes.c_int32), ("nchains", ctypes.c_int32),
         ("chain_offset", ctypes.c_int64), ("seed", ctypes.c_uint64),
+        ("op", ctypes.c_int32), ("cycle_gamma", ctypes.c_int32), ("omega", ctypes.c_double),
+        ("nu0", ctypes.c_int32), ("sampler", ctypes.c_int32),
     ]
 
 
@@ -143,8 +149,10 @@ def _stream_handle(stream):
 
 def mgmc_setup(problem, obs=None, stream=None):
     """problem: dict with dim, n, levels, kappa2 and optional scale, face_coef,
-    prolong_w, nu1, nu2, precision ('fp64'|'fp32'), nchains, chain_offset, seed.
-    obs: (ptr, idx, val, gamma) numpy arrays or None.  Returns an opaque handle."""
+    prolong_w, nu1, nu2, precision ('fp64'|'fp32'), nchains, chain_offset, seed,
+    op ('fd'|'fem'|'ssl13'), cycle_gamma, omega, nu0, sampler
+    ('mgmc'|'gibbs'|'cholesky').  obs: (ptr, idx, val, gamma) numpy arrays or
+    None.  Returns an opaque handle."""
     lib = load_library()
     keep = []
 
@@ -166,7 +174,11 @@ def mgmc_setup(problem, obs=None, stream=None):
         prolong_w=None if pw is None else pw.ctypes.data_as(_dp),
         precision=MGMC_FP32 if prec in ("fp32", MGMC_FP32) else MGMC_FP64,
         nchains=int(problem.get("nchains", 1)), chain_offset=int(problem.get("chain_offset", 0)),
-        seed=int(problem.get("seed", 0)))
+        seed=int(problem.get("seed", 0)),
+        op=_OPS.get(problem.get("op", "fd"), problem.get("op", 0)),
+        cycle_gamma=int(problem.get("cycle_gamma", 1)), omega=float(problem.get("omega", 1.0)),
+        nu0=int(problem.get("nu0", 0)),
+        sampler=_SAMPLERS.get(problem.get("sampler", "mgmc"), problem.get("sampler", 0)))
     o = None
     if obs is not None:
         ptr, idx, val, gamma = obs

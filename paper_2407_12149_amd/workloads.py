@@ -273,12 +273,12 @@ def config(name):
     if name == "posterior255":
         # full posterior at scale: 255^3, lognormal a (correlation length 0.1,
         # variance 1), 256 sensors averaging 3^3 nodes, Gamma = 0.005^2 I,
-        # 64 chains, kappa = 10 as in the 2D posterior
+        # 64 chains, kappa = 1 (the paper's 3D correlation length 1/kappa = 1)
         n, dim, m = 255, 3, 256
         face = lognormal_faces_fft3(n, 0.1, 1.0, seed=4)
         ptr, idx, val = patch_sensors(n, dim, m, seed=5)
         gamma = np.full(m, 0.005 ** 2)
-        return dict(name=name, dim=dim, n=n, levels=6, kappa2=100.0, face_coef=face,
+        return dict(name=name, dim=dim, n=n, levels=6, kappa2=1.0, face_coef=face,
                     obs=(ptr, idx, val, gamma), y=observed_values(m, seed=6), nchains=64,
                     nsamples=5000, seed=0, F=subcube_qoi(n, dim))
     if name == "batched512":

@@ -1,0 +1,282 @@
+"""GPU against the oracle on the launch shapes that the other parity tests
+leave to themselves: FP32 chains (against the FP64 oracle, to a derived
+per-site bound), 3D chain groups above two with a ragged last group and a
+wide low-rank term (beta = 64, many matrix-core row tiles), the autotuned
+per-level forms the benchmark times at 1023^2, the batched shape classes at
+their batch size, and the long-run IACT against its closed form tau_inf
+(eq. tau_int, Thm. IACT).
+
+FP32 bound.  A site update in FP32 forms s = f_i - sum_j A_ij theta_j and
+theta_i = s / A_ii with `nb` products (8 on 9-point levels, 24 on 5 x 5
+ones) and three more operations, each rounded to relative u = 2^-24 of
+magnitudes up to |f_i| + sum_j |A_ij theta_j| <= |f_i| + r A_ii max|theta|
+with r = max_i sum_{j != i} |A_ij| / A_ii (1 for the diagonally dominant
+second-order operators, 2.2 for the 13-point squared Laplacian); its stored
+stencil is rounded likewise, and its normal is formed from the same 53-bit
+uniforms as the FP64 one (device_rng.h), so |z32 - z64| <= 4 u sqrt(-2 ln u1)
+<= 2.1e-6 at the largest radius the uniforms allow.  A site update thus
+injects at most about (nb + 3) u (r max|theta| + max_i |f_i| / A_ii).  The f
+term matters for the posterior: the sweep takes f = B Gamma^{-1} y, which is
+large at the sensor sites (|f| / A_ii ~ 10^3 for Gamma = 1e-4), and the
+low-rank correction then cancels most of the swept value, leaving its
+rounding.  A cycle touches a site at most six times (two sweeps per level,
+the transfers to and from the level below, the coarse correction added back)
+and the noise-free update contracts at rate rho, so the accumulated
+difference stays below 6 (nb + 3) u (r max|theta| + max|f| / A_ii) / (1 - rho)
+at every site; the tests check this with rho = 0.5 for the second-order
+operators (measured rates 0.1 - 0.45) and 0.85 for the 13-point one.
+"""
+import concurrent.futures as cf
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import NOISE_ZERO
+from paper_2407_12149_amd import diagnostics, workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+U32 = 2.0 ** -24
+
+
+def fp32_bound(theta_max, f=None, diag=None, nb=8, r=1.0, rho=0.5):
+    """Absolute per-site bound of |theta32 - theta64| (module docstring)."""
+    rhs = 0.0 if f is None else float(np.max(np.abs(f) / diag))
+    return 6 * (nb + 3) * U32 * (r * theta_max + rhs) / (1.0 - rho)
+
+
+def posterior_rhs(n, dim, obs, y):
+    ptr, idx, val, gamma = obs
+    f = np.zeros(n ** dim)
+    for j in range(len(ptr) - 1):
+        f[idx[ptr[j]:ptr[j + 1]]] += val[ptr[j]:ptr[j + 1]] * y[j] / gamma[j]
+    return f
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def oracle_of(prob, obs=None, y=None):
+    o = oracle.Oracle(prob["dim"], prob["n"], prob["levels"], prob["kappa2"],
+                      face_coef=prob.get("face_coef"), nu1=prob.get("nu1", 1),
+                      nu2=prob.get("nu2", 1), seed=prob.get("seed", 0))
+    if obs is not None:
+        o.set_obs(*obs)
+    if y is not None:
+        o.set_posterior_rhs(y)
+    return o
+
+
+def oracle_traj(o, N, ids, nsamples, threads=8):
+    def one(c):
+        return o.chain(np.zeros(N), 0, nsamples, chain=c, traj=True)[2]
+
+    with cf.ThreadPoolExecutor(max_workers=min(threads, len(ids))) as ex:
+        return dict(zip(ids, ex.map(one, ids)))
+
+
+def run_stepwise(sampler, y, nsamples):
+    out = []
+    for k in range(nsamples):
+        if y is None:
+            sampler.sample(k, 1, want_qoi=False)
+        else:
+            sampler.posterior_sample(y, k, 1, want_qoi=False)
+        torch.cuda.synchronize()
+        out.append(sampler.theta.double().cpu().numpy().copy())
+    return out
+
+
+def worst_rel(got_steps, ref, ids, cols=None):
+    worst = 0.0
+    for k, got in enumerate(got_steps):
+        for j, c in enumerate(ids):
+            g = got[c if cols is None else cols[j]]
+            want = ref[c][k]
+            worst = max(worst, np.abs(g - want).max() / np.abs(want).max())
+    return worst
+
+
+@pytest.mark.parametrize("dim,n,levels,beta", [(2, 127, 5, 8), (3, 31, 4, 6)])
+def test_fp32_chains_track_the_fp64_oracle(dim, n, levels, beta):
+    from paper_2407_12149_amd import mgmc
+    if dim == 2:
+        face = workloads.face_array(n, 2, workloads.fourier_log_field(2, nmodes=16, seed=1))
+    else:
+        face = workloads.face_array(n, 3, workloads.gaussian_log_field(3, 0.1, 1.0, seed=3,
+                                                                        nfeatures=64))
+    ptr, idx, val = workloads.patch_sensors(n, dim, beta, seed=2)
+    obs = (ptr, idx, val, np.full(beta, 1e-4))
+    y = workloads.observed_values(beta, seed=4)
+    prob = dict(dim=dim, n=n, levels=levels, kappa2=100.0, face_coef=face, nchains=3, seed=0,
+                precision="fp32")
+    log(f"[fp32-oracle] {n}^{dim} beta {beta}")
+    o = oracle_of(prob, obs, y)
+    ref = oracle_traj(o, n ** dim, [0, 1, 2], 5)
+    s = mgmc.Sampler(prob, obs=obs)
+    if dim == 3:
+        s.set_option(mgmc.MGMC_OPT_CHAINS_PER_BLOCK, 2)  # chain groups of 2 and 1
+    got = run_stepwise(s, y, 5)
+    s.close()
+    diag = o.dense(levels - 1, 8)
+    f = posterior_rhs(n, dim, obs, y)
+    for c in range(3):
+        worst, tmax = 0.0, 0.0
+        for k in range(5):
+            worst = max(worst, np.abs(got[k][c] - ref[c][k]).max())
+            tmax = max(tmax, np.abs(ref[c][k]).max())
+        bound = fp32_bound(tmax, f, diag)
+        log(f"[fp32-oracle] {n}^{dim} chain {c}: worst site difference {worst:.2e} "
+            f"(max|theta| {tmax:.2f}, max|f|/A_ii {np.max(np.abs(f) / diag):.1f}, bound {bound:.2e})")
+        assert worst <= bound
+
+
+@pytest.mark.parametrize("cpb", [4, 16])
+def test_3d_chain_groups_and_wide_low_rank(cpb):
+    """31^3 posterior, 4 levels, 19 chains in groups of `cpb` (ragged last
+    group), 64 volume sensors: the unfused low-rank step with beta = 64 runs
+    the matrix-core apply over many 64-row tiles.  FP64 stepwise at 1e-10."""
+    from paper_2407_12149_amd import mgmc
+    n, beta = 31, 64
+    face = workloads.face_array(n, 3, workloads.gaussian_log_field(3, 0.1, 1.0, seed=7,
+                                                                    nfeatures=64))
+    ptr, idx, val = workloads.patch_sensors(n, 3, beta, seed=8)
+    obs = (ptr, idx, val, np.full(beta, 2.5e-5))
+    y = workloads.observed_values(beta, seed=9)
+    prob = dict(dim=3, n=n, levels=4, kappa2=1.0, face_coef=face, nchains=19, seed=5)
+    log(f"[3d-groups] 31^3 x 19 chains, cpb {cpb}, beta {beta}")
+    o = oracle_of(prob, obs, y)
+    ids = list(range(19))
+    ref = oracle_traj(o, n ** 3, ids, 2)
+    s = mgmc.Sampler(prob, obs=obs)
+    s.set_option(mgmc.MGMC_OPT_CHAINS_PER_BLOCK, cpb)
+    got = run_stepwise(s, y, 2)
+    s.close()
+    e = worst_rel(got, ref, ids)
+    log(f"[3d-groups] cpb {cpb}: worst {e:.2e}")
+    assert e <= TOL64
+
+
+def test_posterior1023_tuned_forms_keep_parity():
+    """The benchmark's launch configuration: the autotuned per-level forms
+    (and fused bottom levels if chosen) at 1023^2, 8 chains, graph replay."""
+    from paper_2407_12149_amd import autotune, mgmc
+    cfg = workloads.config("posterior1023")
+    prob = dict(dim=2, n=1023, levels=7, kappa2=cfg["kappa2"], face_coef=cfg["face_coef"],
+                nchains=8, seed=0)
+    log("[tuned1023] oracle, 8 chains x 1 update")
+    o = oracle_of(prob, cfg["obs"], cfg["y"])
+
+    def one(c):
+        return o.chain(np.zeros(1023 * 1023), 0, 1, chain=c)[0]
+
+    with cf.ThreadPoolExecutor(max_workers=8) as ex:
+        ref = list(ex.map(one, range(8)))
+    s = mgmc.Sampler(prob, obs=cfg["obs"])
+    s.posterior_sample(cfg["y"], 0, 2, want_qoi=False)  # right-hand side for the timer
+    best = autotune.autotune(s, updates=4)
+    log(f"[tuned1023] forms {best['levels']} fused {best.get('fused')}")
+    s.theta.zero_()
+    s.set_graph(True)
+    s.posterior_sample(cfg["y"], 0, 1, want_qoi=False)
+    torch.cuda.synchronize()
+    got = s.theta.cpu().numpy()
+    s.close()
+    for c in range(8):
+        e = np.abs(got[c] - ref[c]).max() / np.abs(ref[c]).max()
+        assert e <= TOL64, f"chain {c}: {e:.3e}"
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batched_shape_classes_against_oracle(precision):
+    """The batched workload's largest 2D and 3D shapes at their batch size
+    (102 chains each, kappa^2 = 25, prior), tuned, advanced together as
+    branches of one graph; chains 0, 51 and 101 against the oracle."""
+    from paper_2407_12149_amd import autotune, mgmc
+    shapes = [(2, 511, 7), (3, 63, 4)]
+    samplers, refs = [], []
+    ids = [0, 51, 101]
+    for dim, n, levels in shapes:
+        prob = dict(dim=dim, n=n, levels=levels, kappa2=25.0, nchains=102, seed=0,
+                    precision=precision)
+        log(f"[batch-oracle] {precision} {n}^{dim} x 102")
+        o = oracle_of(prob)
+        refs.append(oracle_traj(o, n ** dim, ids, 2, threads=3))
+        s = mgmc.Sampler(prob)
+        autotune.autotune(s, updates=2)
+        samplers.append(s)
+    b = mgmc.Batch(samplers, updates_per_launch=2)
+    b.sample(0, 2)
+    torch.cuda.synchronize()
+    for (dim, n, _), s, ref in zip(shapes, samplers, refs):
+        got = s.theta.double().cpu().numpy()
+        for c in ids:
+            tmax = max(np.abs(ref[c][0]).max(), np.abs(ref[c][1]).max())
+            e = np.abs(got[c] - ref[c][1]).max()
+            tol = TOL64 * np.abs(ref[c][1]).max() if precision == "fp64" else fp32_bound(tmax)
+            log(f"[batch-oracle] {precision} {n}^{dim} chain {c}: {e:.2e} (bound {tol:.2e})")
+            assert e <= tol
+    b.close()
+    for s in samplers:
+        s.close()
+
+
+def test_long_run_iact_matches_tau_inf():
+    """tau_inf = 1 + 2 sum_s F^T X^s v / F^T v with v = At^{-1} F (eq. tau_int;
+    X the noise-free update, Lemma MGidentity-mean-cov), from the oracle's
+    noise-free cycles on a 255^2 posterior; the GPU chains' Wolff estimate over
+    500 burn-in + 6000 updates of 8 chains must lie within 3 of its errors."""
+    from paper_2407_12149_amd import mgmc
+    n, beta = 255, 64
+    face = workloads.face_array(n, 2, workloads.fourier_log_field(2, nmodes=64, seed=1))
+    ptr, idx, val = workloads.patch_sensors(n, 2, beta, seed=2)
+    obs = (ptr, idx, val, np.full(beta, 1e-4))
+    y = workloads.observed_values(beta, seed=3)
+    F = workloads.subcube_qoi(n, 2)
+    prob = dict(dim=2, n=n, levels=5, kappa2=100.0, face_coef=face, nchains=8, seed=0)
+    log("[tau] oracle tau_inf at 255^2")
+    o = oracle_of(prob, obs)
+    o.set_noise(NOISE_ZERO)
+    o.set_rhs(F)  # noise-free chain with f = F converges to v = At^{-1} F
+    v = np.zeros(n * n)
+    for k in range(200):
+        nv = o.cycle(v, m=k)
+        done = np.abs(nv - v).max() <= 1e-15 * np.abs(nv).max()
+        v = nv
+        if done:
+            break
+    o.set_rhs(None)
+    denom = F @ v
+    tau_inf, x = 1.0, v.copy()
+    for k in range(200):
+        x = o.cycle(x, m=k)
+        term = (F @ x) / denom
+        tau_inf += 2.0 * term
+        if abs(term) < 1e-16:
+            break
+    s = mgmc.Sampler(prob, obs=obs)
+    s.set_graph(True)
+    Fd = torch.tensor(F, device="cuda")
+    s.posterior_sample(y, 0, 500, want_qoi=False)
+    q = s.posterior_sample(y, 500, 6000, F=Fd)
+    torch.cuda.synchronize()
+    s.close()
+    qs = q.cpu().numpy()
+    est = [diagnostics.iact_wolff(qs[:, c]) for c in range(8)]
+    tau = float(np.mean([e[0] for e in est]))
+    err = float(np.sqrt(sum(e[1] ** 2 for e in est)) / 8)
+    log(f"[tau] tau_inf {tau_inf:.4f}; GPU {tau:.4f} +- {err:.4f}")
+    assert abs(tau - tau_inf) <= 3 * err

@@ -49,7 +49,10 @@ def setup_status(problem, obs=None):
                           levels=problem.get("levels", 2), nu1=problem.get("nu1", 1),
                           nu2=problem.get("nu2", 1), kappa2=problem.get("kappa2", 1.0), scale=0.0,
                           face_coef=None, prolong_w=None, precision=problem.get("precision", 0),
-                          nchains=problem.get("nchains", 1), chain_offset=0, seed=0)
+                          nchains=problem.get("nchains", 1), chain_offset=0, seed=0,
+                          op=problem.get("op", 0), cycle_gamma=problem.get("cycle_gamma", 1),
+                          omega=problem.get("omega", 1.0), nu0=problem.get("nu0", 0),
+                          sampler=problem.get("sampler", 0))
     st = lib.mgmc_setup(ctypes.byref(p), None if o is None else ctypes.byref(o), None,
                         ctypes.byref(handle))
     if st == mgmc.MGMC_OK:
@@ -61,6 +64,9 @@ def setup_status(problem, obs=None):
     dict(n=10), dict(n=0), dict(dim=4), dict(dim=1), dict(levels=0), dict(levels=5),
     dict(nu1=0), dict(nu2=0), dict(nu1=9, nu2=8), dict(nchains=0), dict(precision=7),
     dict(n=255, levels=2),  # coarsest 127^2 > 4096 sites
+    dict(op=3), dict(op=1, dim=3, n=7), dict(op=2, dim=3, n=7), dict(cycle_gamma=4),
+    dict(cycle_gamma=-1), dict(omega=2.0), dict(omega=-0.5), dict(nu0=9), dict(nu0=-1),
+    dict(sampler=3), dict(sampler=1, levels=2), dict(sampler=2, levels=2),
 ])
 def test_invalid_problem_rejected(bad):
     st, msg = setup_status(bad)
@@ -99,3 +105,14 @@ def test_no_device_reports_edevice():
     st, msg = setup_status({})
     assert st == mgmc.MGMC_EDEVICE
     assert "device" in msg
+
+
+@pytest.mark.parametrize("kappa2", [-1e4, -600.0])
+def test_indefinite_operator_is_not_spd(kappa2):
+    """A negative shift makes A indefinite: with kappa^2 = -1e4 the diagonal
+    itself turns negative, with -600 (below the smallest eigenvalue 2 pi^2 of
+    -Laplace) the coarsest Galerkin matrix has no Cholesky factor.  Both are
+    reported as ENOTSPD by the host set-up, before any device work."""
+    st, msg = setup_status(dict(n=15, levels=2, kappa2=kappa2))
+    assert st == mgmc.MGMC_ENOTSPD, (st, msg)
+    assert msg
