@@ -156,6 +156,22 @@ mgmc_status mgmc_setup(const mgmc_problem* problem, const mgmc_obs* obs, void* h
 mgmc_status mgmc_sample(mgmc_ctx* ctx, int64_t m0, int64_t nsamples, void* theta,
                         const double* rhs, const double* F, double* qoi);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): mgmc_sample with every
+ * kernel launched one by one (no graph of its own) and its per-call scratch
+ * -- the QoI partial sums and the low-rank vectors t and v -- in a fixed
+ * static device array of 4 MiB per GPU instead of the context's buffers.
+ * The call allocates nothing; the context (set up by mgmc_setup) still owns
+ * the level states, operators and factors.  Every call on one GPU shares that
+ * GPU's array (it keeps the last call's contents; nothing in it needs to start
+ * at zero), so calls that overlap on one GPU, on any streams, race.
+ * Arguments and layout as mgmc_sample.  Errors: as mgmc_sample; EINVAL when
+ * the scratch needed, qnb * nchains + 2 beta * nchains doubles (qnb <=
+ * max(256, 16384 / nchains)), exceeds 2^19 doubles; EUNSUPPORTED for the
+ * Cholesky sampler with a right-hand side (its mean is solved on the host). */
+mgmc_status mgmc_sample_noalloc(mgmc_ctx* ctx, int64_t m0, int64_t nsamples, void* theta,
+                                const double* rhs, const double* F, double* qoi);
+
 /* As mgmc_sample for the Bayesian posterior: f_L = B_L Gamma^{-1} y
  * (Sec. 2.3 eq. f_ell_definition), recomputed when y changes.
  *   y: host FP64 [beta] observed values.

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -42,6 +43,34 @@ inline int64_t padded_of(const mgmc::Geom& g, int dim, int64_t lin) {
 
 }  // namespace
 
+// Scratch of mgmc_sample_noalloc: QoI partial sums and the low-rank vectors
+// t and v, for callers that cannot allocate.  Each GPU holds its own copy
+// until the process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns on that device (scratch_ptr).
+constexpr int64_t kScratchDoubles = int64_t(1) << 19;  // 4 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (at the first set-up on it).  nullptr on failure.
+double* scratch_for_current_device(int* dev_out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  *dev_out = dev;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
 namespace mgmc {
 int record_error(int status, const char* msg) {
   g_err = msg;
@@ -74,6 +103,7 @@ struct mgmc_ctx {
   double* mu = nullptr;     // At^{-1} f of the last right-hand side (null: f = 0)
   double* bandx = nullptr;  // [nchains][N] FP64 scratch of the back substitution
   bool mu_set = false;
+  double* scratch = nullptr;  // this device's `scratch` (mgmc_sample_noalloc)
   mgmc::HostHierarchy H;
   std::vector<double> last_y;
   bool posterior_ready = false;
@@ -809,6 +839,14 @@ mgmc_status mgmc_setup(const mgmc_problem* problem, const mgmc_obs* obs, void* h
     return fail(MGMC_EDEVICE, "no HIP device available");
   }
   c->beta = c->H.beta;
+  {
+    int dev = -1;
+    c->scratch = scratch_for_current_device(&dev);
+    if (c->scratch == nullptr) {
+      delete c;
+      return fail(MGMC_EDEVICE, "hipGetSymbolAddress of the no-allocation scratch failed");
+    }
+  }
   c->lv.assign(c->levels, mgmc::DevLevel{});
   auto cleanup = [&](mgmc_status st) {
     mgmc_destroy(c);
@@ -947,6 +985,45 @@ mgmc_status mgmc_sample(mgmc_ctx* c, int64_t m0, int64_t nsamples, void* theta, 
     }
   }
   return run_samples(c, fL, m0, nsamples, theta, F, qoi);
+}
+
+mgmc_status mgmc_sample_noalloc(mgmc_ctx* c, int64_t m0, int64_t nsamples, void* theta,
+                                const double* rhs, const double* F, double* qoi) {
+  g_err.clear();
+  mgmc_status s = check_run_args(c, m0, nsamples, theta, F, qoi);
+  if (s != MGMC_OK) return s;
+  if (c->sampler == MGMC_SAMPLER_CHOLESKY && rhs)
+    return fail(MGMC_EUNSUPPORTED, "the Cholesky sampler solves for its mean on the host (allocates)");
+  const int64_t nch = c->prob.nchains;
+  const int64_t need = int64_t(c->qnb) * nch + 2 * int64_t(c->beta) * nch;
+  if (need > kScratchDoubles)
+    return fail(MGMC_EINVAL, "scratch need " + std::to_string(need) + " doubles exceeds the " +
+                                 std::to_string(kScratchDoubles) + " of the no-allocation scratch");
+  const void* fL = nullptr;
+  if (rhs) {
+    MGMC_LAUNCH(mgmc::launch_unpack_rhs(c->L, c->lv[c->levels - 1], rhs, c->fL));
+    fL = c->fL;
+  }
+  c->posterior_ready = false;
+  // the kernels read partial sums and t, v through these pointers: point them
+  // into the device's scratch for this call (kernels launched one by one, no
+  // graph, no profiling events)
+  double* saved[3] = {c->qpart, c->t, c->v};
+  const bool graph = c->use_graph, prof = c->profiling;
+  c->qpart = c->scratch;
+  if (c->beta > 0) {
+    c->t = c->scratch + int64_t(c->qnb) * nch;
+    c->v = c->t + int64_t(c->beta) * nch;
+  }
+  c->use_graph = false;
+  c->profiling = false;
+  s = run_samples(c, fL, m0, nsamples, theta, F, qoi);
+  c->qpart = saved[0];
+  c->t = saved[1];
+  c->v = saved[2];
+  c->use_graph = graph;
+  c->profiling = prof;
+  return s;
 }
 
 mgmc_status mgmc_posterior_sample(mgmc_ctx* c, const double* y, int64_t m0, int64_t nsamples,

@@ -28,7 +28,7 @@ EXPORTED = [
     "mgmc_last_error", "mgmc_time_updates", "mgmc_batch_create", "mgmc_batch_sample",
     "mgmc_batch_destroy", "mgmc_set_level_option", "mgmc_pnet_param_count", "mgmc_pnet_create", "mgmc_pnet_set_params",
     "mgmc_pnet_get_params", "mgmc_pnet_weights", "mgmc_pnet_loss_grad", "mgmc_pnet_train_step",
-    "mgmc_pnet_destroy",
+    "mgmc_pnet_destroy", "mgmc_sample_noalloc",
 ]
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -77,6 +77,8 @@ def load_library():
                                ctypes.POINTER(vp)]
     lib.mgmc_sample.restype = ctypes.c_int
     lib.mgmc_sample.argtypes = [vp, ctypes.c_int64, ctypes.c_int64, vp, vp, vp, vp]
+    lib.mgmc_sample_noalloc.restype = ctypes.c_int
+    lib.mgmc_sample_noalloc.argtypes = [vp, ctypes.c_int64, ctypes.c_int64, vp, vp, vp, vp]
     lib.mgmc_posterior_sample.restype = ctypes.c_int
     lib.mgmc_posterior_sample.argtypes = [vp, _dp, ctypes.c_int64, ctypes.c_int64, vp, vp, vp]
     lib.mgmc_levels.restype = ctypes.c_int32
@@ -196,6 +198,11 @@ def mgmc_setup(problem, obs=None, stream=None):
 def mgmc_sample(ctx, m0, nsamples, theta, rhs=None, F=None, qoi=None):
     _check(load_library().mgmc_sample(ctx, int(m0), int(nsamples), _ptr(theta), _ptr(rhs),
                                       _ptr(F), _ptr(qoi)))
+
+
+def mgmc_sample_noalloc(ctx, m0, nsamples, theta, rhs=None, F=None, qoi=None):
+    _check(load_library().mgmc_sample_noalloc(ctx, int(m0), int(nsamples), _ptr(theta), _ptr(rhs),
+                                              _ptr(F), _ptr(qoi)))
 
 
 def mgmc_posterior_sample(ctx, y, m0, nsamples, theta, F=None, qoi=None):
