@@ -174,7 +174,9 @@ def batched(args):
             log(f"[bench] batched {prec}: tuned {best}")
             samplers.append(s)
         Fs = [torch.tensor(p["F"], device="cuda") for p in cfg["parts"]]
-        b = mgmc.Batch(samplers, updates_per_launch=10)
+        # every timed step of all 512 chains in one graph launch (the
+        # capture of the whole sampling loop), warm-up in launches of the same size
+        b = mgmc.Batch(samplers, updates_per_launch=min(args.steps, 100))
         log(f"[bench] batched {prec}: warmup {args.warmup}")
         b.sample(0, args.warmup)
         torch.cuda.synchronize()

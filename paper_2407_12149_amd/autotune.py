@@ -1,5 +1,8 @@
 """Autotuner of the sweep kernels.
 
+3D contexts tune the chains per thread of their per-site kernels and the
+form of the finest sweep (parity passes or one launch per colour).
+
 For every level that runs smoother sweeps (levels >= 1) it searches the
 kernel form (LDS tiles, or register-held stencil with 256 or 512 threads per
 block, and on the finest, 5-point level also the form whose state tiles come
@@ -53,7 +56,15 @@ def autotune(sampler, cache_path=None, updates=8, verbose=False):
             cache = json.load(fh)
     if key in cache and "levels" in cache[key]:
         best = dict(cache[key], cached=True)
-    elif sampler.problem["dim"] != 2 or nlev < 2:
+    elif sampler.problem["dim"] == 3:
+        best = dict(_tune_3d(sampler, updates, verbose, key), cached=False)
+        if cache_path:
+            cache[key] = {k: v for k, v in best.items() if k != "cached"}
+            tmp = cache_path + ".tmp"
+            with open(tmp, "w") as fh:
+                json.dump(cache, fh, indent=1, sort_keys=True)
+            os.replace(tmp, cache_path)
+    elif nlev < 2:
         best = {"levels": [None] * nlev, "ms": None, "cached": False}  # per-colour kernels
     else:
         sampler.set_option(mgmc.MGMC_OPT_SWEEP_VARIANT, 3)
@@ -96,8 +107,39 @@ def autotune(sampler, cache_path=None, updates=8, verbose=False):
             with open(tmp, "w") as fh:
                 json.dump(cache, fh, indent=1, sort_keys=True)
             os.replace(tmp, cache_path)
+    if sampler.problem["dim"] == 3:
+        sampler.set_option(mgmc.MGMC_OPT_TILED_SWEEPS, int(best.get("parity", 1)))
+        sampler.set_option(mgmc.MGMC_OPT_CHAINS_PER_BLOCK, int(best.get("cpb", 0)))
+        return best
     sampler.set_option(mgmc.MGMC_OPT_SWEEP_VARIANT, 3)
     sampler.set_option(mgmc.MGMC_OPT_CHAINS_PER_BLOCK, 0)
     sampler.set_option(mgmc.MGMC_OPT_COARSE_FUSED, int(best.get("fused", 0)))
     apply(sampler, best["levels"])
     return best
+
+
+def _tune_3d(sampler, updates, verbose, key):
+    """3D contexts: the chains per thread of the per-site kernels (by size,
+    or forced to 1 .. 16) and, on the 7-point finest level, parity passes or
+    one launch per colour; coordinate descent, forced groups first."""
+    nlev = int(sampler.problem["levels"])
+    choice = {"parity": 1, "cpb": 0}
+    sampler.set_option(mgmc.MGMC_OPT_TILED_SWEEPS, 1)
+    sampler.set_option(mgmc.MGMC_OPT_CHAINS_PER_BLOCK, 0)
+    ms_best = _time(sampler, updates)
+    for c in (1, 2, 4, 8, 16):
+        if c > sampler.nchains:
+            continue
+        sampler.set_option(mgmc.MGMC_OPT_CHAINS_PER_BLOCK, c)
+        ms = _time(sampler, updates)
+        if verbose:
+            print(f"[autotune] {key} 3D chains per thread {c}: {ms:.3f} ms/update", flush=True)
+        if ms < ms_best * (1.0 - MIN_GAIN):
+            ms_best, choice["cpb"] = ms, c
+    sampler.set_option(mgmc.MGMC_OPT_CHAINS_PER_BLOCK, choice["cpb"])
+    sampler.set_option(mgmc.MGMC_OPT_TILED_SWEEPS, 0)
+    ms = _time(sampler, updates)
+    if ms < ms_best * (1.0 - MIN_GAIN):
+        ms_best, choice["parity"] = ms, 0
+    sampler.set_option(mgmc.MGMC_OPT_TILED_SWEEPS, choice["parity"])
+    return {"levels": [None] * nlev, "ms": ms_best, **choice}
