@@ -189,14 +189,29 @@ def batched(args):
         torch.cuda.synchronize()
         seconds = start.elapsed_time(stop) / 1e3
         qs = [q.cpu().numpy() for q in qs]
-        taus = [float(np.mean([diagnostics.iact_wolff(q[:, c])[0] for c in range(q.shape[1])]))
-                for q in qs]
-        ess = sum(q.shape[1] * args.steps / t for q, t in zip(qs, taus)) / seconds
-        runs[prec] = dict(seconds=seconds, qs=qs, taus=taus, ess=ess)
+        if prec == "fp32" and args.iact_samples > 0:
+            # IACT per shape from an untimed run (burn-in, then a fixed number
+            # of updates), independent of --steps
+            nlong = min(args.iact_samples, 2000)
+            log(f"[bench] batched {prec}: IACT from 200 + {nlong} untimed updates")
+            b.sample(10_000_000, 200)
+            ql = b.sample(10_000_200, nlong, Fs=Fs)
+            torch.cuda.synchronize()
+            ql = [q.cpu().numpy() for q in ql]
+            taus = [float(np.mean([diagnostics.iact_wolff(q[:, c])[0] for c in range(q.shape[1])]))
+                    for q in ql]
+        else:
+            taus = [float(np.mean([diagnostics.iact_wolff(q[:, c])[0] for c in range(q.shape[1])]))
+                    for q in qs]
+        runs[prec] = dict(seconds=seconds, qs=qs, taus=taus)
         b.close()
         for s in samplers:
             s.close()
     r32, r64 = runs["fp32"], runs["fp64"]
+    # both precisions use the FP32 run's long-run IACT (the chains are paired)
+    taus = r32["taus"]
+    for r in (r32, r64):
+        r["ess"] = sum(p["nchains"] * args.steps / t for p, t in zip(cfg["parts"], taus)) / r["seconds"]
     out["value"] = r32["ess"]
     out["ms_per_step"] = r32["seconds"] * 1e3 / args.steps
     out["vs_baseline"] = None

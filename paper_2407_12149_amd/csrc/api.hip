@@ -278,7 +278,7 @@ mgmc_status upload_level(mgmc_ctx* c, int l) {
   }
   // a per-chain right-hand side below the finest level; on a 9-point finest
   // level (FEM) too, where the one-launch 2D sweeps take one per chain
-  if (l < H.L || (l == H.L && !d.cross && dim == 2 && l >= 1)) {
+  if (l < H.L || (l == H.L && !d.cross && dim == 2 && (l >= 1 || c->prob.sampler == MGMC_SAMPLER_GIBBS))) {
     s = c->alloc_bytes(d.f, size_t(nch) * Np * c->esz);
     if (s != MGMC_OK) return s;
   }
@@ -594,13 +594,17 @@ mgmc_status enqueue_cycle(mgmc_ctx* c, const void* fL, const double* F, double* 
     // nu1 symmetric Gibbs sweeps (forward then backward Alg. 3) on level 0
     mgmc::DevLevel& lv = c->lv[0];
     const bool fast = tiled && c->H.R == 1 && L.omega == 1.0;
+    // a 9-point level (FEM) sweeps with its per-chain copy of f in the one-launch form
+    const bool own = fast && lv.f != nullptr;
+    const void* fg = own ? lv.f : fL;
+    const int64_t fgs = own ? lv.g.Np : 0;
     for (int j = 0; j < nu1; ++j)
       for (int dir = 0; dir < 2; ++dir) {
         const uint32_t word = mgmc::noise_word(0, 2 * j + dir, 0);
         if (fast) {
           const bool snap = fused_lowrank(c, lv);
           mgmc_status st = timed(c, true, [&] {
-            return sweep2d(c, 0, state(0), lv.buf[1 - cur[0]], 0, fL, 0, word, dir, nullptr, nullptr, snap);
+            return sweep2d(c, 0, state(0), lv.buf[1 - cur[0]], 0, fg, fgs, word, dir, nullptr, nullptr, snap);
           });
           if (st != MGMC_OK) return st;
           cur[0] ^= 1;

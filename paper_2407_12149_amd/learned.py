@@ -130,7 +130,7 @@ def prolong_weights(cfg, params, face):
 
 
 def evaluate(cfg, faces_host, params, nchains=4, nsamples=2000, burn=500, precision="fp64",
-             log=None):
+             log=None, operator=False):
     """IACT and ESS/s of multilinear vs learned P on each field (QoI = mean
     over the central sub-square), both samplers of a field run as branches
     of one batch.  Returns a list of per-field dicts."""
@@ -140,7 +140,10 @@ def evaluate(cfg, faces_host, params, nchains=4, nsamples=2000, burn=500, precis
     for k, face in enumerate(faces_host):
         w = prolong_weights(cfg, params, face) if params is not None else None
         row = {"field": k, "fallback": w is None}
-        for name, pw in (("multilinear", None), ("learned", w)):
+        cands = [("multilinear", None), ("learned", w)]
+        if operator:
+            cands.append(("operator", operator_weights(cfg, face)))
+        for name, pw in cands:
             s = mgmc.Sampler(problem(cfg, face, prolong_w=pw, nchains=nchains, seed=k,
                                      precision=precision))
             s.set_graph(True)
@@ -158,9 +161,58 @@ def evaluate(cfg, faces_host, params, nchains=4, nsamples=2000, burn=500, precis
             s.close()
         if log:
             log(f"[learned] field {k}: iact multilinear {row['multilinear']['iact']:.3f} "
-                f"learned {row['learned']['iact']:.3f}")
+                f"learned {row['learned']['iact']:.3f}"
+                + (f" operator {row['operator']['iact']:.3f}" if operator else ""))
         res.append(row)
     return res
+
+
+def operator_weights(cfg, face):
+    """Operator-dependent ("black box", Dendy 1982) weights of the finest
+    transfer in the prolong_w layout, from the 5-point operator
+    s (kappa^2 - div(a grad)) of this field: a fine node between two coarse
+    nodes along x takes -A_(i, toward J) / (A_ii + A_(i,S) + A_(i,N)) (the
+    stencil collapsed across the other axis), likewise along y, and a node at
+    a cell centre -(A_(i,x-edge) P(x-edge node, J) + A_(i,y-edge) P(y-edge
+    node, J)) / A_ii.  For a = 1 and kappa h -> 0 these are the multilinear
+    weights.  A reference transfer that adapts to the coefficient without
+    training: the headroom an operator-aware P could give."""
+    n = cfg["n"]
+    nc = (n - 1) // 2
+    h = 1.0 / (n + 1)
+    s = h * h
+    per = (n + 1) * n
+    ax = face[:per].reshape(n, n + 1)      # [y][x face]
+    ay = face[per:2 * per].reshape(n + 1, n)  # [y face][x]
+    ih2 = 1.0 / (h * h)
+    # stencil of fine node (x, y), 1-based coordinates
+    def W(x, y): return -s * ih2 * ax[y - 1, x - 1]
+    def E(x, y): return -s * ih2 * ax[y - 1, x]
+    def S(x, y): return -s * ih2 * ay[y - 1, x - 1]
+    def N(x, y): return -s * ih2 * ay[y, x - 1]
+    def C(x, y): return s * (cfg["kappa2"] + ih2 * (ax[y - 1, x - 1] + ax[y - 1, x] + ay[y - 1, x - 1] + ay[y, x - 1]))
+    J1, J2 = np.meshgrid(np.arange(1, nc + 1), np.arange(1, nc + 1), indexing="xy")
+    J1, J2 = J1.reshape(-1), J2.reshape(-1)
+    w = np.zeros((nc * nc, 9))
+    edge = {}
+    for dx in (-1, 1):  # x-edge nodes 2J + (dx, 0)
+        x, y = 2 * J1 + dx, 2 * J2
+        toward = W(x, y) if dx == 1 else E(x, y)
+        edge[(dx, 0)] = -toward / (C(x, y) + S(x, y) + N(x, y))
+    for dy in (-1, 1):  # y-edge nodes 2J + (0, dy)
+        x, y = 2 * J1, 2 * J2 + dy
+        toward = S(x, y) if dy == 1 else N(x, y)
+        edge[(0, dy)] = -toward / (C(x, y) + W(x, y) + E(x, y))
+    for (dx, dy), v in edge.items():
+        w[:, (dx + 1) + 3 * (dy + 1)] = v
+    w[:, 4] = 1.0
+    for dx in (-1, 1):
+        for dy in (-1, 1):
+            x, y = 2 * J1 + dx, 2 * J2 + dy
+            ax_e = W(x, y) if dx == 1 else E(x, y)  # coupling to the y-edge node 2J + (0, dy)
+            ay_e = S(x, y) if dy == 1 else N(x, y)  # coupling to the x-edge node 2J + (dx, 0)
+            w[:, (dx + 1) + 3 * (dy + 1)] = -(ax_e * edge[(0, dy)] + ay_e * edge[(dx, 0)]) / C(x, y)
+    return w.reshape(-1)
 
 
 def save_params(path, params, meta=None):

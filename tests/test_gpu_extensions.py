@@ -176,6 +176,11 @@ def test_gibbs_sampler_3d_and_fp32():
     run_case(2, 127, 1, 100.0, beta=5, sampler="gibbs", precision="fp32")
 
 
+@pytest.mark.parametrize("tiled", [True, False])
+def test_gibbs_sampler_fem(tiled):
+    run_case(2, 127, 1, 100.0, beta=5, op="fem", sampler="gibbs", tiled=tiled)
+
+
 def test_gibbs_sampler_ssl13():
     run_case(2, 31, 1, 100.0, op="ssl13", sampler="gibbs")
 

@@ -49,3 +49,20 @@ def test_patch_sensors_3d_are_volume_means():
         assert len(set(sites.tolist())) == 27
         for c in (x, y, z):
             assert c.max() - c.min() == 2 and c.min() >= 0 and c.max() <= n - 1
+
+
+def test_operator_weights_reduce_to_multilinear():
+    """The operator-dependent transfer of learned.operator_weights equals
+    multilinear interpolation for a = 1 and kappa = 0 (the collapsed 5-point
+    stencil of -Laplace gives 1/2 on edges and 1/4 at cell centres), and
+    stays a convex-like weighting for a rough log-normal field."""
+    from paper_2407_12149_amd import learned
+    n = 31
+    cfg = dict(n=n, kappa2=0.0)
+    face = workloads.face_array(n, 2, lambda x, y: 0.0 * x)
+    w = learned.operator_weights(cfg, face).reshape(-1, 9)
+    ml = np.array([0.25, 0.5, 0.25, 0.5, 1.0, 0.5, 0.25, 0.5, 0.25])
+    assert np.abs(w - ml).max() <= 1e-15
+    rough = workloads.lognormal_faces_fft(n, 2, 0.05, 2.0, seed=3)
+    w = learned.operator_weights(dict(n=n, kappa2=1.0), rough).reshape(-1, 9)
+    assert np.all(w > 0) and np.all(w <= 1.0 + 1e-12)
