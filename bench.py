@@ -337,6 +337,9 @@ def main():
                     help="posterior1023 (2D, FP64 with paired FP32; default), posterior255 "
                          "(3D posterior at scale, 64 chains, FP32 with paired FP64; host set-up "
                          "takes about a minute per precision), batched512")
+    ap.add_argument("--march3d", type=int, default=None,
+                    help="3D workloads: 1 one-launch z-marching finest sweep, 0 parity passes "
+                         "(default: the autotuner's choice)")
     ap.add_argument("--table1-grids", type=int, nargs="+", default=[127, 255, 511])
     ap.add_argument("--table1-samples", type=int, default=4000)
     ap.add_argument("--tune-cache", default=None,
@@ -393,6 +396,8 @@ def main():
         s = mgmc.Sampler(prob, obs=cfg["obs"])
         setup_s = time.perf_counter() - t0
         tuned = None
+        if dim == 3 and args.march3d is not None:
+            s.set_option(mgmc.MGMC_OPT_MARCH3D, args.march3d)
         if args.tune:
             s.posterior_sample(y, 0, 2, want_qoi=False)  # right-hand side for the update timer
             tuned = autotune.autotune(s, cache_path=args.tune_cache)

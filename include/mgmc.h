@@ -216,13 +216,18 @@ mgmc_status mgmc_set_graph(mgmc_ctx* ctx, int32_t enabled);
  *     the sweep kernel also copies its values at the observation sites, so
  *     that B^T theta, the noise xi and the product take one launch; 2 uses the
  *     matrix cores with a separate launch for B^T theta and xi; 0 uses
- *     vector FMA, 8 chains per pass over G.  Results agree to rounding. */
+ *     vector FMA, 8 chains per pass over G.  Results agree to rounding.
+ *   MGMC_OPT_MARCH3D: 1 runs each sweep of a 3D 7-point finest level as one
+ *     launch (both parity passes, marching in z over LDS x-y tiles of 64 x 24
+ *     sites, out of place), 2 the same with tiles of 64 x 8 sites; 0
+ *     (default) as two parity-pass launches.  Results agree to rounding. */
 enum {
   MGMC_OPT_TILED_SWEEPS = 1,
   MGMC_OPT_SWEEP_VARIANT = 2,
   MGMC_OPT_CHAINS_PER_BLOCK = 3,
   MGMC_OPT_COARSE_FUSED = 4,
-  MGMC_OPT_LOWRANK_MFMA = 5
+  MGMC_OPT_LOWRANK_MFMA = 5,
+  MGMC_OPT_MARCH3D = 6
 };
 mgmc_status mgmc_set_option(mgmc_ctx* ctx, int32_t option, int64_t value);
 

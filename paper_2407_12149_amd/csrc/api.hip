@@ -97,6 +97,7 @@ struct mgmc_ctx {
   // update forms beyond the tuned V-cycle: W-cycles, SOR relaxation, Alg. 5
   // on level 0 or 5 x 5 stencils run the per-colour kernels level by level
   bool generic = false;
+  bool march3d = false;  // one-launch z-marching sweep on the 3D finest level
   int sampler = MGMC_SAMPLER_MGMC, gamma = 1, nu0 = 0;
   // banded single-level exact sampler
   double* Uband = nullptr;
@@ -653,6 +654,12 @@ mgmc_status enqueue_cycle(mgmc_ctx* c, const void* fL, const double* F, double* 
             MGMC_LAUNCH(mgmc::launch_lowrank_fused(L, lv, state(l), 0, word, beta, c->gisq, c->gam, v_out));
             continue;
           }
+        } else if (c->march3d && l == top && lv.cross) {
+          mgmc_status st = timed(c, true, [&] {
+            return mgmc::launch_sweep3d_march(L, lv, state(l), lv.buf[1 - cur[l]], f, word, 0);
+          });
+          if (st != MGMC_OK) return st;
+          cur[l] ^= 1;
         } else {
           mgmc_status st = in_place_sweep(l, f, fcs, word, false);
           if (st != MGMC_OK) return st;
@@ -711,8 +718,16 @@ mgmc_status enqueue_cycle(mgmc_ctx* c, const void* fL, const double* F, double* 
           }
         } else {
           if (j == 0) MGMC_LAUNCH(mgmc::launch_prolong(L, lv, state(l), c->lv[l - 1], psi));
-          mgmc_status st = in_place_sweep(l, f, fcs, word, true);
-          if (st != MGMC_OK) return st;
+          if (c->march3d && l == top && lv.cross && !last_in_place) {
+            mgmc_status st = timed(c, true, [&] {
+              return mgmc::launch_sweep3d_march(L, lv, state(l), lv.buf[1 - cur[l]], f, word, 1);
+            });
+            if (st != MGMC_OK) return st;
+            cur[l] ^= 1;
+          } else {
+            mgmc_status st = in_place_sweep(l, f, fcs, word, true);
+            if (st != MGMC_OK) return st;
+          }
         }
         if (beta)
           MGMC_LAUNCH(mgmc::launch_lowrank(L, lv, state(l), 1, word, beta, c->gisq, c->gam, c->t, nullptr));
@@ -1100,6 +1115,11 @@ mgmc_status mgmc_set_option(mgmc_ctx* c, int32_t option, int64_t value) {
     case MGMC_OPT_LOWRANK_MFMA:
       if (value < 0 || value > 2) return fail(MGMC_EINVAL, "MGMC_OPT_LOWRANK_MFMA takes 0, 1 or 2");
       c->L.lowrank_mfma = int(value);
+      return MGMC_OK;
+    case MGMC_OPT_MARCH3D:
+      if (value < 0 || value > 2) return fail(MGMC_EINVAL, "MGMC_OPT_MARCH3D takes 0, 1 or 2");
+      c->march3d = value != 0 && c->prob.dim == 3;
+      c->L.march3d = c->march3d ? int(value) : 0;
       return MGMC_OK;
     default:
       return fail(MGMC_EINVAL, "unknown option");

@@ -15,6 +15,7 @@
 //    banded Cholesky factor At = U^T U (lexicographic order), by blocked back
 //    substitution in one workgroup per group of chains.
 #include <algorithm>
+#include <type_traits>
 
 #include "device_common.h"
 #include "device_rng.h"
@@ -304,6 +305,233 @@ hipError_t launch_band_sample(const Launch& L, const DevLevel& lv, const double*
     else
       k_band_finish<double, 3><<<gf, kBlock, 0, L.stream>>>(x, mu, N, lv.g, (double*)theta);
   }
+  return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------------------
+// One-launch 3D sweep on the 7-point finest level, marching in z.
+//
+// A random Gauss-Seidel sweep on a 7-point level is two parity passes (sites
+// of one parity sum never couple).  A block owns a TX x TY column of the x-y
+// plane over a chunk of planes [za, zb) and marches up through it: at step s
+// it runs the first pass at plane s and the second pass at plane s - 1, which
+// is the order of the two global passes at every site (the first pass at s
+// reads second-parity values at s - 1 before the second pass changes them;
+// the second pass at s - 1 reads the first pass's results at s - 2, s - 1 and
+// s).  Plane s is staged in LDS for the in-plane neighbours, with a halo of
+// two sites in x and y: the first pass also updates the ring of one site
+// around the tile (recomputed identically by neighbouring blocks, the noise
+// being counter-based), so the second pass on the tile sees final values;
+// the chunk likewise starts one plane early.  Each thread owns a segment of
+// four sites in x (two Philox pairs, one per x parity, exactly the pairs of
+// the parity-pass kernel) and keeps the values of planes s-2 .. s+1 of its
+// segment, for a group of chains, in registers, so z neighbours never go
+// through memory twice.  Out of place: reads theta_in, writes the tile's
+// final planes to theta_out.
+constexpr int kMTX = 64, kMSX = kMTX / 4 + 2;
+constexpr int kMLS = kMTX + 8 + 1;  // LDS row stride (padded)
+
+// Tile height TY: 24 rows with 512 threads (one block per compute unit) or
+// 8 rows with 256 threads (two blocks per compute unit hide each other's
+// plane loads, at a larger halo share).
+template <typename T, int CPB, int kMTY, int kMNT>
+__global__ __launch_bounds__(kMNT) void k_sweep3d_march(
+    const T* __restrict__ coef, const T* __restrict__ invd, const T* __restrict__ theta_in,
+    T* __restrict__ theta_out, const T* __restrict__ f, Geom g, int first_parity, uint32_t word,
+    const int64_t* __restrict__ mcur, uint32_t seed, uint32_t chain0, int tiles_x, int tiles_y,
+    int zchunk, int nchains) {
+  constexpr int kMSY = kMTY + 4;
+  static_assert(kMSX * kMSY <= kMNT, "segment owners exceed the block");
+  __shared__ T lds[2][CPB][kMSY][kMLS];
+  const int n = g.n;
+  const int tid = threadIdx.x;
+  const bool active = tid < kMSX * kMSY;
+  const int sx = tid % kMSX, sy = tid / kMSX;
+  const int tile = blockIdx.x % (tiles_x * tiles_y), bz = blockIdx.x / (tiles_x * tiles_y);
+  const int x0 = 1 + kMTX * (tile % tiles_x), y0 = 1 + kMTY * (tile / tiles_x);
+  const int xs = x0 - 4 + 4 * sx;       // first site of the segment (1 mod 4)
+  const int y = y0 - 2 + (active ? sy : 0);
+  const int q = (xs - 1) >> 2;          // segment index
+  const int za = 1 + zchunk * bz, zb = min(n + 1, za + zchunk);
+  const int c0 = int(blockIdx.y) * CPB;
+  const int nc = min(CPB, nchains - c0);
+  const uint32_t m = uint32_t(*mcur);
+  const int64_t plane = int64_t(g.px) * g.py;
+  const bool row_ring = active && y >= y0 - 1 && y <= y0 + kMTY && y >= 1 && y <= n;
+  const bool row_tile = active && y >= y0 && y < y0 + kMTY && y <= n;
+  // global index of site j of the segment in plane z (padding for positions
+  // outside the field: it reads zero and is never written)
+  auto gidx = [&](int j, int yy, int z) -> int64_t {
+    const int x = xs + j;
+    const bool ok = active && x >= 0 && x <= n + 1 && yy >= 0 && yy <= n + 1 && z >= 0 && z <= n + 1;
+    return ok ? pidx(g, x, yy, z) : 0;
+  };
+  auto in_ring = [&](int j) { const int x = xs + j; return row_ring && x >= x0 - 1 && x <= x0 + kMTX && x >= 1 && x <= n; };
+  auto in_tile = [&](int j) { const int x = xs + j; return row_tile && x >= x0 && x < x0 + kMTX && x <= n; };
+  // per chain, the segment's values in planes s-2 .. s+1 (slot p & 3); every
+  // slot index below is a compile-time constant, so the arrays stay in registers
+  T v[CPB][4][4];
+  // operator of the segment in two planes (slot p & 1): -x entries of sites
+  // 0..4, -y and +y, -z and +z entries, inverse diagonal, right-hand side
+  T cw[2][5], cs[2][4], cn[2][4], cb[2][4], ct[2][4], ci[2][4], cf[2][4];
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  using I3 = std::integral_constant<int, 3>;
+  auto load_plane = [&](auto slot_c, int z) {
+    constexpr int slot = decltype(slot_c)::value;
+#pragma unroll
+    for (int c = 0; c < CPB; ++c) {
+      const T* th = theta_in + int64_t(min(c0 + c, nchains - 1)) * g.Np;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[c][slot][j] = th[gidx(j, y, z)];
+    }
+  };
+  auto load_coef = [&](auto set_c, int z) {
+    constexpr int k = decltype(set_c)::value;
+    const bool zin = z >= 1 && z <= n;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      const int x = xs + j;
+      const bool ok = active && zin && x >= 0 && x <= n + 1 && y >= 0 && y <= n + 1;
+      cw[k][j] = coef[int64_t(12) * g.Np + (ok ? pidx(g, x, y, z) : 0)];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t i = zin ? gidx(j, y, z) : 0;
+      cs[k][j] = coef[int64_t(10) * g.Np + i];
+      cn[k][j] = coef[int64_t(10) * g.Np + (zin ? gidx(j, y + 1, z) : 0)];
+      cb[k][j] = coef[int64_t(4) * g.Np + i];
+      ct[k][j] = coef[int64_t(4) * g.Np + (i != 0 ? i + plane : 0)];
+      ci[k][j] = invd[i];
+      cf[k][j] = f ? f[i] : T(0);
+    }
+  };
+  // one pass at plane z over the segment's sites of this pass's x parity
+  // (one Philox pair): CUR, LO, HI are the value slots of planes z, z - 1,
+  // z + 1, K the operator slot of plane z; the first pass (TILE false) covers
+  // the tile and its one-site ring and records its results in LDS buffer K
+  // for the second pass; the second (TILE true) covers the tile.
+  auto pass = [&](auto cur_c, auto lo_c, auto hi_c, auto k_c, auto tile_c, int z, int parity) {
+    constexpr int CUR = decltype(cur_c)::value, LO = decltype(lo_c)::value;
+    constexpr int HI = decltype(hi_c)::value, K = decltype(k_c)::value;
+    constexpr bool TILE = decltype(tile_c)::value;
+    const int xp = (parity + y + z) & 1;  // x parity of this pass's sites
+    const int j0 = xp ? 0 : 1;            // sites j0 and j0 + 2 (one Philox pair)
+    const bool in0 = TILE ? in_tile(j0) : in_ring(j0);
+    const bool in1 = TILE ? in_tile(j0 + 2) : in_ring(j0 + 2);
+    if (!in0 && !in1) return;
+    const int m1 = xp ? (n + 1) / 2 : (n - 1) / 2;
+    const int qx = (m1 + 1) / 2;
+    const int m2 = (y & 1) ? (n + 1) / 2 : (n - 1) / 2;
+    const uint32_t pair = uint32_t(q) + uint32_t(qx) * (uint32_t((y - 1) >> 1) + uint32_t(m2) * uint32_t((z - 1) >> 1));
+    const int colour = xp | ((y & 1) << 1) | ((z & 1) << 2);
+    const int col0 = 4 * sx;
+#pragma unroll
+    for (int c = 0; c < CPB; ++c) {
+      if (c >= nc) break;
+      const Block4 blk = philox10(pair, word | uint32_t(colour), m, 0u, seed, chain0 + c0 + c);
+      T zz[2];
+      Gauss<T>::pair(blk, zz[0], zz[1]);
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        // site jj belongs to this pass when jj has the pass's x parity
+        if (((jj & 1) == 0) != (xp == 1)) continue;
+        const bool inj = (jj >> 1) ? in1 : in0;
+        if (!inj) continue;
+        const int col = col0 + jj;
+        const T xm = jj == 0 ? lds[K][c][sy][col - 1] : v[c][CUR][jj == 0 ? 0 : jj - 1];
+        const T xq = jj == 3 ? lds[K][c][sy][col + 1] : v[c][CUR][jj == 3 ? 3 : jj + 1];
+        T sum = cf[K][jj];
+        sum -= cb[K][jj] * v[c][LO][jj];
+        sum -= cs[K][jj] * lds[K][c][sy - 1][col];
+        sum -= cw[K][jj] * xm;
+        sum -= cw[K][jj + 1] * xq;
+        sum -= cn[K][jj] * lds[K][c][sy + 1][col];
+        sum -= ct[K][jj] * v[c][HI][jj];
+        const T ivd = ci[K][jj];
+        const T nv = sum * ivd + zz[jj >> 1] * sqrt(ivd);
+        v[c][CUR][jj] = nv;
+        if (!TILE) lds[K][c][sy][col] = nv;
+      }
+    }
+  };
+  const int sA = za - 1, sE = zb;  // steps s: first pass at s, second at s - 1
+  // sA is a multiple of 4 (zchunk is): step sA has phase 0
+  load_plane(I3{}, sA - 1);
+  load_plane(I0{}, sA);
+  load_coef(I0{}, sA);
+  auto step = [&](auto phase_c, int s) {
+    constexpr int ph = decltype(phase_c)::value;
+    using PLO2 = std::integral_constant<int, (ph + 2) & 3>;
+    using PLO = std::integral_constant<int, (ph + 3) & 3>;
+    using PCUR = std::integral_constant<int, ph>;
+    using PHI = std::integral_constant<int, (ph + 1) & 3>;
+    using KCUR = std::integral_constant<int, ph & 1>;
+    using KPREV = std::integral_constant<int, (ph + 1) & 1>;
+    load_plane(PHI{}, s + 1);
+    // plane s into LDS (its values so far) for the in-plane neighbours
+    if (active) {
+#pragma unroll
+      for (int c = 0; c < CPB; ++c) {
+        if (c >= nc) break;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) lds[KCUR::value][c][sy][4 * sx + j] = v[c][ph][j];
+      }
+    }
+    __syncthreads();
+    if (s >= 1 && s <= n)
+      pass(PCUR{}, PLO{}, PHI{}, KCUR{}, std::false_type{}, s, first_parity);
+    __syncthreads();
+    const int z = s - 1;
+    if (z >= za && z < zb && z >= 1 && z <= n) {
+      pass(PLO{}, PLO2{}, PCUR{}, KPREV{}, std::true_type{}, z, 1 - first_parity);
+#pragma unroll
+      for (int c = 0; c < CPB; ++c) {
+        if (c >= nc) break;
+        T* out = theta_out + int64_t(c0 + c) * g.Np;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (in_tile(j)) out[pidx(g, xs + j, y, z)] = v[c][PLO::value][j];
+      }
+    }
+    __syncthreads();
+    load_coef(KPREV{}, s + 1);  // plane s + 1 takes the operator slot of plane s - 1
+  };
+  for (int s0 = sA; s0 <= sE; s0 += 4) {
+    step(I0{}, s0);
+    if (s0 + 1 <= sE) step(I1{}, s0 + 1);
+    if (s0 + 2 <= sE) step(I2{}, s0 + 2);
+    if (s0 + 3 <= sE) step(I3{}, s0 + 3);
+  }
+}
+
+hipError_t launch_sweep3d_march(const Launch& L, const DevLevel& lv, const void* theta_in,
+                                void* theta_out, const void* f, uint32_t word, int backward) {
+  if (L.mcur == nullptr || L.dim != 3 || !lv.cross || theta_in == theta_out) return hipErrorInvalidValue;
+  const int n = lv.g.n;
+  const bool small = L.march3d == 2;
+  const int TY = small ? 8 : 24;
+  const int tiles_x = (n + kMTX - 1) / kMTX, tiles_y = (n + TY - 1) / TY;
+  const int cpb = L.fp32 ? 4 : 1;
+  const int groups = (L.nchains + cpb - 1) / cpb;
+  // z chunks (a multiple of 4 planes) so that the grid has >= ~1024 blocks
+  int zchunk = ((n + 3) / 4) * 4;
+  while (zchunk > 16 && int64_t(tiles_x) * tiles_y * groups * ((n + zchunk - 1) / zchunk) < 1024) zchunk -= 4;
+  const int nzc = (n + zchunk - 1) / zchunk;
+  dim3 grid(unsigned(tiles_x * tiles_y * nzc), unsigned(groups));
+  const int first = backward ? 1 : 0;
+#define MGMC_MARCH(T, CPB, TYV, NTV)                                                              \
+  k_sweep3d_march<T, CPB, TYV, NTV><<<grid, NTV, 0, L.stream>>>(                                  \
+      (const T*)lv.coef, (const T*)lv.invd, (const T*)theta_in, (T*)theta_out, (const T*)f, lv.g, \
+      first, word, L.mcur, L.seed, L.chain0, tiles_x, tiles_y, zchunk, L.nchains)
+  if (L.fp32) {
+    if (small) MGMC_MARCH(float, 4, 8, 256); else MGMC_MARCH(float, 4, 24, 512);
+  } else {
+    if (small) MGMC_MARCH(double, 1, 8, 256); else MGMC_MARCH(double, 1, 24, 512);
+  }
+#undef MGMC_MARCH
   return hipGetLastError();
 }
 

@@ -151,6 +151,7 @@ struct Launch {
   const double* bm_table = nullptr;  // device: Box-Muller table (device_rng.h), kBmTable doubles
   int cpb_force = 0;  // > 0: chains per thread of the per-site kernels (3D contexts), else by size
   double omega = 1.0;  // SOR relaxation of the per-colour sweeps (others need 1)
+  int march3d = 0;     // z-marching 3D sweep form: 1 tiles of 24 rows, 2 of 8 rows
 };
 
 // Host: fill the Box-Muller table of gauss_pair_tab (device_rng.h).
@@ -204,6 +205,10 @@ hipError_t launch_prolong(const Launch& L, const DevLevel& fine, void* theta,
                           const DevLevel& coarse, const void* psi);
 hipError_t launch_coarsest(const Launch& L, const DevLevel& lv0, const void* f0, int64_t fcs,
                            void* theta0, const double* K, const double* Uinv, uint32_t word = 0);
+// One-launch sweep of a 3D 7-point level (both parity passes), marching in
+// z over LDS x-y tiles, from theta_in into theta_out (distinct buffers).
+hipError_t launch_sweep3d_march(const Launch& L, const DevLevel& lv, const void* theta_in,
+                                void* theta_out, const void* f, uint32_t word, int backward);
 // Levels with 5 x 5 stencils (2D, nine colours (i_1 mod 3) + 3 (i_2 mod 3)):
 // one colour pass in place, and the residual into scratch followed by the
 // restriction P^T r (minus B_{l-1} v).

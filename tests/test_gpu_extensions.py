@@ -38,7 +38,7 @@ def _device():
 
 
 def run_case(dim, n, levels, kappa2, beta=0, gamma_obs=1e-3, variable=False, nchains=3,
-             nsamples=3, precision="fp64", tiled=True, **kw):
+             nsamples=3, precision="fp64", tiled=True, options=None, **kw):
     """Stepwise GPU vs oracle.  kw: op, cycle_gamma, omega, nu0, sampler, nu1, nu2."""
     from paper_2407_12149_amd import mgmc
     from test_gpu_oracle_paths import fp32_bound, posterior_rhs
@@ -69,6 +69,8 @@ def run_case(dim, n, levels, kappa2, beta=0, gamma_obs=1e-3, variable=False, nch
         ref = list(ex.map(one, range(nchains)))
     s = mgmc.Sampler(prob, obs=obs)
     s.set_option(mgmc.MGMC_OPT_TILED_SWEEPS, 1 if tiled else 0)
+    for opt, val in (options or {}).items():
+        s.set_option(opt, val)
     bound = None
     if precision == "fp32":
         f = posterior_rhs(n, dim, obs, y) if obs is not None else None
@@ -198,3 +200,22 @@ def test_cholesky_sampler(case):
 def test_cholesky_sampler_fem_and_ssl():
     run_case(2, 63, 1, 100.0, op="fem", sampler="cholesky", nsamples=2)
     run_case(2, 31, 1, 100.0, op="ssl13", sampler="cholesky", nsamples=2)
+
+
+# ---- one-launch z-marching sweep on the 3D finest level ----
+
+@pytest.mark.parametrize("case", [dict(n=15, levels=3, nchains=3, beta=0),
+                                  dict(n=31, levels=4, nchains=5, beta=6),
+                                  dict(n=63, levels=4, nchains=3, beta=0),
+                                  dict(n=127, levels=5, nchains=1, beta=4)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("form", [1, 2])
+def test_march3d_sweep(case, precision, form):
+    """The finest 3D sweep as one z-marching launch (tiles of 64 x 24 or
+    64 x 8 sites with a two-site halo, chunks of planes, chain groups)
+    against the oracle:
+    FP64 stepwise at 1e-10, FP32 within the derived bound."""
+    from paper_2407_12149_amd import mgmc
+    run_case(3, case["n"], case["levels"], 10.0, beta=case["beta"], gamma_obs=2.5e-5,
+             variable=True, nchains=case["nchains"], nsamples=2, precision=precision,
+             options={mgmc.MGMC_OPT_MARCH3D: form})
