@@ -337,6 +337,9 @@ def main():
                     help="posterior1023 (2D, FP64 with paired FP32; default), posterior255 "
                          "(3D posterior at scale, 64 chains, FP32 with paired FP64; host set-up "
                          "takes about a minute per precision), batched512")
+    ap.add_argument("--primary", choices=["fp64", "fp32"], default=None,
+                    help="precision of the bench value (default: fp64 for posterior1023, fp32 for "
+                         "posterior255); the other runs paired unless --fp32 0")
     ap.add_argument("--march3d", type=int, default=None,
                     help="3D workloads: 1 one-launch z-marching finest sweep, 0 parity passes "
                          "(default: the autotuner's choice)")
@@ -385,6 +388,8 @@ def main():
     # the precision whose throughput is the bench value; the other one runs
     # paired on common random numbers for the mean and variance error
     primary, paired = ("fp32", "fp64") if wl == "posterior255" else ("fp64", "fp32")
+    if args.primary:
+        primary, paired = args.primary, ("fp64" if args.primary == "fp32" else "fp32")
     F = torch.tensor(cfg["F"], device="cuda")
     y = cfg["y"]
 
@@ -416,8 +421,9 @@ def main():
         torch.cuda.synchronize()
         seconds = start.elapsed_time(stop) / 1e3
         qs = q.cpu().numpy()
-        taus = [diagnostics.iact_wolff(qs[:, c])[0] for c in range(nch)]
-        tau_timed = float(np.mean(taus))
+        # (too few timed steps for an estimate in short profiling runs)
+        tau_timed = (float(np.mean([diagnostics.iact_wolff(qs[:, c])[0] for c in range(nch)]))
+                     if args.steps >= 4 else None)
         long_tau = None
         if precision == primary and args.iact_samples > 0:
             log(f"[bench] {precision}: IACT from {args.iact_burn} + {args.iact_samples} untimed updates")
@@ -448,7 +454,9 @@ def main():
     else:
         tau, tau_err, tau_chains = r64["tau_timed"], None, None
         tau_source = f"the {args.steps} timed updates"
-    value = args.steps * nch / (tau * seconds)
+    if tau is None:
+        tau_source = "not estimated: fewer than 4 timed steps and no long run"
+    value = args.steps * nch / (tau * seconds) if tau else None
     achieved = r64["achieved"]
     setup_s = r64["setup_s"]
     extra = {}
@@ -461,7 +469,7 @@ def main():
         # the paired chains track each other to rounding, so they share the
         # long-run IACT of the primary precision
         extra[paired] = {
-            "value": args.steps * nch / (tau * r32["seconds"]),
+            "value": args.steps * nch / (tau * r32["seconds"]) if tau else None,
             "ms_per_step": r32["seconds"] * 1e3 / args.steps, "iact": tau,
             "iact_timed_steps": r32["tau_timed"],
             "sweep_gbs": r32["achieved"], "sweep_frac": r32["achieved"] / PEAK_HBM_GBS,
@@ -501,8 +509,13 @@ def main():
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS,
-                     "traffic": measured_traffic() if wl == "posterior1023" else None,
+                     "traffic": measured_traffic() if (wl, primary) == ("posterior1023", "fp64") else None,
                      "kernel": "finest-level smoother sweep",
+                     "note": (f"the sweep's working set (~{r64['bytes_launch'] * r64['launches_per_sweep'] / 1e6:.0f} MB) "
+                              "fits the 256 MB Infinity Cache, so this is effective bandwidth, not HBM "
+                              "evidence; counter traffic and VALU-busy counters in profiles/"
+                              if wl == "posterior1023" else
+                              "working set of several GB per array: HBM-bound, counters in profiles/"),
                      "launches_per_sweep": r64["launches_per_sweep"],
                      "avg_launch_us": r64["per_launch_s"] * 1e6,
                      "bytes_per_launch": r64["bytes_launch"]},
@@ -515,7 +528,7 @@ def main():
         args.no_cpu_baseline = True
     if args.learned:
         result["learned"] = learned_block(args)
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and tau:
         log("[bench] CPU oracle baseline")
         result["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds, tau)
     print(json.dumps(result), flush=True)
