@@ -184,14 +184,22 @@ struct Gauss<double> {
 // applied as sin/cos of the first part rotated by the small second one.
 // Radius and angle thus carry float rounding relative to the double
 // transform, not the 24-bit truncation of u.
+//
+// The logarithm, reciprocal and square root are the hardware instructions
+// (v_log_f32 as log2 times ln 2, v_rcp_f32, v_sqrt_f32, each within about
+// one ulp) rather than the library's correctly rounded sequences: their
+// arguments here are never denormal or zero (u >= 2^-54, -2 ln u >= 2^-24),
+// which is all those sequences add, and the noise kernels are bound by
+// vector instruction issue.
 template <>
 struct Gauss<float> {
   static __device__ __forceinline__ void pair(const Block4& x, float& z0, float& z1) {
     const float h1 = float(x.x0 >> 8) * 0x1p-24f;
     const float l1 = (float(((x.x0 & 0xffu) << 21) | (x.x1 >> 11)) + 0.5f) * 0x1p-53f;
     const bool big = h1 >= 0x1p-12f;
-    const float lg = logf(big ? h1 : h1 + l1) + (big ? __fdividef(l1, h1) : 0.0f);
-    const float rad = sqrtf(-2.0f * lg);
+    const float lg = __builtin_amdgcn_logf(big ? h1 : h1 + l1) * 0.693147180559945309f +
+                     (big ? l1 * __builtin_amdgcn_rcpf(h1) : 0.0f);
+    const float rad = __builtin_amdgcn_sqrtf(-2.0f * lg);
     const float h2 = float(x.x2 >> 8) * 0x1p-24f;
     const float l2 = (float(((x.x2 & 0xffu) << 21) | (x.x3 >> 11)) + 0.5f) * 0x1p-53f;
     float sn, cs;
