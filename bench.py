@@ -174,9 +174,10 @@ def batched(args):
             log(f"[bench] batched {prec}: tuned {best}")
             samplers.append(s)
         Fs = [torch.tensor(p["F"], device="cuda") for p in cfg["parts"]]
-        # every timed step of all 512 chains in one graph launch (the
-        # capture of the whole sampling loop), warm-up in launches of the same size
-        b = mgmc.Batch(samplers, updates_per_launch=min(args.steps, 100))
+        # ten steps of all 512 chains per graph launch: a graph of more
+        # updates runs slower per kernel on this runtime (40 per launch cost 3 %
+        # more per step, and on posterior1023 100 per launch cost 65 %)
+        b = mgmc.Batch(samplers, updates_per_launch=min(args.steps, 10))
         log(f"[bench] batched {prec}: warmup {args.warmup}")
         b.sample(0, args.warmup)
         torch.cuda.synchronize()

@@ -220,14 +220,20 @@ mgmc_status mgmc_set_graph(mgmc_ctx* ctx, int32_t enabled);
  *   MGMC_OPT_MARCH3D: 1 runs each sweep of a 3D 7-point finest level as one
  *     launch (both parity passes, marching in z over LDS x-y tiles of 64 x 24
  *     sites, out of place), 2 the same with tiles of 64 x 8 sites; 0
- *     (default) as two parity-pass launches.  Results agree to rounding. */
+ *     (default) as two parity-pass launches.  Results agree to rounding.
+ *   MGMC_OPT_RESTRICT3D: 1 (default) forms the residual and its restriction
+ *     on 3D 7-point levels in one launch over LDS tiles (the residual stays
+ *     on chip); 0 writes the residual to memory and restricts it in a second
+ *     launch.  Both sum in the same order.  Values other than 0 and 1:
+ *     EINVAL. */
 enum {
   MGMC_OPT_TILED_SWEEPS = 1,
   MGMC_OPT_SWEEP_VARIANT = 2,
   MGMC_OPT_CHAINS_PER_BLOCK = 3,
   MGMC_OPT_COARSE_FUSED = 4,
   MGMC_OPT_LOWRANK_MFMA = 5,
-  MGMC_OPT_MARCH3D = 6
+  MGMC_OPT_MARCH3D = 6,
+  MGMC_OPT_RESTRICT3D = 7
 };
 mgmc_status mgmc_set_option(mgmc_ctx* ctx, int32_t option, int64_t value);
 

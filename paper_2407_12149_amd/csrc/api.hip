@@ -1121,6 +1121,10 @@ mgmc_status mgmc_set_option(mgmc_ctx* c, int32_t option, int64_t value) {
       c->march3d = value != 0 && c->prob.dim == 3;
       c->L.march3d = c->march3d ? int(value) : 0;
       return MGMC_OK;
+    case MGMC_OPT_RESTRICT3D:
+      if (value < 0 || value > 1) return fail(MGMC_EINVAL, "MGMC_OPT_RESTRICT3D takes 0 or 1");
+      c->L.restrict3d = int(value);
+      return MGMC_OK;
     default:
       return fail(MGMC_EINVAL, "unknown option");
   }

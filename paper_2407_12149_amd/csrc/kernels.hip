@@ -806,6 +806,8 @@ hipError_t launch_restrict_2stage(const Launch& L, const DevLevel& fine, const v
                                   void* scratch, const DevLevel& coarse, const void* f,
                                   int64_t fcs, const LowRankRhs& lr) {
   if (scratch == nullptr || scratch == theta) return hipErrorInvalidValue;
+  if (L.restrict3d && L.dim == 3 && fine.cross && fine.wP == nullptr)
+    return launch_restrict3d_lds(L, fine, theta, coarse, f, fcs, lr);
   const int rcpb = chain_group(blocks_for(fine.N), L.nchains, L.cpb_force);
   // FP32: a group of chains per thread amortises the index arithmetic; FP64
   // moves twice the bytes and runs faster with one chain per thread

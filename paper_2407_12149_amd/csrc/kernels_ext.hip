@@ -535,4 +535,164 @@ hipError_t launch_sweep3d_march(const Launch& L, const DevLevel& lv, const void*
   return hipGetLastError();
 }
 
+namespace {
+
+// Residual and full-weighting restriction of a 3D 7-point level in one
+// launch (Alg. 1 restriction step, f_{l-1} = P^T (f - A theta) - B_{l-1} v),
+// so that the fine residual never goes to memory.  A block owns an 8 x 8 x 4
+// tile of coarse nodes.  Per chain it stages theta on the fine region under
+// the tile plus a ring of one site in LDS (19 x 19 x 11), forms the residual
+// on the 17 x 17 x 9 fine sites that the tile's restriction stencils cover
+// (into LDS), and each of the first 256 threads sums the 27 weighted
+// residuals of its coarse node.  A thread keeps the stencil (and a shared
+// right-hand side) of its residual sites in registers for all chains of the
+// block.  The sums run in the order of the two-stage form (residual over the
+// stencil entries in index order, then the 27 restriction terms in index
+// order), so the two forms round alike.
+constexpr int kR3X = 8, kR3Y = 8, kR3Z = 4;  // coarse nodes per tile
+
+// NT threads per block: 1024 in single precision (fewer residual sites per
+// thread, so more resident wavefronts), 512 in double (a 1024-thread block
+// would spill)
+template <typename T, int kR3NT>
+__global__ __launch_bounds__(kR3NT) void k_restrict3d_lds(
+    const T* __restrict__ coef, const T* __restrict__ theta, const T* __restrict__ f, int64_t fcs,
+    Geom gf, T* __restrict__ fcoarse, Geom gc, LowRankRhs lr, int tiles_x, int tiles_y, int cpb,
+    int nchains) {
+  constexpr int RX = 2 * kR3X + 1, RY = 2 * kR3Y + 1, RZ = 2 * kR3Z + 1;  // residual region
+  constexpr int HX = RX + 2, HY = RY + 2, HZ = RZ + 2;                    // state region
+  constexpr int NR = RX * RY * RZ, NH = HX * HY * HZ;
+  constexpr int KR = (NR + kR3NT - 1) / kR3NT, KH = (NH + kR3NT - 1) / kR3NT;
+  static_assert(kR3X * kR3Y * kR3Z <= kR3NT, "one coarse node per thread");
+  __shared__ T sth[NH];
+  __shared__ T sr[NR];
+  const int n = gf.n, nc = gc.n;
+  const int tid = int(threadIdx.x);
+  const int bx = int(blockIdx.x) % tiles_x, by = (int(blockIdx.x) / tiles_x) % tiles_y,
+            bz = int(blockIdx.x) / (tiles_x * tiles_y);
+  const int J0x = bx * kR3X + 1, J0y = by * kR3Y + 1, J0z = bz * kR3Z + 1;
+  // origin of the state region: fine node 2 J0 - 2 (the residual region
+  // starts one site further, at 2 J0 - 1 >= 1)
+  const int h0x = 2 * J0x - 2, h0y = 2 * J0y - 2, h0z = 2 * J0z - 2;
+  // The thread's residual sites.  Sites past n belong only to coarse nodes
+  // outside the grid: zero stencil, never read.
+  // (field offsets fit 32 bits: the launcher checks Np)
+  T cf[KR][7], fr[KR];
+  int gi[KR];
+#pragma unroll
+  for (int k = 0; k < KR; ++k) {
+    const int s = min(tid + k * kR3NT, NR - 1);
+    const int rx = s % RX, ry = (s / RX) % RY, rz = s / (RX * RY);
+    const int x = h0x + 1 + rx, y = h0y + 1 + ry, z = h0z + 1 + rz;
+    const bool in = x <= n && y <= n && z <= n;
+    gi[k] = in ? int(pidx(gf, x, y, z)) : -1;
+    const int64_t i = in ? int64_t(gi[k]) : pidx(gf, 1, 1, 1);
+    int b = 0;
+#pragma unroll
+    for (int t = 0; t < 27; ++t) {
+      const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+      if ((dx != 0) + (dy != 0) + (dz != 0) > 1) continue;
+      cf[k][b++] = in ? stencil_entry<T, 3>(coef, gf, t, i) : T(0);
+    }
+    fr[k] = (in && f != nullptr && fcs == 0) ? f[i] : T(0);
+  }
+  // offsets of the thread's state-region loads (positions past the last
+  // ghost plane clamped onto it: they feed only residual sites that no
+  // coarse node reads)
+  int ho[KH];
+#pragma unroll
+  for (int k = 0; k < KH; ++k) {
+    const int s = min(tid + k * kR3NT, NH - 1);
+    const int hx = s % HX, hy = (s / HX) % HY, hz = s / (HX * HY);
+    ho[k] = int(pidx(gf, min(h0x + hx, n + 1), min(h0y + hy, n + 1), min(h0z + hz, n + 1)));
+  }
+  // the thread's coarse node (first 256 threads)
+  const int cx = tid % kR3X, cy = (tid / kR3X) % kR3Y, cz = tid / (kR3X * kR3Y);
+  const int Jx = J0x + cx, Jy = J0y + cy, Jz = J0z + cz;
+  const bool jin = tid < kR3X * kR3Y * kR3Z && Jx <= nc && Jy <= nc && Jz <= nc;
+  const int64_t iJ = jin ? pidx(gc, Jx, Jy, Jz) : 0;
+  const int rb = (2 * cx + 1) + RX * ((2 * cy + 1) + RY * (2 * cz + 1));
+  const int cb = int(blockIdx.y) * cpb;
+  const int ce = min(nchains, cb + cpb);
+  // The state region of chain c + 1 is loaded into registers while chain c
+  // forms its residual, and moved into LDS once chain c no longer reads it.
+  T hv[KH];
+  auto load = [&](int c) {
+    const T* th = theta + int64_t(c) * gf.Np;
+#pragma unroll
+    for (int k = 0; k < KH; ++k) hv[k] = th[ho[k]];
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int k = 0; k < KH; ++k)
+      if (tid + k * kR3NT < NH) sth[tid + k * kR3NT] = hv[k];
+  };
+  if (cb < ce) {
+    load(cb);
+    stage();
+  }
+  if (cb + 1 < ce) load(cb + 1);
+  for (int c = cb; c < ce; ++c) {
+    __syncthreads();  // sth holds chain c; the previous chain's restriction has read sr
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      if (tid + k * kR3NT >= NR) continue;
+      T acc = fcs == 0 ? fr[k] : ((gi[k] >= 0 && f != nullptr) ? f[int64_t(c) * fcs + gi[k]] : T(0));
+      const int s = tid + k * kR3NT;
+      const int h = (s % RX + 1) + HX * ((s / RX) % RY + 1 + HY * (s / (RX * RY) + 1));
+      acc -= cf[k][0] * sth[h - HX * HY];  // (0, 0, -1)
+      acc -= cf[k][1] * sth[h - HX];       // (0, -1, 0)
+      acc -= cf[k][2] * sth[h - 1];        // (-1, 0, 0)
+      acc -= cf[k][3] * sth[h];            // centre
+      acc -= cf[k][4] * sth[h + 1];        // (+1, 0, 0)
+      acc -= cf[k][5] * sth[h + HX];       // (0, +1, 0)
+      acc -= cf[k][6] * sth[h + HX * HY];  // (0, 0, +1)
+      sr[tid + k * kR3NT] = acc;
+    }
+    __syncthreads();  // sr holds chain c; no thread reads sth until the next barrier
+    if (c + 1 < ce) stage();
+    if (c + 2 < ce) load(c + 2);
+    if (jin) {
+      T acc = T(0);
+#pragma unroll
+      for (int t1 = 0; t1 < 27; ++t1) {
+        const int ex = t1 % 3 - 1, ey = (t1 / 3) % 3 - 1, ez = t1 / 9 - 1;
+        acc += T(multilinear(ex, ey, ez)) * sr[rb + ex + RX * (ey + RY * ez)];
+      }
+      fcoarse[int64_t(c) * gc.Np + iJ] = T(double(acc) - lowrank_rhs(lr, c, iJ));
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_restrict3d_lds(const Launch& L, const DevLevel& fine, const void* theta,
+                                 const DevLevel& coarse, const void* f, int64_t fcs,
+                                 const LowRankRhs& lr) {
+  if (L.dim != 3 || !fine.cross || fine.wP != nullptr || coarse.g.n != (fine.g.n - 1) / 2 ||
+      fine.g.Np >= (int64_t(1) << 31))
+    return hipErrorInvalidValue;
+  const int nc = coarse.g.n;
+  const int tiles_x = (nc + kR3X - 1) / kR3X, tiles_y = (nc + kR3Y - 1) / kR3Y,
+            tiles_z = (nc + kR3Z - 1) / kR3Z;
+  const int64_t tiles = int64_t(tiles_x) * tiles_y * tiles_z;
+  // chain groups as the per-site kernels choose them, from the tile count
+  int cpb = 1;
+  if (L.cpb_force > 0) {
+    cpb = std::min(std::min(L.cpb_force, 16), L.nchains);
+  } else {
+    while (cpb < 16 && cpb < L.nchains && tiles * ((L.nchains + 2 * cpb - 1) / (2 * cpb)) >= 2048) cpb *= 2;
+  }
+  dim3 grid(unsigned(tiles), unsigned((L.nchains + cpb - 1) / cpb));
+  if (L.fp32)
+    k_restrict3d_lds<float, 1024><<<grid, 1024, 0, L.stream>>>(
+        (const float*)fine.coef, (const float*)theta, (const float*)f, fcs, fine.g,
+        (float*)coarse.f, coarse.g, lr, tiles_x, tiles_y, cpb, L.nchains);
+  else
+    k_restrict3d_lds<double, 512><<<grid, 512, 0, L.stream>>>(
+        (const double*)fine.coef, (const double*)theta, (const double*)f, fcs, fine.g,
+        (double*)coarse.f, coarse.g, lr, tiles_x, tiles_y, cpb, L.nchains);
+  return hipGetLastError();
+}
+
 }  // namespace mgmc

@@ -152,6 +152,7 @@ struct Launch {
   int cpb_force = 0;  // > 0: chains per thread of the per-site kernels (3D contexts), else by size
   double omega = 1.0;  // SOR relaxation of the per-colour sweeps (others need 1)
   int march3d = 0;     // z-marching 3D sweep form: 1 tiles of 24 rows, 2 of 8 rows
+  int restrict3d = 1;  // 3D 7-point levels: residual and restriction in one launch
 };
 
 // Host: fill the Box-Muller table of gauss_pair_tab (device_rng.h).
@@ -201,6 +202,11 @@ hipError_t launch_restrict(const Launch& L, const DevLevel& fine, const void* th
 hipError_t launch_restrict_2stage(const Launch& L, const DevLevel& fine, const void* theta,
                                   void* scratch, const DevLevel& coarse, const void* f,
                                   int64_t fcs, const LowRankRhs& lr);
+// Residual and restriction of a 3D 7-point level (multilinear weights) in one
+// launch over LDS tiles; used by launch_restrict_2stage when L.restrict3d.
+hipError_t launch_restrict3d_lds(const Launch& L, const DevLevel& fine, const void* theta,
+                                 const DevLevel& coarse, const void* f, int64_t fcs,
+                                 const LowRankRhs& lr);
 hipError_t launch_prolong(const Launch& L, const DevLevel& fine, void* theta,
                           const DevLevel& coarse, const void* psi);
 hipError_t launch_coarsest(const Launch& L, const DevLevel& lv0, const void* f0, int64_t fcs,

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libmgmc.so")
 MGMC_OK, MGMC_EINVAL, MGMC_ENOMEM, MGMC_EDEVICE, MGMC_ENOTSPD, MGMC_EUNSUPPORTED, MGMC_ESTATE = range(7)
 MGMC_FP64, MGMC_FP32 = 0, 1
 MGMC_OPT_TILED_SWEEPS, MGMC_OPT_SWEEP_VARIANT, MGMC_OPT_CHAINS_PER_BLOCK = 1, 2, 3
-MGMC_OPT_COARSE_FUSED, MGMC_OPT_LOWRANK_MFMA, MGMC_OPT_MARCH3D = 4, 5, 6
+MGMC_OPT_COARSE_FUSED, MGMC_OPT_LOWRANK_MFMA, MGMC_OPT_MARCH3D, MGMC_OPT_RESTRICT3D = 4, 5, 6, 7
 MGMC_OP_FD, MGMC_OP_FEM_Q1, MGMC_OP_SSL13 = 0, 1, 2
 MGMC_SAMPLER_MGMC, MGMC_SAMPLER_GIBBS, MGMC_SAMPLER_CHOLESKY = 0, 1, 2
 _OPS = {"fd": MGMC_OP_FD, "fem": MGMC_OP_FEM_Q1, "ssl13": MGMC_OP_SSL13}

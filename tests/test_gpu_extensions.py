@@ -219,3 +219,25 @@ def test_march3d_sweep(case, precision, form):
     run_case(3, case["n"], case["levels"], 10.0, beta=case["beta"], gamma_obs=2.5e-5,
              variable=True, nchains=case["nchains"], nsamples=2, precision=precision,
              options={mgmc.MGMC_OPT_MARCH3D: form})
+
+
+# ---- residual and restriction of the 3D finest level in one launch ----
+
+@pytest.mark.parametrize("case", [dict(n=15, levels=3, nchains=3, beta=0, cpb=0),
+                                  dict(n=31, levels=4, nchains=19, beta=6, cpb=4),
+                                  dict(n=63, levels=4, nchains=3, beta=0, cpb=0),
+                                  dict(n=127, levels=5, nchains=1, beta=4, cpb=0)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("form", [0, 1])
+def test_restrict3d_forms(case, precision, form):
+    """Both forms of the 3D 7-point restriction against the oracle: the
+    residual written to memory and restricted by a second launch (0), and
+    residual plus restriction in one launch over 8 x 8 x 4 coarse tiles (1;
+    partial tiles at every size here, and at 31^3 chain groups forced to 4
+    with a ragged last group of 3).  FP64 stepwise at 1e-10, FP32 within the
+    derived bound."""
+    from paper_2407_12149_amd import mgmc
+    run_case(3, case["n"], case["levels"], 10.0, beta=case["beta"], gamma_obs=2.5e-5,
+             variable=True, nchains=case["nchains"], nsamples=2, precision=precision,
+             options={mgmc.MGMC_OPT_RESTRICT3D: form,
+                      mgmc.MGMC_OPT_CHAINS_PER_BLOCK: case["cpb"]})
