@@ -26,6 +26,17 @@ def test_header_declares_the_boundary():
     assert sorted(mgmc.EXPORTED) == syms
 
 
+def test_binding_constants_match_the_header():
+    """Every enumerator of include/mgmc.h has a binding constant of the same
+    name and value (status codes, precisions, operators, samplers, options)."""
+    text = open(os.path.join(ROOT, "include", "mgmc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    enums = dict((k, int(v)) for k, v in re.findall(r"\b(MGMC_[A-Z0-9_]+)\s*=\s*(-?\d+)", text))
+    assert len(enums) >= 20
+    for name, value in enums.items():
+        assert getattr(mgmc, name) == value, name
+
+
 def test_library_exports_every_declared_symbol():
     lib = mgmc.load_library()
     for name in declared_symbols():
