@@ -14,7 +14,8 @@ with r = max_i sum_{j != i} |A_ij| / A_ii (1 for the diagonally dominant
 second-order operators, 2.2 for the 13-point squared Laplacian); its stored
 stencil is rounded likewise, and its normal is formed from the same 53-bit
 uniforms as the FP64 one (device_rng.h; its logarithm, reciprocal and
-square root are the hardware instructions, about one ulp each), so
+square root are the hardware instructions and its sin/cos a short series,
+about one ulp each), so
 |z32 - z64| <= 6 u sqrt(-2 ln u1) <= 3.1e-6 at the largest radius the
 uniforms allow.  A site update thus
 injects at most about (nb + 3) u (r max|theta| + max_i |f_i| / A_ii).  The f
