@@ -16,15 +16,24 @@ static __device__ __forceinline__ int64_t pidx(const Geom& g, int i1, int i2, in
   return g.o0 + int64_t(i1 + 3) + int64_t(g.px) * (int64_t(i2) + int64_t(g.py) * i3);
 }
 
-// (B_{l-1} v)(J) for coarse padded site iJ and chain c (0 without a low-rank term).
-static __device__ __forceinline__ double lowrank_rhs(const LowRankRhs& lr, int c, int64_t iJ) {
-  if (lr.row_of == nullptr) return 0.0;
-  const int r = lr.row_of[iJ];
+// (B_{l-1} v)(J) for chain c at the coarse site whose row of B_{l-1} is r
+// (r < 0: no observation touches the site).
+static __device__ __forceinline__ double lowrank_rhs_row(const LowRankRhs& lr, int c, int r) {
   if (r < 0) return 0.0;
   double s = 0.0;
   for (int64_t e = lr.ptr[r]; e < lr.ptr[r + 1]; ++e)
     s += lr.val[e] * lr.v[int64_t(c) * lr.beta + lr.col[e]];
   return s;
+}
+
+// Row of B_{l-1} at coarse padded site iJ, or -1 (also without a low-rank term).
+static __device__ __forceinline__ int lowrank_row(const LowRankRhs& lr, int64_t iJ) {
+  return lr.row_of == nullptr ? -1 : lr.row_of[iJ];
+}
+
+// (B_{l-1} v)(J) for coarse padded site iJ and chain c (0 without a low-rank term).
+static __device__ __forceinline__ double lowrank_rhs(const LowRankRhs& lr, int c, int64_t iJ) {
+  return lowrank_rhs_row(lr, c, lowrank_row(lr, iJ));
 }
 
 static __device__ __forceinline__ int64_t poff(const Geom& g, int dx, int dy, int dz) {

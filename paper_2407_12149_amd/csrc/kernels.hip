@@ -323,6 +323,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict_residual(const T* __restric
   }
   const int cb = int(blockIdx.y) * cpb;
   const int ce = min(nchains, cb + cpb);
+  const int brow = lowrank_row(lr, iJ);  // the same for every chain
 #pragma unroll 2
   for (int c = cb; c < ce; ++c) {
     const T* rc = r + int64_t(c) * gf.Np;
@@ -333,7 +334,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict_residual(const T* __restric
       const T w = USERP ? wu[t1] : T(multilinear(ex, ey, ez));
       acc += w * rc[i0 + poff(gf, ex, ey, ez)];
     }
-    fcoarse[int64_t(c) * gc.Np + iJ] = T(double(acc) - lowrank_rhs(lr, c, iJ));
+    fcoarse[int64_t(c) * gc.Np + iJ] = T(double(acc) - lowrank_rhs_row(lr, c, brow));
   }
 }
 

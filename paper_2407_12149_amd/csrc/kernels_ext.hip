@@ -611,6 +611,7 @@ __global__ __launch_bounds__(kR3NT) void k_restrict3d_lds(
   const int Jx = J0x + cx, Jy = J0y + cy, Jz = J0z + cz;
   const bool jin = tid < kR3X * kR3Y * kR3Z && Jx <= nc && Jy <= nc && Jz <= nc;
   const int64_t iJ = jin ? pidx(gc, Jx, Jy, Jz) : 0;
+  const int brow = jin ? lowrank_row(lr, iJ) : -1;  // the same for every chain
   const int rb = (2 * cx + 1) + RX * ((2 * cy + 1) + RY * (2 * cz + 1));
   const int cb = int(blockIdx.y) * cpb;
   const int ce = min(nchains, cb + cpb);
@@ -659,7 +660,7 @@ __global__ __launch_bounds__(kR3NT) void k_restrict3d_lds(
         const int ex = t1 % 3 - 1, ey = (t1 / 3) % 3 - 1, ez = t1 / 9 - 1;
         acc += T(multilinear(ex, ey, ez)) * sr[rb + ex + RX * (ey + RY * ez)];
       }
-      fcoarse[int64_t(c) * gc.Np + iJ] = T(double(acc) - lowrank_rhs(lr, c, iJ));
+      fcoarse[int64_t(c) * gc.Np + iJ] = T(double(acc) - lowrank_rhs_row(lr, c, brow));
     }
   }
 }
