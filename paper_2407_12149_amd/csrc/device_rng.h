@@ -66,6 +66,24 @@ __device__ __forceinline__ double log_unit(double u) {
   return fma(double(k), 0.69314718055994530942, 2.0 * s * p);
 }
 
+// Square root of a positive double that is neither tiny (below 2^-767) nor
+// infinite: the hardware reciprocal square root refined by the Newton steps
+// of the general sequence, without its rescaling of tiny arguments and its
+// checks for zero and infinity (the Box-Muller radicand -2 ln u lies in
+// [2^-53, 75]), so the result is the same as sqrt() for such arguments.
+__device__ __forceinline__ double sqrt_normal(double a) {
+  const double y = __builtin_amdgcn_rsq(a);
+  double s = a * y;
+  double h = 0.5 * y;
+  const double r = fma(-h, s, 0.5);
+  s = fma(s, r, s);
+  h = fma(h, r, h);
+  double d = fma(-s, s, a);
+  s = fma(d, h, s);
+  d = fma(-s, s, a);
+  return fma(d, h, s);
+}
+
 // sin and cos of 2 pi u for u in [0, 1).  t = 4u is exact; with q the
 // nearest integer and r = t - q (exact, |r| <= 1/2) the angle is
 // q pi/2 + x, x = r pi/2 in [-pi/4, pi/4], where Taylor series of nine
@@ -139,7 +157,7 @@ __device__ __forceinline__ void gauss_pair_tab(const Block4& x, const double* __
   p = fma(p, r, -0.5);
   p = fma(p, r, 1.0);
   const double lg = fma(double(e), 0.69314718055994530942, fma(r, p, tab[i]));
-  const double rad = sqrt(-2.0 * lg);
+  const double rad = sqrt_normal(-2.0 * lg);
   const double t = u2 * 256.0;
   const double kd = rint(t);
   const int k = int(kd);
@@ -167,7 +185,7 @@ struct Gauss<double> {
     const uint64_t w2 = (uint64_t(x.x2) << 32) | uint64_t(x.x3);
     const double u1 = (double(w1 >> 11) + 0.5) * 0x1p-53;
     const double u2 = (double(w2 >> 11) + 0.5) * 0x1p-53;
-    const double rad = sqrt(-2.0 * log_unit(u1));
+    const double rad = sqrt_normal(-2.0 * log_unit(u1));
     double sn, cs;
     sincos_2pi(u2, sn, cs);
     z0 = rad * cs;
