@@ -30,7 +30,9 @@ if ROOT not in sys.path:
 PEAK_HBM_GBS = 8000.0
 METRIC = "effective samples/s, plain vs learned-prolong MGMC at 1 GPU; sweep HBM GB/s"
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "sweep_seg_posterior1023_fp64_pmc.md")
-SWEEP_SOURCE = os.path.join(ROOT, "paper_2407_12149_amd", "csrc", "kernels_tiled.hip")
+# the finest sweep's source and the device headers it inlines (noise, indexing)
+SWEEP_SOURCES = [os.path.join(ROOT, "paper_2407_12149_amd", "csrc", f)
+                 for f in ("kernels_tiled.hip", "device_rng.h", "device_common.h")]
 
 
 def log(msg):
@@ -94,7 +96,10 @@ def measured_traffic():
     import hashlib
     try:
         text = open(TRAFFIC_PROFILE).read()
-        src = hashlib.sha256(open(SWEEP_SOURCE, "rb").read()).hexdigest()
+        h = hashlib.sha256()
+        for path in SWEEP_SOURCES:
+            h.update(open(path, "rb").read())
+        src = h.hexdigest()
     except OSError:
         return None
     fields = {}
