@@ -540,20 +540,20 @@ namespace {
 // Residual and full-weighting restriction of a 3D 7-point level in one
 // launch (Alg. 1 restriction step, f_{l-1} = P^T (f - A theta) - B_{l-1} v),
 // so that the fine residual never goes to memory.  A block owns an 8 x 8 x 4
-// tile of coarse nodes.  Per chain it stages theta on the fine region under
-// the tile plus a ring of one site in LDS (19 x 19 x 11), forms the residual
-// on the 17 x 17 x 9 fine sites that the tile's restriction stencils cover
-// (into LDS), and each of the first 256 threads sums the 27 weighted
-// residuals of its coarse node.  A thread keeps the stencil (and a shared
+// tile of coarse nodes.  Per chain it forms, into LDS, the residual on the
+// 17 x 17 x 9 fine sites that the tile's restriction stencils cover, from
+// theta staged in LDS on those sites plus a ring of one (19 x 19 x 11), and
+// each of the first 256 threads sums the 27 weighted residuals of its coarse
+// node.  A thread keeps the stencil (and a shared
 // right-hand side) of its residual sites in registers for all chains of the
 // block.  The sums run in the order of the two-stage form (residual over the
 // stencil entries in index order, then the 27 restriction terms in index
 // order), so the two forms round alike.
 constexpr int kR3X = 8, kR3Y = 8, kR3Z = 4;  // coarse nodes per tile
 
-// NT threads per block: 1024 in single precision (fewer residual sites per
-// thread, so more resident wavefronts), 512 in double (a 1024-thread block
-// would spill)
+// kR3NT threads per block: 1024 in single precision (fewer residual sites
+// per thread, so more resident wavefronts), 512 in double (a 1024-thread
+// block would spill)
 template <typename T, int kR3NT>
 __global__ __launch_bounds__(kR3NT) void k_restrict3d_lds(
     const T* __restrict__ coef, const T* __restrict__ theta, const T* __restrict__ f, int64_t fcs,
