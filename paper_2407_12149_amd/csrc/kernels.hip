@@ -1021,11 +1021,19 @@ __global__ __launch_bounds__(kBlock) void k_lowrank_apply_mfma(T* __restrict__ t
                                                                const int32_t* __restrict__ supp,
                                                                const double* __restrict__ GT,
                                                                const double* __restrict__ t,
-                                                               int nchains) {
+                                                               int nchains, int ngroups) {
   extern __shared__ double sT[];  // [beta][16], zero past the last chain
-  const int c0 = blockIdx.y * 16;
+  // The chain groups of one row tile run on one XCD one after another, so
+  // the tile's rows of G come from memory once and from that XCD's L2 for
+  // the other groups: linear block b runs on XCD b % 8, and its place
+  // q = b / 8 in that XCD's sequence selects chain group q % ngroups of row
+  // tile (q / ngroups) * 8 + b % 8.  Row tiles are padded to a multiple of 8.
+  const int b = int(blockIdx.x), q = b / 8;
+  const int rb = (q / ngroups) * 8 + b % 8;
+  if (rb * 64 >= nsupp) return;  // padding tile: the whole block leaves before any barrier
+  const int c0 = (q % ngroups) * 16;
   MfmaRowsPrefetch<T> pf;
-  lowrank_mfma_prefetch<T>(pf, theta, Np, beta, nsupp, supp, GT, c0, nchains, blockIdx.x);
+  lowrank_mfma_prefetch<T>(pf, theta, Np, beta, nsupp, supp, GT, c0, nchains, rb);
   // staged four entries per thread at a time with branch-free loads
   for (int e0 = 0; e0 < beta * 16; e0 += 4 * int(blockDim.x)) {
     double tv[4];
@@ -1042,7 +1050,7 @@ __global__ __launch_bounds__(kBlock) void k_lowrank_apply_mfma(T* __restrict__ t
     }
   }
   __syncthreads();
-  lowrank_mfma_rows<T>(pf, theta, Np, beta, nsupp, supp, GT, sT, c0, nchains, blockIdx.x);
+  lowrank_mfma_rows<T>(pf, theta, Np, beta, nsupp, supp, GT, sT, c0, nchains, rb);
 }
 
 hipError_t launch_lowrank(const Launch& L, const DevLevel& lv, void* theta, int dir, uint32_t word,
@@ -1059,11 +1067,13 @@ hipError_t launch_lowrank(const Launch& L, const DevLevel& lv, void* theta, int 
   if (e != hipSuccess || lv.nsupp[dir] == 0) return e;
   if (L.lowrank_mfma && beta <= 512) {  // LDS: beta x 16 doubles <= 64 KiB
     const size_t mshm = size_t(beta) * 16 * sizeof(double);
-    dim3 mgrid(unsigned((lv.nsupp[dir] + 63) / 64), unsigned((L.nchains + 15) / 16));
+    const int64_t nrt8 = (int64_t(lv.nsupp[dir]) + 64 * 8 - 1) / (64 * 8) * 8;  // row tiles, padded
+    const int ngroups = (L.nchains + 15) / 16;
+    const unsigned mgrid = unsigned(nrt8 * ngroups);
     if (L.fp32)
-      k_lowrank_apply_mfma<float><<<mgrid, kBlock, mshm, L.stream>>>((float*)theta, lv.g.Np, beta, lv.nsupp[dir], lv.supp[dir], lv.GT[dir], t, L.nchains);
+      k_lowrank_apply_mfma<float><<<mgrid, kBlock, mshm, L.stream>>>((float*)theta, lv.g.Np, beta, lv.nsupp[dir], lv.supp[dir], lv.GT[dir], t, L.nchains, ngroups);
     else
-      k_lowrank_apply_mfma<double><<<mgrid, kBlock, mshm, L.stream>>>((double*)theta, lv.g.Np, beta, lv.nsupp[dir], lv.supp[dir], lv.GT[dir], t, L.nchains);
+      k_lowrank_apply_mfma<double><<<mgrid, kBlock, mshm, L.stream>>>((double*)theta, lv.g.Np, beta, lv.nsupp[dir], lv.supp[dir], lv.GT[dir], t, L.nchains, ngroups);
     return hipGetLastError();
   }
   // chain groups of 8 share each G entry; LDS holds t of the group and the
