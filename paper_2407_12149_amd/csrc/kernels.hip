@@ -921,6 +921,7 @@ template <typename T>
 struct MfmaRowsPrefetch {
   double av[16];  // G^T entries of the first 64 columns
   double th[4];   // this lane's theta values at its four result rows
+  int si[4];      // and their sites, kept for the stores
 };
 
 // The loads that do not depend on t: the first column chunk of G and the
@@ -939,7 +940,8 @@ __device__ __forceinline__ void lowrank_mfma_prefetch(MfmaRowsPrefetch<T>& pf,
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int rr = min(r0 + (lane >> 4) + 4 * v, nsupp - 1);
-    pf.th[v] = double(th[supp[rr]]);
+    pf.si[v] = supp[rr];
+    pf.th[v] = double(th[pf.si[v]]);
   }
 }
 
@@ -959,7 +961,7 @@ __device__ __forceinline__ void lowrank_mfma_rows(const MfmaRowsPrefetch<T>& pf,
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int rr = r0 + (lane >> 4) + 4 * v;
-    if (rr < nsupp) th[supp[rr]] = T(pf.th[v] - acc[v]);
+    if (rr < nsupp) th[pf.si[v]] = T(pf.th[v] - acc[v]);
   }
 }
 
