@@ -707,15 +707,6 @@ __global__ void k_advance_m(int64_t* mcur) { *mcur += 1; }
 
 inline unsigned blocks_for(int64_t count) { return unsigned((count + kBlock - 1) / kBlock); }
 
-// Chains per thread for kernels that keep a site's stencil in registers
-// across chains: up to 16, halved while fewer than ~2048 blocks would remain.
-inline int chain_group(int64_t blocks, int nchains, int force = 0) {
-  if (force > 0) return std::min(std::min(force, 16), nchains);
-  int cpb = 1;
-  while (cpb < 16 && cpb < nchains && blocks * ((nchains + 2 * cpb - 1) / (2 * cpb)) >= 2048) cpb *= 2;
-  return cpb;
-}
-
 }  // namespace
 
 #define MGMC_DISPATCH(L, ...)  \

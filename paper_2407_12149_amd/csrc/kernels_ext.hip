@@ -678,12 +678,7 @@ hipError_t launch_restrict3d_lds(const Launch& L, const DevLevel& fine, const vo
             tiles_z = (nc + kR3Z - 1) / kR3Z;
   const int64_t tiles = int64_t(tiles_x) * tiles_y * tiles_z;
   // chain groups as the per-site kernels choose them, from the tile count
-  int cpb = 1;
-  if (L.cpb_force > 0) {
-    cpb = std::min(std::min(L.cpb_force, 16), L.nchains);
-  } else {
-    while (cpb < 16 && cpb < L.nchains && tiles * ((L.nchains + 2 * cpb - 1) / (2 * cpb)) >= 2048) cpb *= 2;
-  }
+  const int cpb = chain_group(tiles, L.nchains, L.cpb_force);
   dim3 grid(unsigned(tiles), unsigned((L.nchains + cpb - 1) / cpb));
   if (L.fp32)
     k_restrict3d_lds<float, 1024><<<grid, 1024, 0, L.stream>>>(

@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 namespace mgmc {
 
 struct Geom {
@@ -154,6 +156,16 @@ struct Launch {
   int march3d = 0;     // z-marching 3D sweep form: 1 tiles of 24 rows, 2 of 8 rows
   int restrict3d = 1;  // 3D 7-point levels: residual and restriction in one launch
 };
+
+// Chains per thread (or block) for kernels that keep a site's stencil in
+// registers across chains: up to 16, doubled while at least ~2048 blocks
+// would remain; force > 0 sets it (capped at 16 and at nchains).
+inline int chain_group(int64_t blocks, int nchains, int force = 0) {
+  if (force > 0) return std::min(std::min(force, 16), nchains);
+  int cpb = 1;
+  while (cpb < 16 && cpb < nchains && blocks * ((nchains + 2 * cpb - 1) / (2 * cpb)) >= 2048) cpb *= 2;
+  return cpb;
+}
 
 // Host: fill the Box-Muller table of gauss_pair_tab (device_rng.h).
 constexpr int kBmTable = 770;
