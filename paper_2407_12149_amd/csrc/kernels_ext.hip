@@ -557,8 +557,8 @@ constexpr int kR3X = 8, kR3Y = 8, kR3Z = 4;  // coarse nodes per tile
 template <typename T, int kR3NT>
 __global__ __launch_bounds__(kR3NT) void k_restrict3d_lds(
     const T* __restrict__ coef, const T* __restrict__ theta, const T* __restrict__ f, int64_t fcs,
-    Geom gf, T* __restrict__ fcoarse, Geom gc, LowRankRhs lr, int tiles_x, int tiles_y, int cpb,
-    int nchains) {
+    Geom gf, T* __restrict__ fcoarse, Geom gc, LowRankRhs lr, int tiles_x, int tiles_y,
+    int tiles_z, int per_xcd, int cpb, int nchains) {
   constexpr int RX = 2 * kR3X + 1, RY = 2 * kR3Y + 1, RZ = 2 * kR3Z + 1;  // residual region
   constexpr int HX = RX + 2, HY = RY + 2, HZ = RZ + 2;                    // state region
   constexpr int NR = RX * RY * RZ, NH = HX * HY * HZ;
@@ -568,8 +568,13 @@ __global__ __launch_bounds__(kR3NT) void k_restrict3d_lds(
   __shared__ T sr[NR];
   const int n = gf.n, nc = gc.n;
   const int tid = int(threadIdx.x);
-  const int bx = int(blockIdx.x) % tiles_x, by = (int(blockIdx.x) / tiles_x) % tiles_y,
-            bz = int(blockIdx.x) / (tiles_x * tiles_y);
+  // Each XCD takes a contiguous range of tiles (x fastest, then y, then z),
+  // so the neighbouring tiles whose state regions overlap run on one XCD and
+  // share its L2: linear block b runs on XCD b % 8 and takes tile
+  // (b % 8) * per_xcd + b / 8 (the tile count padded to 8 * per_xcd).
+  const int tile = (int(blockIdx.x) % 8) * per_xcd + int(blockIdx.x) / 8;
+  if (tile >= tiles_x * tiles_y * tiles_z) return;  // padding: the whole block leaves before any barrier
+  const int bx = tile % tiles_x, by = (tile / tiles_x) % tiles_y, bz = tile / (tiles_x * tiles_y);
   const int J0x = bx * kR3X + 1, J0y = by * kR3Y + 1, J0z = bz * kR3Z + 1;
   // origin of the state region: fine node 2 J0 - 2 (the residual region
   // starts one site further, at 2 J0 - 1 >= 1)
@@ -679,15 +684,16 @@ hipError_t launch_restrict3d_lds(const Launch& L, const DevLevel& fine, const vo
   const int64_t tiles = int64_t(tiles_x) * tiles_y * tiles_z;
   // chain groups as the per-site kernels choose them, from the tile count
   const int cpb = chain_group(tiles, L.nchains, L.cpb_force);
-  dim3 grid(unsigned(tiles), unsigned((L.nchains + cpb - 1) / cpb));
+  const int per_xcd = int((tiles + 7) / 8);
+  dim3 grid(unsigned(8 * per_xcd), unsigned((L.nchains + cpb - 1) / cpb));
   if (L.fp32)
     k_restrict3d_lds<float, 1024><<<grid, 1024, 0, L.stream>>>(
         (const float*)fine.coef, (const float*)theta, (const float*)f, fcs, fine.g,
-        (float*)coarse.f, coarse.g, lr, tiles_x, tiles_y, cpb, L.nchains);
+        (float*)coarse.f, coarse.g, lr, tiles_x, tiles_y, tiles_z, per_xcd, cpb, L.nchains);
   else
     k_restrict3d_lds<double, 512><<<grid, 512, 0, L.stream>>>(
         (const double*)fine.coef, (const double*)theta, (const double*)f, fcs, fine.g,
-        (double*)coarse.f, coarse.g, lr, tiles_x, tiles_y, cpb, L.nchains);
+        (double*)coarse.f, coarse.g, lr, tiles_x, tiles_y, tiles_z, per_xcd, cpb, L.nchains);
   return hipGetLastError();
 }
 
