@@ -283,3 +283,46 @@ def test_long_run_iact_matches_tau_inf():
     err = float(np.sqrt(sum(e[1] ** 2 for e in est)) / 8)
     log(f"[tau] tau_inf {tau_inf:.4f}; GPU {tau:.4f} +- {err:.4f}")
     assert abs(tau - tau_inf) <= 3 * err
+
+
+def test_fp32_moments_against_the_exact_posterior():
+    """Sample mean and variance of the QoI from 4096 FP32 chains against the
+    exact posterior (eqs. post-mean, post-cov, from the oracle's dense
+    operators), as z-tests with IACT-corrected standard errors, and the
+    systematic FP32 error against FP64 chains on the same counters: below
+    1e-3 of the QoI standard deviation (mean) and 1e-3 relative (variance)."""
+    from paper_2407_12149_amd import mgmc
+    n, dim, levels, beta, gamma = 31, 2, 4, 6, 1e-2
+    nch, burn, nsamp = 4096, 100, 2000
+    ptr, idx, val = workloads.patch_sensors(n, dim, beta, seed=5)
+    obs = (ptr, idx, val, np.full(beta, gamma))
+    y = workloads.observed_values(beta, seed=6)
+    prob = dict(dim=dim, n=n, levels=levels, kappa2=10.0, nchains=nch, seed=3)
+    o = oracle_of(prob, obs, y)
+    L = levels - 1
+    A, B, At = o.dense(L, 0), o.dense(L, 2), o.dense(L, 6)
+    mu = np.linalg.solve(A, B) @ np.linalg.solve(np.diag(np.full(beta, gamma)) +
+                                                 B.T @ np.linalg.solve(A, B), y)
+    F = workloads.subcube_qoi(n, dim)
+    qmean, qvar = float(F @ mu), float(F @ np.linalg.solve(At, F))
+    Fd = torch.tensor(F, device="cuda")
+    series = {}
+    for precision in ("fp32", "fp64"):
+        s = mgmc.Sampler(dict(prob, precision=precision), obs=obs)
+        s.posterior_sample(y, 0, burn, want_qoi=False)
+        series[precision] = s.posterior_sample(y, burn, nsamp, F=Fd).cpu().numpy()
+        s.close()
+    q32, q64 = series["fp32"], series["fp64"]
+    tau = float(np.mean([diagnostics.iact_wolff(q32[:, c])[0] for c in range(0, nch, 64)]))
+    ntot = q32.size
+    se_mean = np.sqrt(qvar * tau / ntot)
+    se_var = qvar * np.sqrt(2.0 * tau / ntot)
+    m32, v32 = q32.mean(), q32.var()
+    log(f"[moments] tau {tau:.3f}; mean {m32:.6g} vs {qmean:.6g} (z {(m32 - qmean) / se_mean:+.2f}); "
+        f"var {v32:.6g} vs {qvar:.6g} (z {(v32 - qvar) / se_var:+.2f}); "
+        f"FP32-FP64 mean {abs(m32 - q64.mean()) / np.sqrt(qvar):.2e} sd, "
+        f"var {abs(v32 - q64.var()) / q64.var():.2e} rel")
+    assert abs(m32 - qmean) / se_mean < 4.0
+    assert abs(v32 - qvar) / se_var < 4.0
+    assert abs(m32 - q64.mean()) / np.sqrt(qvar) < 1e-3
+    assert abs(v32 - q64.var()) / q64.var() < 1e-3
