@@ -285,14 +285,15 @@ def test_long_run_iact_matches_tau_inf():
     assert abs(tau - tau_inf) <= 3 * err
 
 
-def test_fp32_moments_against_the_exact_posterior():
+@pytest.mark.parametrize("dim,n,levels", [(2, 31, 4), (3, 15, 3)])
+def test_fp32_moments_against_the_exact_posterior(dim, n, levels):
     """Sample mean and variance of the QoI from 4096 FP32 chains against the
     exact posterior (eqs. post-mean, post-cov, from the oracle's dense
     operators), as z-tests with IACT-corrected standard errors, and the
     systematic FP32 error against FP64 chains on the same counters: below
     1e-3 of the QoI standard deviation (mean) and 1e-3 relative (variance)."""
     from paper_2407_12149_amd import mgmc
-    n, dim, levels, beta, gamma = 31, 2, 4, 6, 1e-2
+    beta, gamma = 6, 1e-2
     nch, burn, nsamp = 4096, 100, 2000
     ptr, idx, val = workloads.patch_sensors(n, dim, beta, seed=5)
     obs = (ptr, idx, val, np.full(beta, gamma))
